@@ -1,0 +1,193 @@
+/*
+ * tdwp.h -- C ABI of the MI355X time-dependent wave-packet library.
+ *
+ * The library propagates triatomic A + BC wave packets with the damped real
+ * Chebyshev recursion of arXiv 2412.10167 (MADWAVE3), Sec. 2.2, Eq. wvp-k:
+ *     u_1 = D H_s u_0,   u_{k+1} = D (2 H_s u_k - D u_{k-1}),
+ *     H_s = (H - E0)/dE,  D = exp(-phi_r(r) - phi_R(R))  (Eq. imaginary-potential),
+ * with H the Jacobi-coordinate Hamiltonian of Sec. 2.1 (Eq. hamiltonian):
+ * sine-DVR radial kinetic terms along r and R, the rotational and centrifugal
+ * terms applied in the Legendre FBR with the Omega-tridiagonal Coriolis
+ * coupling, and the diabatic potential matrix, diagonal on the grid.  Every
+ * step also records the flux line at r* and the analysis line at R_inf and
+ * folds them into energy-resolved amplitudes (Eqs. wvf-chebyshev,
+ * chebyshev-expansion-constants), from which tdwp_state_to_state returns the
+ * total reactive flux per diabatic state (Eq. total-flux) and inelastic
+ * state-to-state probabilities |S|^2 (Eqs. Chebyshev-products-overlaps,
+ * S-matrix-from-chebyshev).
+ *
+ * Conventions common to every call:
+ *  - Atomic units throughout: bohr, hartree, electron masses, hbar = 1.
+ *  - Host arrays are FP64, borrowed for the duration of the call and copied;
+ *    the plan owns every device allocation and frees it in tdwp_destroy.
+ *  - Packet layout (device, and every host array that mirrors it):
+ *      u[omega_index][elec][gamma][R][r], r fastest, one array per packet.
+ *    Omega runs over omega_min..omega_max of its unit, omega_min = 0 when
+ *    parity * (-1)^J = +1, else 1 (Eq. angular-functions, Lambda = 0 states).
+ *    The stored coefficients are DVR-weighted: sqrt(dr dR w_n) Phi(r, R, gamma).
+ *  - Grids (Table tab:parameters, inputgridbase): r_i = r_min + i dr,
+ *    i = 0..n_r-1, dr = (r_max - r_min)/(n_r - 1), Dirichlet walls one step
+ *    outside both ends (the real sine transform of Sec. 2.1, item 2); the same
+ *    for R; gamma on Gauss-Legendre nodes, cos(gamma) ascending.
+ *  - Errors are negative return codes; nothing aborts or throws across the ABI.
+ *    A failed call leaves the plan as it was, except TDWP_EDEVICE (the device
+ *    state is then undefined and the plan should be destroyed).
+ *  - One plan is used by one host thread at a time.  Work is enqueued on the
+ *    stream given in tdwp_config (a hipStream_t), or on a private stream if
+ *    that is NULL; calls that return results to host memory synchronise it.
+ */
+#ifndef TDWP_H
+#define TDWP_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tdwp_plan_s* tdwp_plan_t;
+
+enum tdwp_status {
+  TDWP_OK = 0,
+  TDWP_EINVAL = -1,   /* bad argument or configuration                          */
+  TDWP_ENOMEM = -2,   /* device allocation failed or the plan exceeds limits    */
+  TDWP_EDEVICE = -3,  /* HIP runtime error (no device, launch failure)          */
+  TDWP_ESTATE = -4,   /* call out of order, e.g. propagate before a packet      */
+  TDWP_ERANGE = -5    /* packet norm diverged: spectral bounds too narrow       */
+};
+
+/* Arithmetic of the kinetic and angular contractions (the recursion, damping,
+ * norms and energy accumulation are FP64 in every form). */
+enum tdwp_precision {
+  TDWP_FP64 = 0,
+  TDWP_FP32 = 1,
+  TDWP_BF16X3 = 2,
+  TDWP_FP16X3 = 3
+};
+
+enum tdwp_potential_mode { TDWP_POT_TABLE = 0, TDWP_POT_MLP = 1 };
+
+/* One partial wave (J, p): Jtot, iparity, iommax of the input namelists. */
+typedef struct {
+  int J;
+  int parity;      /* +1 or -1 */
+  int omega_max;   /* 0 <= omega_max <= J */
+  int n_packets;   /* initial states propagated with this Hamiltonian, >= 1 */
+} tdwp_unit;
+
+typedef struct {
+  int n_r, n_R, n_gamma;                 /* npun1, npun2, nangu; each >= 2        */
+  double r_min, r_max, R_min, R_max;     /* first and last grid points, > 0       */
+  double mass_A, mass_B, mass_C;         /* A + BC, electron masses               */
+  int n_elec;                            /* diabatic states, 1..4                 */
+  double rad_cut;                        /* cap on radial kinetic eigenvalues, <= 0: none */
+  double rot_cut;                        /* cap on angular eigenvalues, <= 0: none */
+  double abs_r_start, abs_r_strength; int abs_r_power;   /* absr1, absalp1, n1expo */
+  double abs_R_start, abs_R_strength; int abs_R_power;   /* absr2, absalp2, n2expo */
+  double e_min, e_max;                   /* spectral bounds; both 0: computed      */
+  double r_flux;                         /* r* of the total flux (Eq. total-flux)  */
+  double R_inf;                          /* analysis line, snapped to the nearest R point */
+  int n_energy;                          /* netot >= 2                             */
+  double ecol_min, ecol_max;             /* collision energies above E_v0j0        */
+  int n_units;                           /* partial waves in the batch, >= 1       */
+  const tdwp_unit* units;
+  int precision;                         /* enum tdwp_precision                    */
+  void* stream;                          /* hipStream_t or NULL                    */
+} tdwp_config;
+
+/* Initial collision packet (Sec. 2.3.1, Eqs. initial-collision-wvp and
+ * initial-gaussian; nvref, jref, iomref, ielecref and the inputcol namelist). */
+typedef struct {
+  int unit, slot;          /* which unit, and which of its n_packets           */
+  int v0, j0, omega0, elec0;
+  double E_v0j0;           /* energy of chi_{v0 j0}, zero of collision energy  */
+  double R0, width;        /* Gaussian centre and width Gamma                  */
+  double ecol_mean;        /* mean collision energy, k0 = sqrt(2 mu ecol_mean) */
+  long k_min_elastic;      /* first k in the elastic-channel sum (kminelastic) */
+} tdwp_packet;
+
+/* Final channel of the reactant arrangement (Eq. final-states with beta = A). */
+typedef struct {
+  int elec, v, j, omega;
+  double energy;           /* E_{v' j'} of the channel function                */
+} tdwp_channel;
+
+/* Builds a plan: grids, quadrature, sine-DVR and Legendre tables, angular
+ * blocks, damping, flux rows, index maps and all device buffers.
+ * Errors: EINVAL (inconsistent sizes, omega_max > J, parity not +-1, ...),
+ * ENOMEM, EDEVICE.  On success *out owns everything; free with tdwp_destroy. */
+int tdwp_plan(const tdwp_config* cfg, tdwp_plan_t* out);
+
+/* Copies the plan's grids: r[n_r], R[n_R], cos_gamma[n_gamma] (any may be NULL). */
+int tdwp_grid(tdwp_plan_t p, double* r, double* R, double* cos_gamma, double* gl_weights);
+
+/* Preparatory stage (Sec. 4, pot.out): the n_states lowest eigenpairs of the
+ * diatomic channel Hamiltonian T_r + v_asym(r) + min(j(j+1)/(2 m r^2), rot_cut)
+ * on the plan's r grid, with T_r the plan's (capped) radial kinetic matrix.
+ * chi[n_states][n_r] is DVR-normalised (sum_i chi_i^2 = 1); each vector's
+ * first component above 1e-3 of its largest magnitude is positive.
+ * Errors: EINVAL for n_states outside 1..n_r or j < 0. */
+int tdwp_diatomic_states(tdwp_plan_t p, const double* v_asym, int j, int n_states,
+                         double* energies, double* chi);
+
+/* Installs the diabatic potential matrix, diagonal on the grid (Sec. 2.1,
+ * item 5).  v: packed upper triangle [n_elec (n_elec+1)/2][n_gamma][n_R][n_r]
+ * in the order 11, 12, .., 1n, 22, .., nn; n_values must equal that size.
+ * Any cut (VcutmaxeV) is applied by the caller.  Unless cfg.e_min/e_max were
+ * given, this also fixes E0 and dE from the rigorous bounds: Gershgorin range
+ * of V plus the largest eigenvalue of each kinetic and angular term.
+ * Only TDWP_POT_TABLE is accepted by this entry point.  Resets propagation. */
+int tdwp_set_potential(tdwp_plan_t p, int mode, const double* v, size_t n_values);
+
+/* Returns the (E_min, E_max) in use (after tdwp_set_potential). */
+int tdwp_spectral_bounds(tdwp_plan_t p, double* e_min, double* e_max);
+
+/* Builds u_0 = P^{omega0}[j0][n] g_m chi0_i in block (omega0, elec0) of packet
+ * (unit, slot), unit norm; g(R) = exp(-(R-R0)^2/(2 width^2)) cos(k0 R) made
+ * DVR-weighted and normalised.  chi0[n_r] is normalised by the library.
+ * Resets that packet to k = 0 and records its k = 0 slices.  All packets of a
+ * plan must be set before tdwp_propagate.  Errors: EINVAL, ESTATE (no potential). */
+int tdwp_set_initial_packet(tdwp_plan_t p, const tdwp_packet* pk, const double* chi0);
+
+/* Advances every packet by n_steps Chebyshev steps from its current (u_{k-1},
+ * u_k, k).  norms: NULL, or host [n_packets_total][n_steps] receiving
+ * ||u_{k+1}||^2 .. ||u_{k+n_steps}||^2, packets ordered by (unit, slot).
+ * Chunked calls give the same results as one call.  Errors: ESTATE (packets
+ * missing), ERANGE (a norm exceeded 1e6 or is not finite: E_max too low). */
+int tdwp_propagate(tdwp_plan_t p, long n_steps, double* norms);
+
+/* Current Chebyshev index k of the plan (all packets advance together). */
+int tdwp_step_index(tdwp_plan_t p, long* k);
+
+/* Copies packet (unit, slot) to host: which = 0 gives u_k, 1 gives u_{k-1}.
+ * out has n_omega(unit) * n_elec * n_gamma * n_R * n_r doubles. */
+int tdwp_get_packet(tdwp_plan_t p, int unit, int slot, int which, double* out);
+
+/* Energy analysis of packet (unit, slot) on the collision-energy grid
+ * ecol_min..ecol_max (n_energy points, both ends included):
+ *   p_reac[n_elec][n_energy]: K0 F_Lambda / (mu |g^(K0)|^2), F the flux of
+ *     the energy-resolved packet through r* (Eq. total-flux), g^ the Fourier
+ *     amplitude of the incoming Gaussian (Eq. initial-flux-collisions);
+ *   p_inel[n_ch][n_energy]: |S_f|^2 with S_f = -sqrt(K0 K_f) e^{-i K_f R_inf}
+ *     Phi_f / (mu g^(K0)), Phi_f the energy-resolved projection of the R_inf
+ *     line on chi_f(r) P~_{j' omega'}(gamma) (Eqs. Chebyshev-products-overlaps,
+ *     S-matrix-from-chebyshev); the initial channel sums k >= k_min_elastic.
+ *     Closed channels (E_tot <= energy) give 0.
+ * chi: [n_ch][n_r] DVR-normalised channel functions.  Either output may be NULL. */
+int tdwp_state_to_state(tdwp_plan_t p, int unit, int slot, int n_ch, const tdwp_channel* ch,
+                        const double* chi, double* p_inel, double* p_reac);
+
+/* Per-kernel average device time (microseconds) over n_steps further steps,
+ * each kernel bracketed by HIP events on the plan's stream.  names receives
+ * up to n_max kernel-kind names joined by ';' (buffer of names_len bytes).
+ * Returns the number of kernel kinds (>= 0) or an error.  Advances the plan. */
+int tdwp_time_kernels(tdwp_plan_t p, long n_steps, int n_max, double* avg_us,
+                      char* names, size_t names_len);
+
+void tdwp_destroy(tdwp_plan_t p);
+const char* tdwp_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TDWP_H */

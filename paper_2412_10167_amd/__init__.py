@@ -1,0 +1,7 @@
+"""MI355X-native damped Chebyshev wave-packet propagation (arXiv 2412.10167 hot path).
+
+The compute path is the HIP library libtdwp.so (C ABI in include/tdwp.h);
+`tdwp` is its thin ctypes binding.
+"""
+from .tdwp import (Plan, TdwpError, library_path, load_library,  # noqa: F401
+                   PRECISIONS, EXPORTED_SYMBOLS)

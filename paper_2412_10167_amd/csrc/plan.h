@@ -1,0 +1,111 @@
+// Internal plan object of the tdwp library.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/tdwp.h"
+
+namespace tdwp {
+
+constexpr int kMaxOmega = 16;     // helicity blocks per unit (omega_max <= 15)
+constexpr int kMaxElec = 4;       // diabatic states
+constexpr int kRing = 64;         // Chebyshev slices buffered per energy-accumulation flush
+constexpr int kNormChunk = 4096;  // steps of norms held on the device per host read-back
+
+struct UnitInfo {
+  int J, parity, om_lo, om_hi, n_om, n_packets;
+  // Angular blocks per j: n_omega_j = number of Omega <= j in [om_lo, om_hi];
+  // eigenvectors U (n x n, column a = eigenvector a) and eigenvalues ell of l^2.
+  std::vector<int> ang_off;   // per j: offset into ang_U (ell offset = ang_off/n? see ell_off)
+  std::vector<int> ell_off;   // per j: offset into ang_ell
+  std::vector<int> n_om_j;    // per j
+  std::vector<double> ang_U, ang_ell;
+  double* d_U = nullptr;
+  double* d_ell = nullptr;
+  int* d_ang_off = nullptr;
+  int* d_ell_off = nullptr;
+  int* d_n_om_j = nullptr;
+};
+
+struct PacketInfo {
+  int unit, slot;
+  size_t off;          // offset of this packet in the packet arrays (doubles)
+  size_t n_values;
+  size_t slice_off;    // offset of this packet's slice vector in a ring row
+  int n_sv;            // flux-line values per packet: n_om * n_elec * n_gamma * n_R
+  int n_w;             // analysis-line values: n_om * n_elec * n_gamma * n_r
+  int n_slice;         // 2 * n_sv + n_w
+  size_t acc_off;      // offset of this packet's accumulators [2][n_E][n_slice]
+  size_t snap_off;     // offset of the elastic snapshot [2][n_E][n_w]
+  size_t wg_off;       // offset of this packet's workgroups in the norm partials
+  int n_wg;
+  bool set = false;
+  bool snap_taken = false;
+  tdwp_packet pk{};
+  std::vector<double> g;   // DVR-weighted unit-normalised g_m
+};
+
+}  // namespace tdwp
+
+// The opaque plan handle of the C ABI.
+struct tdwp_plan_s {
+  using UnitInfo = tdwp::UnitInfo;
+  using PacketInfo = tdwp::PacketInfo;
+  tdwp_config cfg{};
+  std::vector<tdwp_unit> units_in;
+  std::vector<UnitInfo> units;
+  std::vector<PacketInfo> packets;
+  int nr = 0, nR = 0, ng = 0, ne = 0, npair = 0;
+  double mu = 0, m = 0, dr = 0, dR = 0, Lr = 0, LR = 0, r_wall = 0, R_wall = 0;
+  std::vector<double> r, R, x, w, Tr, TR, er, eR, Br, BR, D, arow, drow;
+  std::vector<double> Ptab;   // [omega 0..max_om][j 0..ng-1][n], zero rows for j < omega
+  int max_om = 0;
+  int m_inf = 0;
+  double e_min = 0, e_max = 0, E0 = 0, dE = 0;
+  bool bounds_given = false, have_potential = false;
+  size_t n_total = 0;        // doubles per packet buffer (all packets)
+  size_t slice_total = 0;    // doubles per ring row
+  size_t acc_total = 0, snap_total = 0;
+  size_t n_wg_total = 0;     // norm partials per step
+  int rt_ang = 1;            // r-tile of the angular kernel
+  int rt_rad = 1;            // R-rows per workgroup of the radial kernel
+  // propagation state
+  long k = 0;
+  int cur = 0;               // u_k lives in d_u[cur], u_{k-1} in d_u[1 - cur]
+  int ring_count = 0;
+  long ring_k0 = 0;
+  // device
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  double* d_u[2] = {nullptr, nullptr};
+  double* d_h = nullptr;
+  double* d_V = nullptr;
+  double* d_Tr = nullptr;
+  double* d_TR = nullptr;
+  double* d_P = nullptr;
+  double* d_D = nullptr;
+  double* d_Br = nullptr;
+  double* d_BR = nullptr;
+  double* d_arow = nullptr;
+  double* d_drow = nullptr;
+  double* d_ring = nullptr;
+  double* d_acc = nullptr;
+  double* d_snap = nullptr;
+  double* d_coef = nullptr;       // [n_packets][2][n_E][kRing]
+  double* d_normpart = nullptr;   // [kNormChunk][n_wg_total]
+  double* d_norms = nullptr;      // [n_packets][kNormChunk]
+  double* d_chan = nullptr;       // staging for channel functions
+  size_t chan_cap = 0;
+  double* d_out = nullptr;        // staging for analysis outputs
+  size_t out_cap = 0;
+  double* d_g = nullptr;          // [n_packets][n_R]
+  size_t* d_wg_off = nullptr;     // per packet: first norm partial
+  int* d_n_wg = nullptr;          // per packet: number of norm partials
+  std::vector<void*> allocations;
+};
+
+namespace tdwp {
+using Plan = ::tdwp_plan_s;
+}  // namespace tdwp

@@ -1,0 +1,802 @@
+// C ABI of the tdwp library: plan construction, potential and packet set-up,
+// the propagation loop, energy analysis.  See include/tdwp.h for the contract.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "host_tables.h"
+#include "plan.h"
+#include "step_kernels.hpp"
+
+using namespace tdwp;
+
+namespace {
+
+constexpr size_t kLdsBudget = 64 * 1024;
+
+#define HIP_TRY(expr)                                   \
+  do {                                                  \
+    hipError_t e_ = (expr);                             \
+    if (e_ != hipSuccess) return e_ == hipErrorOutOfMemory ? TDWP_ENOMEM : TDWP_EDEVICE; \
+  } while (0)
+
+#define TRY(expr)                 \
+  do {                            \
+    int s_ = (expr);              \
+    if (s_ != TDWP_OK) return s_; \
+  } while (0)
+
+int dev_alloc(Plan* P, void** ptr, size_t bytes) {
+  *ptr = nullptr;
+  if (bytes == 0) bytes = 8;
+  hipError_t e = hipMalloc(ptr, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    *ptr = nullptr;
+    return e == hipErrorOutOfMemory ? TDWP_ENOMEM : TDWP_EDEVICE;
+  }
+  P->allocations.push_back(*ptr);
+  return TDWP_OK;
+}
+
+template <class T>
+int alloc_copy(Plan* P, T** dptr, const std::vector<T>& h) {
+  TRY(dev_alloc(P, (void**)dptr, h.size() * sizeof(T)));
+  if (!h.empty()) HIP_TRY(hipMemcpy(*dptr, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+  return TDWP_OK;
+}
+
+void free_plan(Plan* P) {
+  if (!P) return;
+  if (P->stream) (void)hipStreamSynchronize(P->stream);
+  for (void* a : P->allocations) (void)hipFree(a);
+  if (P->own_stream && P->stream) (void)hipStreamDestroy(P->stream);
+  delete P;
+}
+
+int omega_lo(const tdwp_unit& u) { return (u.parity * ((u.J % 2) ? -1 : 1) == 1) ? 0 : 1; }
+
+int validate(const tdwp_config* c) {
+  if (!c) return TDWP_EINVAL;
+  if (c->n_r < 2 || c->n_R < 2 || c->n_gamma < 2) return TDWP_EINVAL;
+  if (c->n_r > 1024 || c->n_R > 1024 || c->n_gamma > 256) return TDWP_EINVAL;
+  if (!(c->r_min > 0) || !(c->r_max > c->r_min) || !(c->R_min > 0) || !(c->R_max > c->R_min))
+    return TDWP_EINVAL;
+  if (!(c->mass_A > 0) || !(c->mass_B > 0) || !(c->mass_C > 0)) return TDWP_EINVAL;
+  if (c->n_elec < 1 || c->n_elec > kMaxElec) return TDWP_EINVAL;
+  if (c->abs_r_power < 1 || c->abs_R_power < 1) return TDWP_EINVAL;
+  if (c->abs_r_strength < 0 || c->abs_R_strength < 0) return TDWP_EINVAL;
+  if (!(c->r_flux >= c->r_min && c->r_flux <= c->r_max)) return TDWP_EINVAL;
+  if (!(c->R_inf >= c->R_min && c->R_inf <= c->R_max)) return TDWP_EINVAL;
+  if (c->n_energy < 2 || !(c->ecol_min > 0) || !(c->ecol_max > c->ecol_min)) return TDWP_EINVAL;
+  if (c->n_units < 1 || !c->units) return TDWP_EINVAL;
+  if (!(c->e_min == 0 && c->e_max == 0) && !(c->e_max > c->e_min)) return TDWP_EINVAL;
+  if (c->precision != TDWP_FP64) return TDWP_EINVAL;
+  for (int i = 0; i < c->n_units; ++i) {
+    const tdwp_unit& u = c->units[i];
+    if (u.J < 0 || (u.parity != 1 && u.parity != -1)) return TDWP_EINVAL;
+    if (u.omega_max < 0 || u.omega_max > u.J || u.omega_max >= kMaxOmega) return TDWP_EINVAL;
+    if (u.omega_max > c->n_gamma - 1) return TDWP_EINVAL;
+    if (omega_lo(u) > u.omega_max) return TDWP_EINVAL;
+    if (u.n_packets < 1 || u.n_packets > 64) return TDWP_EINVAL;
+  }
+  return TDWP_OK;
+}
+
+double absorb(double x, double start, double strength, int power) {
+  if (x <= start) return 0.0;
+  return strength * std::pow(x - start, power);
+}
+
+int build_tables(Plan* P) {
+  const tdwp_config& c = P->cfg;
+  P->nr = c.n_r;
+  P->nR = c.n_R;
+  P->ng = c.n_gamma;
+  P->ne = c.n_elec;
+  P->npair = P->ne * (P->ne + 1) / 2;
+  const double M = c.mass_A + c.mass_B + c.mass_C;
+  P->mu = c.mass_A * (c.mass_B + c.mass_C) / M;
+  P->m = c.mass_B * c.mass_C / (c.mass_B + c.mass_C);
+  P->dr = (c.r_max - c.r_min) / (P->nr - 1);
+  P->dR = (c.R_max - c.R_min) / (P->nR - 1);
+  P->Lr = (P->nr + 1) * P->dr;
+  P->LR = (P->nR + 1) * P->dR;
+  P->r_wall = c.r_min - P->dr;
+  P->R_wall = c.R_min - P->dR;
+  P->r.resize(P->nr);
+  P->R.resize(P->nR);
+  for (int i = 0; i < P->nr; ++i) P->r[i] = c.r_min + P->dr * i;
+  for (int i = 0; i < P->nR; ++i) P->R[i] = c.R_min + P->dR * i;
+  gauss_legendre(P->ng, P->x, P->w);
+  sine_kinetic(P->nr, P->Lr, P->m, c.rad_cut, P->Tr, P->er);
+  sine_kinetic(P->nR, P->LR, P->mu, c.rad_cut, P->TR, P->eR);
+  P->Br.resize(P->nr);
+  P->BR.resize(P->nR);
+  for (int i = 0; i < P->nr; ++i) P->Br[i] = 1.0 / (2.0 * P->m * P->r[i] * P->r[i]);
+  for (int i = 0; i < P->nR; ++i) P->BR[i] = 1.0 / (2.0 * P->mu * P->R[i] * P->R[i]);
+  // damping D(R, r) = exp(-phi_r(r) - phi_R(R))
+  P->D.resize((size_t)P->nR * P->nr);
+  for (int mm = 0; mm < P->nR; ++mm)
+    for (int i = 0; i < P->nr; ++i)
+      P->D[(size_t)mm * P->nr + i] =
+          std::exp(-absorb(P->r[i], c.abs_r_start, c.abs_r_strength, c.abs_r_power) -
+                   absorb(P->R[mm], c.abs_R_start, c.abs_R_strength, c.abs_R_power));
+  // flux rows from the plain sine basis sqrt(2/L) sin(n pi (r - r_wall)/L)
+  {
+    const double pi = std::acos(-1.0);
+    const int n = P->nr;
+    P->arow.assign(n, 0.0);
+    P->drow.assign(n, 0.0);
+    const double cS = std::sqrt(2.0 / (n + 1)), cB = std::sqrt(2.0 / P->Lr);
+    for (int a = 1; a <= n; ++a) {
+      const double ka = pi * a / P->Lr;
+      const double phi = cB * std::sin(ka * (c.r_flux - P->r_wall));
+      const double dphi = cB * ka * std::cos(ka * (c.r_flux - P->r_wall));
+      for (int i = 1; i <= n; ++i) {
+        long prod = (long)a * i % (2L * (n + 1));
+        const double s = cS * std::sin(pi * (double)prod / (n + 1));
+        P->arow[i - 1] += s * phi;
+        P->drow[i - 1] += s * dphi;
+      }
+    }
+  }
+  P->m_inf = (int)std::floor((c.R_inf - c.R_min) / P->dR + 0.5);
+  // Legendre FBR tables for every Omega in use
+  P->max_om = 0;
+  for (auto& u : P->units_in) P->max_om = std::max(P->max_om, u.omega_max);
+  P->Ptab.assign((size_t)(P->max_om + 1) * P->ng * P->ng, 0.0);
+  for (int om = 0; om <= P->max_om; ++om) {
+    std::vector<double> rows;
+    legendre_fbr_rows(P->ng - 1, om, P->x, P->w, rows);
+    for (int j = om; j < P->ng; ++j)
+      for (int n = 0; n < P->ng; ++n)
+        P->Ptab[((size_t)om * P->ng + j) * P->ng + n] = rows[(size_t)(j - om) * P->ng + n];
+  }
+  // angular blocks per unit and j
+  P->units.clear();
+  for (auto& u : P->units_in) {
+    UnitInfo U;
+    U.J = u.J;
+    U.parity = u.parity;
+    U.om_lo = omega_lo(u);
+    U.om_hi = u.omega_max;
+    U.n_om = U.om_hi - U.om_lo + 1;
+    U.n_packets = u.n_packets;
+    for (int j = 0; j < P->ng; ++j) {
+      const int hi = std::min(U.om_hi, j);
+      const int nj = hi - U.om_lo + 1;
+      U.ang_off.push_back((int)U.ang_U.size());
+      U.ell_off.push_back((int)U.ang_ell.size());
+      U.n_om_j.push_back(std::max(nj, 0));
+      if (nj <= 0) continue;
+      std::vector<double> L, ev, vec;
+      ell2_block(U.J, j, U.om_lo, hi, L);
+      jacobi_eigh(nj, L, ev, vec);
+      U.ang_U.insert(U.ang_U.end(), vec.begin(), vec.end());
+      U.ang_ell.insert(U.ang_ell.end(), ev.begin(), ev.end());
+    }
+    P->units.push_back(U);
+  }
+  return TDWP_OK;
+}
+
+int layout_and_allocate(Plan* P) {
+  const int nr = P->nr, nR = P->nR, ng = P->ng, ne = P->ne;
+  // kernel tiles
+  int max_col = 0;
+  for (auto& U : P->units) max_col = std::max(max_col, U.n_om * ne);
+  P->rt_ang = 0;
+  for (int rt : {64, 32, 16, 8, 4, 2, 1}) {
+    if (rt > nr && rt > 1) continue;
+    if ((size_t)2 * max_col * ng * rt * sizeof(double) <= kLdsBudget) {
+      P->rt_ang = rt;
+      break;
+    }
+  }
+  if (P->rt_ang == 0) return TDWP_ENOMEM;
+  P->rt_rad = 0;
+  for (int rows : {8, 4, 2, 1})
+    if ((size_t)rows * (nr + nR) * sizeof(double) <= kLdsBudget) {
+      P->rt_rad = rows;
+      break;
+    }
+  if (P->rt_rad == 0) return TDWP_ENOMEM;
+  const int n_tiles_R = (nR + P->rt_rad - 1) / P->rt_rad;
+  // packets
+  P->packets.clear();
+  size_t off = 0, soff = 0, aoff = 0, snoff = 0, wgoff = 0;
+  const int nE = P->cfg.n_energy;
+  for (int ui = 0; ui < (int)P->units.size(); ++ui) {
+    const UnitInfo& U = P->units[ui];
+    for (int s = 0; s < U.n_packets; ++s) {
+      PacketInfo pk;
+      pk.unit = ui;
+      pk.slot = s;
+      pk.off = off;
+      pk.n_values = (size_t)U.n_om * ne * ng * nR * nr;
+      pk.n_sv = U.n_om * ne * ng * nR;
+      pk.n_w = U.n_om * ne * ng * nr;
+      pk.n_slice = 2 * pk.n_sv + pk.n_w;
+      pk.slice_off = soff;
+      pk.acc_off = aoff;
+      pk.snap_off = snoff;
+      pk.wg_off = wgoff;
+      pk.n_wg = U.n_om * ne * ng * n_tiles_R;
+      off += pk.n_values;
+      soff += pk.n_slice;
+      aoff += (size_t)2 * nE * pk.n_slice;
+      snoff += (size_t)2 * nE * pk.n_w;
+      wgoff += pk.n_wg;
+      P->packets.push_back(pk);
+    }
+  }
+  P->n_total = off;
+  P->slice_total = soff;
+  P->acc_total = aoff;
+  P->snap_total = snoff;
+  P->n_wg_total = wgoff;
+  // device buffers
+  TRY(dev_alloc(P, (void**)&P->d_u[0], P->n_total * sizeof(double)));
+  TRY(dev_alloc(P, (void**)&P->d_u[1], P->n_total * sizeof(double)));
+  TRY(dev_alloc(P, (void**)&P->d_h, P->n_total * sizeof(double)));
+  TRY(dev_alloc(P, (void**)&P->d_V, (size_t)P->npair * ng * nR * nr * sizeof(double)));
+  TRY(alloc_copy(P, &P->d_Tr, P->Tr));
+  TRY(alloc_copy(P, &P->d_TR, P->TR));
+  TRY(alloc_copy(P, &P->d_P, P->Ptab));
+  TRY(alloc_copy(P, &P->d_D, P->D));
+  TRY(alloc_copy(P, &P->d_Br, P->Br));
+  TRY(alloc_copy(P, &P->d_BR, P->BR));
+  TRY(alloc_copy(P, &P->d_arow, P->arow));
+  TRY(alloc_copy(P, &P->d_drow, P->drow));
+  for (auto& U : P->units) {
+    std::vector<double> Uv = U.ang_U.empty() ? std::vector<double>{0.0} : U.ang_U;
+    std::vector<double> lv = U.ang_ell.empty() ? std::vector<double>{0.0} : U.ang_ell;
+    TRY(alloc_copy(P, &U.d_U, Uv));
+    TRY(alloc_copy(P, &U.d_ell, lv));
+    TRY(alloc_copy(P, &U.d_ang_off, U.ang_off));
+    TRY(alloc_copy(P, &U.d_ell_off, U.ell_off));
+    TRY(alloc_copy(P, &U.d_n_om_j, U.n_om_j));
+  }
+  TRY(dev_alloc(P, (void**)&P->d_ring, (size_t)kRing * P->slice_total * sizeof(double)));
+  TRY(dev_alloc(P, (void**)&P->d_acc, P->acc_total * sizeof(double)));
+  TRY(dev_alloc(P, (void**)&P->d_snap, P->snap_total * sizeof(double)));
+  TRY(dev_alloc(P, (void**)&P->d_coef, P->packets.size() * 2 * nE * kRing * sizeof(double)));
+  TRY(dev_alloc(P, (void**)&P->d_normpart, (size_t)kNormChunk * P->n_wg_total * sizeof(double)));
+  TRY(dev_alloc(P, (void**)&P->d_norms, P->packets.size() * kNormChunk * sizeof(double)));
+  TRY(dev_alloc(P, (void**)&P->d_g, P->packets.size() * nR * sizeof(double)));
+  std::vector<size_t> wg_off;
+  std::vector<int> n_wg;
+  for (auto& pk : P->packets) {
+    wg_off.push_back(pk.wg_off);
+    n_wg.push_back(pk.n_wg);
+  }
+  TRY(alloc_copy(P, &P->d_wg_off, wg_off));
+  TRY(alloc_copy(P, &P->d_n_wg, n_wg));
+  return TDWP_OK;
+}
+
+int ensure_staging(Plan* P, double** buf, size_t* cap, size_t need) {
+  if (*cap >= need) return TDWP_OK;
+  void* p = nullptr;
+  TRY(dev_alloc(P, &p, need * sizeof(double)));
+  *buf = (double*)p;
+  *cap = need;
+  return TDWP_OK;
+}
+
+// ---- propagation -----------------------------------------------------------
+
+struct Timing {
+  hipEvent_t ev[2];
+  double ms[4] = {0, 0, 0, 0};
+  long calls[4] = {0, 0, 0, 0};
+};
+
+int timed_begin(Plan* P, Timing* T) {
+  if (T) HIP_TRY(hipEventRecord(T->ev[0], P->stream));
+  return TDWP_OK;
+}
+
+int timed_end(Plan* P, Timing* T, int kind) {
+  if (!T) return TDWP_OK;
+  HIP_TRY(hipEventRecord(T->ev[1], P->stream));
+  HIP_TRY(hipEventSynchronize(T->ev[1]));
+  float ms = 0.f;
+  HIP_TRY(hipEventElapsedTime(&ms, T->ev[0], T->ev[1]));
+  T->ms[kind] += ms;
+  T->calls[kind] += 1;
+  return TDWP_OK;
+}
+
+int record_slices(Plan* P, int row) {
+  const double* u = P->d_u[P->cur];
+  for (auto& pk : P->packets) {
+    const int nlines = pk.n_sv;
+    const int blocks = (nlines * 64 + 255) / 256;
+    hipLaunchKernelGGL(k_slices, dim3(blocks), dim3(256), 0, P->stream, u + pk.off, nlines, P->nR,
+                       P->nr, P->m_inf, P->d_arow, P->d_drow, 1.0 / std::sqrt(P->dR),
+                       P->d_ring + (size_t)row * P->slice_total + pk.slice_off);
+  }
+  HIP_TRY(hipGetLastError());
+  return TDWP_OK;
+}
+
+int flush_ring(Plan* P) {
+  if (P->ring_count == 0) return TDWP_OK;
+  const tdwp_config& c = P->cfg;
+  const int nE = c.n_energy;
+  const double step = (c.ecol_max - c.ecol_min) / (nE - 1);
+  for (size_t ip = 0; ip < P->packets.size(); ++ip) {
+    auto& pk = P->packets[ip];
+    double* coef = P->d_coef + ip * 2 * nE * kRing;
+    const int nq = nE * P->ring_count;
+    hipLaunchKernelGGL(k_coef, dim3((nq + 255) / 256), dim3(256), 0, P->stream, coef, nE,
+                       c.ecol_min, step, pk.pk.E_v0j0, P->E0, P->dE, P->ring_k0, P->ring_count);
+    const int epb = 8;
+    dim3 grid((pk.n_slice + 255) / 256, (nE + epb - 1) / epb);
+    hipLaunchKernelGGL(k_accumulate, grid, dim3(256), 0, P->stream, P->d_acc + pk.acc_off, coef,
+                       P->d_ring + pk.slice_off, P->slice_total, pk.n_slice, nE, epb,
+                       P->ring_count);
+  }
+  HIP_TRY(hipGetLastError());
+  P->ring_k0 += P->ring_count;
+  P->ring_count = 0;
+  return TDWP_OK;
+}
+
+int take_snapshots(Plan* P) {
+  const int nE = P->cfg.n_energy;
+  for (auto& pk : P->packets) {
+    if (pk.snap_taken || pk.pk.k_min_elastic != P->k) continue;
+    const size_t n = (size_t)2 * nE * pk.n_w;
+    hipLaunchKernelGGL(k_snapshot, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, P->stream,
+                       P->d_snap + pk.snap_off, P->d_acc + pk.acc_off, nE, pk.n_slice,
+                       2 * pk.n_sv, pk.n_w);
+    pk.snap_taken = true;
+  }
+  HIP_TRY(hipGetLastError());
+  return TDWP_OK;
+}
+
+int one_step(Plan* P, int chunk_row, Timing* T) {
+  const int first = (P->k == 0) ? 1 : 0;
+  double* uk = P->d_u[P->cur];
+  double* uo = P->d_u[1 - P->cur];
+  TRY(timed_begin(P, T));
+  for (auto& pk : P->packets) {
+    const UnitInfo& U = P->units[pk.unit];
+    const int ntile = (P->nr + P->rt_ang - 1) / P->rt_ang;
+    const size_t lds = (size_t)2 * U.n_om * P->ne * P->ng * P->rt_ang * sizeof(double);
+    hipLaunchKernelGGL(k_angular_pot, dim3(ntile, P->nR), dim3(256), lds, P->stream, uk + pk.off,
+                       P->d_h + pk.off, U.n_om, U.om_lo, P->ne, P->ng, P->nR, P->nr, P->rt_ang,
+                       P->d_P, U.d_U, U.d_ell, U.d_ang_off, U.d_ell_off, U.d_n_om_j, P->d_Br,
+                       P->d_BR, P->cfg.rot_cut, P->d_V);
+  }
+  HIP_TRY(hipGetLastError());
+  TRY(timed_end(P, T, 0));
+  TRY(timed_begin(P, T));
+  const int n_tiles_R = (P->nR + P->rt_rad - 1) / P->rt_rad;
+  const size_t lds_rad = (size_t)P->rt_rad * (P->nr + P->nR) * sizeof(double);
+  for (auto& pk : P->packets) {
+    const UnitInfo& U = P->units[pk.unit];
+    const int slabs = U.n_om * P->ne * P->ng;
+    hipLaunchKernelGGL(k_radial_epi, dim3(n_tiles_R, slabs), dim3(256), lds_rad, P->stream,
+                       uk + pk.off, uo + pk.off, P->d_h + pk.off, P->d_TR, P->d_Tr, P->d_D,
+                       P->nR, P->nr, P->rt_rad, P->E0, 1.0 / P->dE, first,
+                       P->d_normpart + (size_t)chunk_row * P->n_wg_total + pk.wg_off);
+  }
+  HIP_TRY(hipGetLastError());
+  TRY(timed_end(P, T, 1));
+  P->cur = 1 - P->cur;
+  P->k += 1;
+  // slices of u_k (new k): flush first if the ring is full or an elastic window opens
+  bool opens = false;
+  for (auto& pk : P->packets)
+    if (!pk.snap_taken && pk.pk.k_min_elastic == P->k) opens = true;
+  if (P->ring_count == kRing || opens) {
+    TRY(timed_begin(P, T));
+    TRY(flush_ring(P));
+    TRY(take_snapshots(P));
+    TRY(timed_end(P, T, 3));
+  }
+  TRY(timed_begin(P, T));
+  TRY(record_slices(P, P->ring_count));
+  P->ring_count += 1;
+  TRY(timed_end(P, T, 2));
+  return TDWP_OK;
+}
+
+int run_steps(Plan* P, long n_steps, double* norms_out, Timing* T) {
+  if (!P->have_potential) return TDWP_ESTATE;
+  for (auto& pk : P->packets)
+    if (!pk.set) return TDWP_ESTATE;
+  const int np = (int)P->packets.size();
+  std::vector<double> hn;
+  long done = 0;
+  while (done < n_steps) {
+    const int chunk = (int)std::min<long>(kNormChunk, n_steps - done);
+    for (int s = 0; s < chunk; ++s) TRY(one_step(P, s, T));
+    const int nq = np * chunk;
+    hipLaunchKernelGGL(k_norm_reduce, dim3((nq + 255) / 256), dim3(256), 0, P->stream,
+                       P->d_norms, P->d_normpart, P->n_wg_total, P->d_wg_off, P->d_n_wg,
+                       np, chunk);
+    HIP_TRY(hipGetLastError());
+    hn.resize((size_t)np * kNormChunk);
+    HIP_TRY(hipMemcpyAsync(hn.data(), P->d_norms, hn.size() * sizeof(double),
+                           hipMemcpyDeviceToHost, P->stream));
+    HIP_TRY(hipStreamSynchronize(P->stream));
+    bool bad = false;
+    for (int p = 0; p < np; ++p)
+      for (int s = 0; s < chunk; ++s) {
+        const double v = hn[(size_t)p * kNormChunk + s];
+        if (!std::isfinite(v) || v > 1e6) bad = true;
+        if (norms_out) norms_out[(size_t)p * n_steps + done + s] = v;
+      }
+    done += chunk;
+    if (bad) return TDWP_ERANGE;
+  }
+  return TDWP_OK;
+}
+
+void reset_propagation(Plan* P) {
+  P->k = 0;
+  P->cur = 0;
+  P->ring_count = 0;
+  P->ring_k0 = 0;
+  for (auto& pk : P->packets) {
+    pk.set = false;
+    pk.snap_taken = false;
+  }
+}
+
+}  // namespace
+
+// ---- C ABI -------------------------------------------------------------------
+
+extern "C" {
+
+int tdwp_plan(const tdwp_config* cfg, tdwp_plan_t* out) {
+  if (!out) return TDWP_EINVAL;
+  *out = nullptr;
+  TRY(validate(cfg));
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
+    (void)hipGetLastError();
+    return TDWP_EDEVICE;
+  }
+  Plan* P = new (std::nothrow) Plan();
+  if (!P) return TDWP_ENOMEM;
+  P->cfg = *cfg;
+  P->units_in.assign(cfg->units, cfg->units + cfg->n_units);
+  P->cfg.units = nullptr;
+  P->bounds_given = !(cfg->e_min == 0 && cfg->e_max == 0);
+  if (cfg->stream) {
+    P->stream = (hipStream_t)cfg->stream;
+  } else {
+    if (hipStreamCreate(&P->stream) != hipSuccess) {
+      delete P;
+      return TDWP_EDEVICE;
+    }
+    P->own_stream = true;
+  }
+  int st = build_tables(P);
+  if (st == TDWP_OK) st = layout_and_allocate(P);
+  if (st != TDWP_OK) {
+    free_plan(P);
+    return st;
+  }
+  if (P->bounds_given) {
+    P->e_min = cfg->e_min;
+    P->e_max = cfg->e_max;
+    P->E0 = 0.5 * (P->e_max + P->e_min);
+    P->dE = 0.5 * (P->e_max - P->e_min);
+  }
+  *out = P;
+  return TDWP_OK;
+}
+
+int tdwp_grid(tdwp_plan_t p, double* r, double* R, double* cos_gamma, double* gl_weights) {
+  if (!p) return TDWP_EINVAL;
+  if (r) std::memcpy(r, p->r.data(), p->nr * sizeof(double));
+  if (R) std::memcpy(R, p->R.data(), p->nR * sizeof(double));
+  if (cos_gamma) std::memcpy(cos_gamma, p->x.data(), p->ng * sizeof(double));
+  if (gl_weights) std::memcpy(gl_weights, p->w.data(), p->ng * sizeof(double));
+  return TDWP_OK;
+}
+
+int tdwp_diatomic_states(tdwp_plan_t p, const double* v_asym, int j, int n_states,
+                         double* energies, double* chi) {
+  if (!p || !v_asym || j < 0 || n_states < 1 || n_states > p->nr) return TDWP_EINVAL;
+  const int n = p->nr;
+  std::vector<double> A(p->Tr);
+  for (int i = 0; i < n; ++i) {
+    double rot = p->Br[i] * (double)j * (j + 1);
+    if (p->cfg.rot_cut > 0) rot = std::min(rot, p->cfg.rot_cut);
+    A[(size_t)i * n + i] += v_asym[i] + rot;
+  }
+  std::vector<double> ev, vec;
+  jacobi_eigh(n, A, ev, vec);
+  for (int s = 0; s < n_states; ++s) {
+    if (energies) energies[s] = ev[s];
+    if (!chi) continue;
+    double mx = 0.0, nrm = 0.0;
+    for (int i = 0; i < n; ++i) {
+      mx = std::max(mx, std::fabs(vec[(size_t)i * n + s]));
+      nrm += vec[(size_t)i * n + s] * vec[(size_t)i * n + s];
+    }
+    double sign = 1.0;
+    for (int i = 0; i < n; ++i)
+      if (std::fabs(vec[(size_t)i * n + s]) > 1e-3 * mx) {
+        sign = vec[(size_t)i * n + s] < 0 ? -1.0 : 1.0;
+        break;
+      }
+    const double scale = sign / std::sqrt(nrm);
+    for (int i = 0; i < n; ++i) chi[(size_t)s * n + i] = vec[(size_t)i * n + s] * scale;
+  }
+  return TDWP_OK;
+}
+
+int tdwp_set_potential(tdwp_plan_t p, int mode, const double* v, size_t n_values) {
+  if (!p || !v) return TDWP_EINVAL;
+  if (mode != TDWP_POT_TABLE) return TDWP_EINVAL;
+  const size_t plane = (size_t)p->ng * p->nR * p->nr;
+  if (n_values != (size_t)p->npair * plane) return TDWP_EINVAL;
+  HIP_TRY(hipMemcpyAsync(p->d_V, v, n_values * sizeof(double), hipMemcpyHostToDevice, p->stream));
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  if (!p->bounds_given) {
+    // Gershgorin range of the per-point diabatic matrix
+    const int ne = p->ne;
+    double lo = INFINITY, hi = -INFINITY;
+    for (size_t q = 0; q < plane; ++q) {
+      for (int a = 0; a < ne; ++a) {
+        double off = 0.0, dia = 0.0;
+        for (int b = 0; b < ne; ++b) {
+          const int i0 = std::min(a, b), i1 = std::max(a, b);
+          const int pi = i0 * ne - i0 * (i0 - 1) / 2 + (i1 - i0);
+          const double val = v[(size_t)pi * plane + q];
+          if (a == b) dia = val;
+          else off += std::fabs(val);
+        }
+        lo = std::min(lo, dia - off);
+        hi = std::max(hi, dia + off);
+      }
+    }
+    if (!std::isfinite(lo) || !std::isfinite(hi)) return TDWP_EINVAL;
+    double ang = 0.0;
+    for (auto& U : p->units)
+      for (int j = 0; j < p->ng; ++j) {
+        const int nj = U.n_om_j[j];
+        if (nj <= 0) continue;
+        const double lmax = U.ang_ell[U.ell_off[j] + nj - 1];
+        double e = p->Br[0] * (double)j * (j + 1) + p->BR[0] * lmax;
+        if (p->cfg.rot_cut > 0) e = std::min(e, p->cfg.rot_cut);
+        ang = std::max(ang, e);
+      }
+    const double tmax = *std::max_element(p->er.begin(), p->er.end()) +
+                        *std::max_element(p->eR.begin(), p->eR.end());
+    p->e_min = lo;
+    p->e_max = hi + tmax + ang;
+    p->E0 = 0.5 * (p->e_max + p->e_min);
+    p->dE = 0.5 * (p->e_max - p->e_min);
+  }
+  p->have_potential = true;
+  reset_propagation(p);
+  return TDWP_OK;
+}
+
+int tdwp_spectral_bounds(tdwp_plan_t p, double* e_min, double* e_max) {
+  if (!p) return TDWP_EINVAL;
+  if (!p->have_potential && !p->bounds_given) return TDWP_ESTATE;
+  if (e_min) *e_min = p->e_min;
+  if (e_max) *e_max = p->e_max;
+  return TDWP_OK;
+}
+
+int tdwp_set_initial_packet(tdwp_plan_t p, const tdwp_packet* pk, const double* chi0) {
+  if (!p || !pk || !chi0) return TDWP_EINVAL;
+  if (!p->have_potential) return TDWP_ESTATE;
+  if (pk->unit < 0 || pk->unit >= (int)p->units.size()) return TDWP_EINVAL;
+  const UnitInfo& U = p->units[pk->unit];
+  if (pk->slot < 0 || pk->slot >= U.n_packets) return TDWP_EINVAL;
+  if (pk->omega0 < U.om_lo || pk->omega0 > U.om_hi) return TDWP_EINVAL;
+  if (pk->j0 < pk->omega0 || pk->j0 > p->ng - 1) return TDWP_EINVAL;
+  if (pk->elec0 < 0 || pk->elec0 >= p->ne) return TDWP_EINVAL;
+  if (!(pk->width > 0) || !(pk->ecol_mean > 0) || pk->k_min_elastic < 0) return TDWP_EINVAL;
+  if (p->k > 0) reset_propagation(p);
+  int ip = -1;
+  for (size_t i = 0; i < p->packets.size(); ++i)
+    if (p->packets[i].unit == pk->unit && p->packets[i].slot == pk->slot) ip = (int)i;
+  PacketInfo& P = p->packets[ip];
+  P.pk = *pk;
+  const int nr = p->nr, nR = p->nR, ng = p->ng;
+  // factor vectors: Legendre row, DVR-weighted Gaussian, channel function
+  std::vector<double> pj(ng), g(nR), chi(nr);
+  double s = 0.0;
+  for (int n = 0; n < ng; ++n) {
+    pj[n] = p->Ptab[((size_t)pk->omega0 * ng + pk->j0) * ng + n];
+    s += pj[n] * pj[n];
+  }
+  for (auto& v : pj) v /= std::sqrt(s);
+  const double k0 = std::sqrt(2.0 * p->mu * pk->ecol_mean);
+  s = 0.0;
+  for (int mm = 0; mm < nR; ++mm) {
+    const double d = p->R[mm] - pk->R0;
+    g[mm] = std::sqrt(p->dR) * std::exp(-d * d / (2.0 * pk->width * pk->width)) * 2.0 *
+            std::cos(k0 * p->R[mm]);
+    s += g[mm] * g[mm];
+  }
+  if (!(s > 0)) return TDWP_EINVAL;
+  for (auto& v : g) v /= std::sqrt(s);
+  s = 0.0;
+  for (int i = 0; i < nr; ++i) {
+    chi[i] = chi0[i];
+    s += chi[i] * chi[i];
+  }
+  if (!(s > 0) || !std::isfinite(s)) return TDWP_EINVAL;
+  for (auto& v : chi) v /= std::sqrt(s);
+  P.g = g;
+  std::vector<double> stage;
+  stage.insert(stage.end(), pj.begin(), pj.end());
+  stage.insert(stage.end(), g.begin(), g.end());
+  stage.insert(stage.end(), chi.begin(), chi.end());
+  TRY(ensure_staging(p, &p->d_chan, &p->chan_cap, stage.size()));
+  HIP_TRY(hipMemcpyAsync(p->d_chan, stage.data(), stage.size() * sizeof(double),
+                         hipMemcpyHostToDevice, p->stream));
+  HIP_TRY(hipMemcpyAsync(p->d_g + (size_t)ip * nR, g.data(), nR * sizeof(double),
+                         hipMemcpyHostToDevice, p->stream));
+  const int col = (pk->omega0 - U.om_lo) * p->ne + pk->elec0;
+  hipLaunchKernelGGL(k_build_packet, dim3((unsigned)((P.n_values + 255) / 256)), dim3(256), 0,
+                     p->stream, p->d_u[p->cur] + P.off, p->d_u[1 - p->cur] + P.off, P.n_values,
+                     col, ng, nR, nr, p->d_chan, p->d_chan + ng, p->d_chan + ng + nR);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemsetAsync(p->d_acc + P.acc_off, 0, (size_t)2 * p->cfg.n_energy * P.n_slice * sizeof(double), p->stream));
+  HIP_TRY(hipMemsetAsync(p->d_snap + P.snap_off, 0, (size_t)2 * p->cfg.n_energy * P.n_w * sizeof(double), p->stream));
+  P.snap_taken = (pk->k_min_elastic == 0);
+  // k = 0 slices of this packet into ring row 0
+  {
+    const int nlines = P.n_sv;
+    hipLaunchKernelGGL(k_slices, dim3((nlines * 64 + 255) / 256), dim3(256), 0, p->stream,
+                       p->d_u[p->cur] + P.off, nlines, nR, nr, p->m_inf, p->d_arow, p->d_drow,
+                       1.0 / std::sqrt(p->dR), p->d_ring + P.slice_off);
+    HIP_TRY(hipGetLastError());
+  }
+  p->ring_k0 = 0;
+  p->ring_count = 1;
+  P.set = true;
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  return TDWP_OK;
+}
+
+int tdwp_propagate(tdwp_plan_t p, long n_steps, double* norms) {
+  if (!p || n_steps < 0) return TDWP_EINVAL;
+  return run_steps(p, n_steps, norms, nullptr);
+}
+
+int tdwp_step_index(tdwp_plan_t p, long* k) {
+  if (!p || !k) return TDWP_EINVAL;
+  *k = p->k;
+  return TDWP_OK;
+}
+
+int tdwp_get_packet(tdwp_plan_t p, int unit, int slot, int which, double* out) {
+  if (!p || !out || (which != 0 && which != 1)) return TDWP_EINVAL;
+  for (auto& pk : p->packets)
+    if (pk.unit == unit && pk.slot == slot) {
+      if (!pk.set) return TDWP_ESTATE;
+      const double* src = p->d_u[which == 0 ? p->cur : 1 - p->cur] + pk.off;
+      HIP_TRY(hipMemcpyAsync(out, src, pk.n_values * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+      HIP_TRY(hipStreamSynchronize(p->stream));
+      return TDWP_OK;
+    }
+  return TDWP_EINVAL;
+}
+
+int tdwp_state_to_state(tdwp_plan_t p, int unit, int slot, int n_ch, const tdwp_channel* ch,
+                        const double* chi, double* p_inel, double* p_reac) {
+  if (!p || n_ch < 0 || (n_ch > 0 && (!ch || !chi))) return TDWP_EINVAL;
+  int ip = -1;
+  for (size_t i = 0; i < p->packets.size(); ++i)
+    if (p->packets[i].unit == unit && p->packets[i].slot == slot) ip = (int)i;
+  if (ip < 0) return TDWP_EINVAL;
+  PacketInfo& P = p->packets[ip];
+  if (!P.set) return TDWP_ESTATE;
+  const UnitInfo& U = p->units[unit];
+  const tdwp_config& c = p->cfg;
+  const int nE = c.n_energy;
+  const double step = (c.ecol_max - c.ecol_min) / (nE - 1);
+  for (int f = 0; f < n_ch; ++f) {
+    if (ch[f].elec < 0 || ch[f].elec >= p->ne || ch[f].j < 0 || ch[f].j > p->ng - 1) return TDWP_EINVAL;
+    if (ch[f].omega < U.om_lo || ch[f].omega > U.om_hi) return TDWP_EINVAL;
+  }
+  TRY(flush_ring(p));
+  const size_t need_out = (size_t)(n_ch + p->ne) * nE;
+  TRY(ensure_staging(p, &p->d_out, &p->out_cap, need_out));
+  if (p_reac) {
+    hipLaunchKernelGGL(k_flux, dim3(p->ne, nE), dim3(256), 0, p->stream, p->d_out + (size_t)n_ch * nE,
+                       p->d_acc + P.acc_off, p->d_g + (size_t)ip * p->nR, U.n_om, nE, p->ne, p->ng,
+                       p->nR, P.n_slice, P.n_sv, c.ecol_min, step, p->mu, p->m, c.R_min, p->dR);
+    HIP_TRY(hipGetLastError());
+  }
+  if (n_ch > 0 && p_inel) {
+    // staging: chi [n_ch][nr], energies [n_ch], then int records [n_ch][5]
+    const size_t nd = (size_t)n_ch * p->nr + n_ch;
+    const size_t ni_d = ((size_t)n_ch * 5 * sizeof(int) + sizeof(double) - 1) / sizeof(double);
+    TRY(ensure_staging(p, &p->d_chan, &p->chan_cap, nd + ni_d));
+    std::vector<double> host(nd + ni_d, 0.0);
+    std::memcpy(host.data(), chi, (size_t)n_ch * p->nr * sizeof(double));
+    std::vector<int> rec((size_t)n_ch * 5);
+    for (int f = 0; f < n_ch; ++f) {
+      host[(size_t)n_ch * p->nr + f] = ch[f].energy;
+      const bool initial = ch[f].elec == P.pk.elec0 && ch[f].v == P.pk.v0 && ch[f].j == P.pk.j0 &&
+                           ch[f].omega == P.pk.omega0;
+      rec[f * 5 + 0] = ch[f].omega - U.om_lo;
+      rec[f * 5 + 1] = ch[f].elec;
+      rec[f * 5 + 2] = ch[f].j;
+      rec[f * 5 + 3] = ch[f].omega;
+      rec[f * 5 + 4] = initial ? 1 : 0;
+    }
+    std::memcpy(host.data() + nd, rec.data(), rec.size() * sizeof(int));
+    HIP_TRY(hipMemcpyAsync(p->d_chan, host.data(), host.size() * sizeof(double),
+                           hipMemcpyHostToDevice, p->stream));
+    const int snap_valid = P.snap_taken ? 1 : 0;
+    hipLaunchKernelGGL(k_project, dim3(n_ch, nE), dim3(256), 0, p->stream, p->d_out,
+                       p->d_acc + P.acc_off, p->d_snap + P.snap_off, snap_valid, p->d_chan,
+                       (const int*)(p->d_chan + nd), p->d_chan + (size_t)n_ch * p->nr, p->d_P,
+                       p->d_g + (size_t)ip * p->nR, n_ch, nE, p->ne, p->ng, p->nR, p->nr,
+                       P.n_slice, 2 * P.n_sv, P.n_w, c.ecol_min, step, P.pk.E_v0j0, p->mu,
+                       c.R_min, p->dR, p->R[p->m_inf]);
+    HIP_TRY(hipGetLastError());
+  }
+  std::vector<double> h(need_out);
+  HIP_TRY(hipMemcpyAsync(h.data(), p->d_out, need_out * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  if (p_inel && n_ch > 0) std::memcpy(p_inel, h.data(), (size_t)n_ch * nE * sizeof(double));
+  if (p_reac) std::memcpy(p_reac, h.data() + (size_t)n_ch * nE, (size_t)p->ne * nE * sizeof(double));
+  return TDWP_OK;
+}
+
+int tdwp_time_kernels(tdwp_plan_t p, long n_steps, int n_max, double* avg_us, char* names,
+                      size_t names_len) {
+  if (!p || n_steps < 1 || n_max < 0) return TDWP_EINVAL;
+  Timing T;
+  HIP_TRY(hipEventCreate(&T.ev[0]));
+  HIP_TRY(hipEventCreate(&T.ev[1]));
+  int st = run_steps(p, n_steps, nullptr, &T);
+  (void)hipEventDestroy(T.ev[0]);
+  (void)hipEventDestroy(T.ev[1]);
+  if (st != TDWP_OK) return st;
+  static const char* kinds[4] = {"angular_pot", "radial_epi", "slices", "accumulate"};
+  std::string joined;
+  for (int i = 0; i < 4; ++i) {
+    if (i < n_max && avg_us) avg_us[i] = T.calls[i] ? 1000.0 * T.ms[i] / T.calls[i] : 0.0;
+    if (i) joined += ";";
+    joined += kinds[i];
+  }
+  if (names && names_len) {
+    std::strncpy(names, joined.c_str(), names_len - 1);
+    names[names_len - 1] = 0;
+  }
+  return 4;
+}
+
+void tdwp_destroy(tdwp_plan_t p) { free_plan(p); }
+
+const char* tdwp_strerror(int code) {
+  switch (code) {
+    case TDWP_OK: return "ok";
+    case TDWP_EINVAL: return "invalid argument";
+    case TDWP_ENOMEM: return "out of device memory or plan too large";
+    case TDWP_EDEVICE: return "HIP device error";
+    case TDWP_ESTATE: return "call out of order";
+    case TDWP_ERANGE: return "packet norm diverged (spectral bounds too narrow)";
+    default: return "unknown error";
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,53 @@
+"""Sets up a library plan for a workload definition: evaluates the caller's
+potential-energy surface on the plan's own grid, solves the diatomic channel
+problems with the library's preparatory-stage entry point and installs the
+initial packets.  Marshalling only; no step of the method runs here."""
+import numpy as np
+
+from workloads import asymptotic_potential, diabatic_matrix
+
+from .tdwp import Plan
+
+
+def potential_table(plan, spec):
+    r, R, x, _ = plan.grid()
+    return diabatic_matrix(spec, r[None, None, :], R[None, :, None], x[:, None, None])
+
+
+def build(spec, precision="fp64", bounds=None, stream="current", vtable=None):
+    """Plan + potential + every initial packet.  Returns (plan, info) where info
+    holds the grid, E_v0j0 per packet and the initial channel functions."""
+    plan = Plan(spec, precision=precision, bounds=bounds, stream=stream)
+    r, R, x, w = plan.grid()
+    if vtable is None:
+        vtable = potential_table(plan, spec)
+    plan.set_potential(vtable)
+    info = dict(r=r, R=R, x=x, w=w, e0={}, chi0={})
+    for pk in spec["packets"]:
+        va = asymptotic_potential(spec, r, pk["elec0"])
+        e, chi = plan.diatomic_states(va, pk["j0"], pk["v0"] + 1)
+        E, c = e[pk["v0"]], chi[pk["v0"]]
+        plan.set_initial_packet(pk, c, E)
+        info["e0"][(pk["unit"], pk["slot"])] = E
+        info["chi0"][(pk["unit"], pk["slot"])] = c
+    return plan, info
+
+
+def channels(plan, spec, unit, jmax, vmax, elecs=None, omegas=None):
+    """Reactant-arrangement channels (elec, v, j, omega) with the library's
+    channel functions and energies."""
+    r = plan.grid()[0]
+    u = spec["units"][unit]
+    lo = 0 if u["parity"] * (-1) ** u["J"] == 1 else 1
+    oms = omegas if omegas is not None else list(range(lo, u["omega_max"] + 1))
+    out = []
+    for el in (elecs if elecs is not None else range(spec["n_elec"])):
+        va = asymptotic_potential(spec, r, el)
+        for j in range(jmax + 1):
+            e, chi = plan.diatomic_states(va, j, vmax + 1)
+            for v in range(vmax + 1):
+                for om in oms:
+                    if om <= j:
+                        out.append(dict(elec=el, v=v, j=j, omega=om, energy=float(e[v]),
+                                        chi=np.array(chi[v])))
+    return out

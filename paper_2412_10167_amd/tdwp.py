@@ -1,0 +1,266 @@
+"""ctypes binding of libtdwp.so (argument marshalling only; every step of the
+propagation and analysis runs in the library's HIP kernels).
+
+The library owns its device memory; PyTorch, when present, only supplies the
+current HIP stream so that the library's work is ordered with the caller's.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2, "fp16x3": 3}
+EXPORTED_SYMBOLS = (
+    "tdwp_plan", "tdwp_grid", "tdwp_diatomic_states", "tdwp_set_potential",
+    "tdwp_spectral_bounds", "tdwp_set_initial_packet", "tdwp_propagate", "tdwp_step_index",
+    "tdwp_get_packet", "tdwp_state_to_state", "tdwp_time_kernels", "tdwp_destroy",
+    "tdwp_strerror",
+)
+
+
+class TdwpError(RuntimeError):
+    def __init__(self, code, what):
+        self.code = code
+        super().__init__(f"{what}: {_strerror(code)} ({code})")
+
+
+class Unit(ctypes.Structure):
+    _fields_ = [("J", ctypes.c_int), ("parity", ctypes.c_int), ("omega_max", ctypes.c_int),
+                ("n_packets", ctypes.c_int)]
+
+
+class Config(ctypes.Structure):
+    _fields_ = [
+        ("n_r", ctypes.c_int), ("n_R", ctypes.c_int), ("n_gamma", ctypes.c_int),
+        ("r_min", ctypes.c_double), ("r_max", ctypes.c_double),
+        ("R_min", ctypes.c_double), ("R_max", ctypes.c_double),
+        ("mass_A", ctypes.c_double), ("mass_B", ctypes.c_double), ("mass_C", ctypes.c_double),
+        ("n_elec", ctypes.c_int),
+        ("rad_cut", ctypes.c_double), ("rot_cut", ctypes.c_double),
+        ("abs_r_start", ctypes.c_double), ("abs_r_strength", ctypes.c_double), ("abs_r_power", ctypes.c_int),
+        ("abs_R_start", ctypes.c_double), ("abs_R_strength", ctypes.c_double), ("abs_R_power", ctypes.c_int),
+        ("e_min", ctypes.c_double), ("e_max", ctypes.c_double),
+        ("r_flux", ctypes.c_double), ("R_inf", ctypes.c_double),
+        ("n_energy", ctypes.c_int), ("ecol_min", ctypes.c_double), ("ecol_max", ctypes.c_double),
+        ("n_units", ctypes.c_int), ("units", ctypes.POINTER(Unit)),
+        ("precision", ctypes.c_int),
+        ("stream", ctypes.c_void_p),
+    ]
+
+
+class Packet(ctypes.Structure):
+    _fields_ = [("unit", ctypes.c_int), ("slot", ctypes.c_int), ("v0", ctypes.c_int),
+                ("j0", ctypes.c_int), ("omega0", ctypes.c_int), ("elec0", ctypes.c_int),
+                ("E_v0j0", ctypes.c_double), ("R0", ctypes.c_double), ("width", ctypes.c_double),
+                ("ecol_mean", ctypes.c_double), ("k_min_elastic", ctypes.c_long)]
+
+
+class Channel(ctypes.Structure):
+    _fields_ = [("elec", ctypes.c_int), ("v", ctypes.c_int), ("j", ctypes.c_int),
+                ("omega", ctypes.c_int), ("energy", ctypes.c_double)]
+
+
+_LIB = None
+
+
+def library_path():
+    return os.environ.get("TDWP_LIBRARY", os.path.join(HERE, "libtdwp.so"))
+
+
+def load_library():
+    """Loads the HIP library; raises if it has not been built (there is no fallback)."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    path = library_path()
+    if not os.path.exists(path):
+        raise RuntimeError(f"tdwp HIP library not found at {path}; build it with "
+                           "`python -m paper_2412_10167_amd.build_lib` or __graft_entry__.build()")
+    lib = ctypes.CDLL(path)
+    dp = ctypes.POINTER(ctypes.c_double)
+    P = ctypes.c_void_p
+    lib.tdwp_plan.argtypes = [ctypes.POINTER(Config), ctypes.POINTER(ctypes.c_void_p)]
+    lib.tdwp_grid.argtypes = [P, dp, dp, dp, dp]
+    lib.tdwp_diatomic_states.argtypes = [P, dp, ctypes.c_int, ctypes.c_int, dp, dp]
+    lib.tdwp_set_potential.argtypes = [P, ctypes.c_int, dp, ctypes.c_size_t]
+    lib.tdwp_spectral_bounds.argtypes = [P, dp, dp]
+    lib.tdwp_set_initial_packet.argtypes = [P, ctypes.POINTER(Packet), dp]
+    lib.tdwp_propagate.argtypes = [P, ctypes.c_long, dp]
+    lib.tdwp_step_index.argtypes = [P, ctypes.POINTER(ctypes.c_long)]
+    lib.tdwp_get_packet.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp]
+    lib.tdwp_state_to_state.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                        ctypes.POINTER(Channel), dp, dp, dp]
+    lib.tdwp_time_kernels.argtypes = [P, ctypes.c_long, ctypes.c_int, dp, ctypes.c_char_p,
+                                      ctypes.c_size_t]
+    lib.tdwp_destroy.argtypes = [P]
+    lib.tdwp_destroy.restype = None
+    lib.tdwp_strerror.argtypes = [ctypes.c_int]
+    lib.tdwp_strerror.restype = ctypes.c_char_p
+    for name in EXPORTED_SYMBOLS:
+        if name not in ("tdwp_destroy", "tdwp_strerror"):
+            getattr(lib, name).restype = ctypes.c_int
+    _LIB = lib
+    return lib
+
+
+def _strerror(code):
+    try:
+        return load_library().tdwp_strerror(code).decode()
+    except Exception:  # library not loadable: plain code
+        return "error"
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _f64(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def _check(code, what):
+    if code < 0:
+        raise TdwpError(code, what)
+    return code
+
+
+def _current_stream():
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return torch.cuda.current_stream().cuda_stream
+    except Exception:
+        pass
+    return None
+
+
+class Plan:
+    """One tdwp plan: a batch of partial waves on one grid, owned device memory."""
+
+    def __init__(self, spec, precision="fp64", bounds=None, stream="current"):
+        self.lib = load_library()
+        self.spec = spec
+        units = spec["units"]
+        self._units = (Unit * len(units))(*[Unit(u["J"], u["parity"], u["omega_max"], u["n_packets"])
+                                           for u in units])
+        if stream == "current":
+            stream = _current_stream()
+        e_min, e_max = bounds if bounds is not None else (0.0, 0.0)
+        c = Config(
+            n_r=spec["n_r"], n_R=spec["n_R"], n_gamma=spec["n_gamma"],
+            r_min=spec["r_min"], r_max=spec["r_max"], R_min=spec["R_min"], R_max=spec["R_max"],
+            mass_A=spec["mass_A"], mass_B=spec["mass_B"], mass_C=spec["mass_C"],
+            n_elec=spec["n_elec"], rad_cut=spec["rad_cut"], rot_cut=spec["rot_cut"],
+            abs_r_start=spec["abs_r_start"], abs_r_strength=spec["abs_r_strength"],
+            abs_r_power=spec["abs_r_power"],
+            abs_R_start=spec["abs_R_start"], abs_R_strength=spec["abs_R_strength"],
+            abs_R_power=spec["abs_R_power"],
+            e_min=e_min, e_max=e_max, r_flux=spec["r_flux"], R_inf=spec["R_inf"],
+            n_energy=spec["n_energy"], ecol_min=spec["ecol_min"], ecol_max=spec["ecol_max"],
+            n_units=len(units), units=self._units, precision=PRECISIONS[precision],
+            stream=stream)
+        self._cfg = c
+        h = ctypes.c_void_p()
+        _check(self.lib.tdwp_plan(ctypes.byref(c), ctypes.byref(h)), "tdwp_plan")
+        self.handle = h
+
+    # -- plan queries ------------------------------------------------------
+    def grid(self):
+        s = self.spec
+        r, R = np.empty(s["n_r"]), np.empty(s["n_R"])
+        x, w = np.empty(s["n_gamma"]), np.empty(s["n_gamma"])
+        _check(self.lib.tdwp_grid(self.handle, _ptr(r), _ptr(R), _ptr(x), _ptr(w)), "tdwp_grid")
+        return r, R, x, w
+
+    def diatomic_states(self, v_asym, j, n_states):
+        v = _f64(v_asym)
+        e = np.empty(n_states)
+        chi = np.empty((n_states, self.spec["n_r"]))
+        _check(self.lib.tdwp_diatomic_states(self.handle, _ptr(v), j, n_states, _ptr(e), _ptr(chi)),
+               "tdwp_diatomic_states")
+        return e, chi
+
+    def set_potential(self, vtable, mode=0):
+        v = _f64(vtable)
+        _check(self.lib.tdwp_set_potential(self.handle, mode, _ptr(v), v.size), "tdwp_set_potential")
+
+    def spectral_bounds(self):
+        a, b = ctypes.c_double(), ctypes.c_double()
+        _check(self.lib.tdwp_spectral_bounds(self.handle, ctypes.byref(a), ctypes.byref(b)),
+               "tdwp_spectral_bounds")
+        return a.value, b.value
+
+    def set_initial_packet(self, packet, chi0, E_v0j0):
+        p = Packet(unit=packet["unit"], slot=packet["slot"], v0=packet["v0"], j0=packet["j0"],
+                   omega0=packet["omega0"], elec0=packet["elec0"], E_v0j0=E_v0j0,
+                   R0=packet["R0"], width=packet["width"], ecol_mean=packet["ecol_mean"],
+                   k_min_elastic=packet.get("k_min_elastic", 0))
+        c = _f64(chi0)
+        _check(self.lib.tdwp_set_initial_packet(self.handle, ctypes.byref(p), _ptr(c)),
+               "tdwp_set_initial_packet")
+
+    def n_packets(self):
+        return sum(u["n_packets"] for u in self.spec["units"])
+
+    def propagate(self, n_steps, norms=True):
+        out = np.empty((self.n_packets(), n_steps)) if norms else None
+        _check(self.lib.tdwp_propagate(self.handle, n_steps, _ptr(out) if norms else None),
+               "tdwp_propagate")
+        return out
+
+    def step_index(self):
+        k = ctypes.c_long()
+        _check(self.lib.tdwp_step_index(self.handle, ctypes.byref(k)), "tdwp_step_index")
+        return k.value
+
+    def n_omega(self, unit):
+        u = self.spec["units"][unit]
+        lo = 0 if u["parity"] * (-1) ** u["J"] == 1 else 1
+        return u["omega_max"] - lo + 1
+
+    def get_packet(self, unit=0, slot=0, which=0):
+        s = self.spec
+        out = np.empty((self.n_omega(unit), s["n_elec"], s["n_gamma"], s["n_R"], s["n_r"]))
+        _check(self.lib.tdwp_get_packet(self.handle, unit, slot, which, _ptr(out)), "tdwp_get_packet")
+        return out
+
+    def state_to_state(self, unit, slot, channels, reactive=True):
+        """channels: list of dicts (elec, v, j, omega, energy, chi)."""
+        s = self.spec
+        n = len(channels)
+        ch = (Channel * max(n, 1))(*[Channel(c["elec"], c["v"], c["j"], c["omega"], c["energy"])
+                                     for c in channels])
+        chi = _f64(np.array([c["chi"] for c in channels]) if n else np.zeros((1, s["n_r"])))
+        p_inel = np.empty((n, s["n_energy"]))
+        p_reac = np.empty((s["n_elec"], s["n_energy"]))
+        _check(self.lib.tdwp_state_to_state(self.handle, unit, slot, n, ch, _ptr(chi),
+                                            _ptr(p_inel) if n else None,
+                                            _ptr(p_reac) if reactive else None),
+               "tdwp_state_to_state")
+        return p_inel, (p_reac if reactive else None)
+
+    def time_kernels(self, n_steps, n_max=8):
+        avg = np.zeros(n_max)
+        names = ctypes.create_string_buffer(512)
+        n = _check(self.lib.tdwp_time_kernels(self.handle, n_steps, n_max, _ptr(avg), names, 512),
+                   "tdwp_time_kernels")
+        keys = names.value.decode().split(";")[:n]
+        return dict(zip(keys, avg[:n]))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.tdwp_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
