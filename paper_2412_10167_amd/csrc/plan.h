@@ -11,7 +11,8 @@ namespace tdwp {
 
 constexpr int kMaxOmega = 16;     // helicity blocks per unit (omega_max <= 15)
 constexpr int kMaxElec = 4;       // diabatic states
-constexpr int kRing = 64;         // Chebyshev slices buffered per energy-accumulation flush
+constexpr int kRing = 64;         // slices buffered per flush, general accumulation kernel
+constexpr int kRingFast = 256;    // slices buffered per flush, matrix-core accumulation
 constexpr int kNormChunk = 4096;  // steps of norms held on the device per host read-back
 
 struct UnitInfo {
@@ -69,12 +70,25 @@ struct tdwp_plan_s {
   size_t slice_total = 0;    // doubles per ring row
   size_t acc_total = 0, snap_total = 0;
   size_t n_wg_total = 0;     // norm partials per step
-  int rt_ang = 1;            // r-tile of the angular kernel
-  int rt_rad = 1;            // R-rows per workgroup of the radial kernel
+  int rt_ang = 1;            // r-tile of the angular kernel (general path)
+  int rt_rad = 1;            // R-rows per workgroup of the radial kernel (general path)
+  // matrix-core path (even n_r, n_R, n_gamma)
+  bool fast = false;
+  bool fast_accum = false;
+  int ntr = 1;               // 16-column tiles per k_radR_epi workgroup
+  int nrhk = 0, nRhk = 0, ngk = 0;
+  size_t lds_radr = 0, lds_ang = 0, lds_radR = 0;
+  std::vector<double> Trs, Trd, TRs, TRd, Pc;
+  double* d_Trs = nullptr;
+  double* d_Trd = nullptr;
+  double* d_TRs = nullptr;
+  double* d_TRd = nullptr;
+  double* d_Pc = nullptr;
   // propagation state
   long k = 0;
   int cur = 0;               // u_k lives in d_u[cur], u_{k-1} in d_u[1 - cur]
   int ring_count = 0;
+  int ring_len = tdwp::kRing;
   long ring_k0 = 0;
   // device
   hipStream_t stream = nullptr;
@@ -93,7 +107,7 @@ struct tdwp_plan_s {
   double* d_ring = nullptr;
   double* d_acc = nullptr;
   double* d_snap = nullptr;
-  double* d_coef = nullptr;       // [n_packets][2][n_E][kRing]
+  double* d_coef = nullptr;       // [n_packets][2][n_E][ring_len]
   double* d_normpart = nullptr;   // [kNormChunk][n_wg_total]
   double* d_norms = nullptr;      // [n_packets][kNormChunk]
   double* d_chan = nullptr;       // staging for channel functions

@@ -188,8 +188,8 @@ __global__ void k_slices(const double* __restrict__ u, int nlines, int nR, int n
 // Chebyshev energy coefficients c_k(E) = (2 - delta_k0) e^{-ik theta}/(dE sin theta),
 // theta = arccos((E_col + E_v0j0 - E0)/dE), for k = k0 .. k0 + count - 1.
 // coef layout [2][n_E][kRing] (real, imaginary).
-__global__ void k_coef(double* __restrict__ coef, int nE, double ecol_min, double ecol_step,
-                       double E_v0j0, double E0, double dE, long k0, int count) {
+__global__ void k_coef(double* __restrict__ coef, int ldc, int nE, double ecol_min,
+                       double ecol_step, double E_v0j0, double E0, double dE, long k0, int count) {
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= nE * count) return;
   const int e = q / count, b = q % count;
@@ -198,8 +198,8 @@ __global__ void k_coef(double* __restrict__ coef, int nE, double ecol_min, doubl
   const long kk = k0 + b;
   const double f = (kk == 0 ? 1.0 : 2.0) / (dE * sin(th));
   const double ph = (double)kk * th;
-  coef[(size_t)e * kRing + b] = f * cos(ph);
-  coef[((size_t)nE + e) * kRing + b] = -f * sin(ph);
+  coef[(size_t)e * ldc + b] = f * cos(ph);
+  coef[((size_t)nE + e) * ldc + b] = -f * sin(ph);
 }
 
 // acc[c][e][s] += sum_b coef[c][e][b] ring[b][s] for one packet (s < n_slice).

@@ -4,6 +4,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -11,18 +13,27 @@
 
 #include "host_tables.h"
 #include "plan.h"
+#include "fast_kernels.hpp"
 #include "step_kernels.hpp"
 
 using namespace tdwp;
 
 namespace {
 
-constexpr size_t kLdsBudget = 64 * 1024;
+constexpr size_t kLdsBudget = 64 * 1024;       // general kernels
+size_t kLdsMax = 64 * 1024;                    // queried per device in tdwp_plan
 
-#define HIP_TRY(expr)                                   \
-  do {                                                  \
-    hipError_t e_ = (expr);                             \
-    if (e_ != hipSuccess) return e_ == hipErrorOutOfMemory ? TDWP_ENOMEM : TDWP_EDEVICE; \
+// With TDWP_DEBUG set in the environment, HIP errors are reported on stderr.
+int hip_fail(hipError_t e, const char* what, int line) {
+  if (std::getenv("TDWP_DEBUG"))
+    std::fprintf(stderr, "tdwp: %s failed at line %d: %s\n", what, line, hipGetErrorString(e));
+  return e == hipErrorOutOfMemory ? TDWP_ENOMEM : TDWP_EDEVICE;
+}
+
+#define HIP_TRY(expr)                                     \
+  do {                                                    \
+    hipError_t e_ = (expr);                               \
+    if (e_ != hipSuccess) return hip_fail(e_, #expr, __LINE__); \
   } while (0)
 
 #define TRY(expr)                 \
@@ -76,7 +87,7 @@ int validate(const tdwp_config* c) {
   if (c->n_energy < 2 || !(c->ecol_min > 0) || !(c->ecol_max > c->ecol_min)) return TDWP_EINVAL;
   if (c->n_units < 1 || !c->units) return TDWP_EINVAL;
   if (!(c->e_min == 0 && c->e_max == 0) && !(c->e_max > c->e_min)) return TDWP_EINVAL;
-  if (c->precision != TDWP_FP64) return TDWP_EINVAL;
+  if (c->precision < TDWP_FP64 || c->precision > TDWP_FP16X3) return TDWP_EINVAL;
   for (int i = 0; i < c->n_units; ++i) {
     const tdwp_unit& u = c->units[i];
     if (u.J < 0 || (u.parity != 1 && u.parity != -1)) return TDWP_EINVAL;
@@ -183,7 +194,85 @@ int build_tables(Plan* P) {
     }
     P->units.push_back(U);
   }
+  // half-size operators of the matrix-core path (even sizes only)
+  if (P->nr % 2 == 0 && P->nR % 2 == 0 && P->ng % 2 == 0) {
+    auto split = [](const std::vector<double>& T, int N, int nhk, std::vector<double>& Ts,
+                    std::vector<double>& Td) {
+      const int h = N / 2;
+      Ts.assign((size_t)nhk * nhk, 0.0);
+      Td.assign((size_t)nhk * nhk, 0.0);
+      for (int i = 0; i < h; ++i)
+        for (int j = 0; j < h; ++j) {
+          const double a = T[(size_t)i * N + j], b = T[(size_t)i * N + (N - 1 - j)];
+          Ts[(size_t)i * nhk + j] = 0.5 * (a + b);
+          Td[(size_t)i * nhk + j] = 0.5 * (a - b);
+        }
+    };
+    P->nrhk = round_up(P->nr / 2, 32);
+    P->nRhk = round_up(P->nR / 2, 32);
+    P->ngk = round_up(P->ng / 2, 32);
+    split(P->Tr, P->nr, P->nrhk, P->Trs, P->Trd);
+    split(P->TR, P->nR, P->nRhk, P->TRs, P->TRd);
+    const int ngh = P->ng / 2, ngk = P->ngk;
+    P->Pc.assign((size_t)(P->max_om + 1) * 2 * ngk * ngk, 0.0);
+    for (int om = 0; om <= P->max_om; ++om)
+      for (int c = 0; c < 2; ++c)
+        for (int jj = 0; om + c + 2 * jj < P->ng; ++jj)
+          for (int n = 0; n < ngh; ++n)
+            P->Pc[(((size_t)om * 2 + c) * ngk + jj) * ngk + n] =
+                P->Ptab[((size_t)om * P->ng + om + c + 2 * jj) * P->ng + n];
+  }
   return TDWP_OK;
+}
+
+size_t ks_of(int prec) { return (prec == TDWP_BF16X3 || prec == TDWP_FP16X3) ? 32 : 4; }
+
+// Decides whether the matrix-core kernels apply and sizes their LDS.
+void choose_fast_path(Plan* P) {
+  P->fast = false;
+  if (P->nr % 2 || P->nR % 2 || P->ng % 2) return;
+  const size_t ks = ks_of(P->cfg.precision);
+  const size_t kpr = round_up(P->nr / 2, (int)ks), kpR = round_up(P->nR / 2, (int)ks);
+  const size_t kpa = round_up(P->ng / 2, (int)ks);
+  int max_om = 0;
+  for (auto& U : P->units) max_om = std::max(max_om, U.n_om);
+  P->lds_radr = (size_t)2 * kRadrLines * (kpr + 1) * sizeof(double);
+  P->lds_ang = ((size_t)2 * max_om * kpa * 16 + (size_t)max_om * P->ng * 16) * sizeof(double);
+  const int MT = (P->nR / 2 + 15) / 16;
+  const int per_wave = (P->ne * 2 * MT + 3) / 4;
+  P->ntr = (P->ne == 1 && per_wave * 2 <= kRadRMaxAcc && P->nr >= 32) ? 2 : 1;
+  if (per_wave * P->ntr > kRadRMaxAcc) return;
+  P->lds_radR = (size_t)2 * P->ne * kpR * 16 * P->ntr * sizeof(double);
+  if ((P->nr / 2 + 15) / 16 > 32) return;
+  if (P->lds_radr > kLdsMax || P->lds_ang > kLdsMax || P->lds_radR > kLdsMax) return;
+  P->fast = true;
+}
+
+// Raises the dynamic-LDS limit of the matrix-core kernels above the 64 KB
+// default where the device allows it; a refusal only matters if a launch
+// actually needs more, which choose_fast_path has already excluded.
+template <int PR>
+void set_lds_limits() {
+  if (kLdsMax <= 64 * 1024) return;
+  const void* fns[4] = {(const void*)k_radr<PR>, (const void*)k_ang<PR>,
+                        (const void*)k_radR_epi<PR, 1>, (const void*)k_radR_epi<PR, 2>};
+  for (const void* f : fns) {
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsMax);
+    if (e != hipSuccess) {
+      hip_fail(e, "hipFuncSetAttribute", __LINE__);
+      (void)hipGetLastError();
+    }
+  }
+}
+
+void query_lds_limit() {
+  int dev = 0, a = 0, b = 0;
+  if (hipGetDevice(&dev) != hipSuccess) { (void)hipGetLastError(); return; }
+  if (hipDeviceGetAttribute(&a, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) a = 0;
+  if (hipDeviceGetAttribute(&b, hipDeviceAttributeSharedMemPerBlockOptin, dev) != hipSuccess) b = 0;
+  (void)hipGetLastError();
+  const size_t lim = (size_t)std::max(a, b);
+  if (lim >= 64 * 1024) kLdsMax = lim;
 }
 
 int layout_and_allocate(Plan* P) {
@@ -208,6 +297,11 @@ int layout_and_allocate(Plan* P) {
     }
   if (P->rt_rad == 0) return TDWP_ENOMEM;
   const int n_tiles_R = (nR + P->rt_rad - 1) / P->rt_rad;
+  choose_fast_path(P);
+  if (!P->fast && P->cfg.precision != TDWP_FP64) return TDWP_EINVAL;
+  P->fast_accum = P->cfg.n_energy <= 16 * kAccMaxMT * 4 / 2;
+  P->ring_len = P->fast_accum ? kRingFast : kRing;
+  const int rtf = 16 * P->ntr;
   // packets
   P->packets.clear();
   size_t off = 0, soff = 0, aoff = 0, snoff = 0, wgoff = 0;
@@ -227,7 +321,7 @@ int layout_and_allocate(Plan* P) {
       pk.acc_off = aoff;
       pk.snap_off = snoff;
       pk.wg_off = wgoff;
-      pk.n_wg = U.n_om * ne * ng * n_tiles_R;
+      pk.n_wg = P->fast ? U.n_om * ng * ((nr + rtf - 1) / rtf) : U.n_om * ne * ng * n_tiles_R;
       off += pk.n_values;
       soff += pk.n_slice;
       aoff += (size_t)2 * nE * pk.n_slice;
@@ -263,10 +357,23 @@ int layout_and_allocate(Plan* P) {
     TRY(alloc_copy(P, &U.d_ell_off, U.ell_off));
     TRY(alloc_copy(P, &U.d_n_om_j, U.n_om_j));
   }
-  TRY(dev_alloc(P, (void**)&P->d_ring, (size_t)kRing * P->slice_total * sizeof(double)));
+  TRY(dev_alloc(P, (void**)&P->d_ring, (size_t)P->ring_len * P->slice_total * sizeof(double)));
   TRY(dev_alloc(P, (void**)&P->d_acc, P->acc_total * sizeof(double)));
   TRY(dev_alloc(P, (void**)&P->d_snap, P->snap_total * sizeof(double)));
-  TRY(dev_alloc(P, (void**)&P->d_coef, P->packets.size() * 2 * nE * kRing * sizeof(double)));
+  TRY(dev_alloc(P, (void**)&P->d_coef, P->packets.size() * 2 * nE * P->ring_len * sizeof(double)));
+  if (P->fast) {
+    TRY(alloc_copy(P, &P->d_Trs, P->Trs));
+    TRY(alloc_copy(P, &P->d_Trd, P->Trd));
+    TRY(alloc_copy(P, &P->d_TRs, P->TRs));
+    TRY(alloc_copy(P, &P->d_TRd, P->TRd));
+    TRY(alloc_copy(P, &P->d_Pc, P->Pc));
+    switch (P->cfg.precision) {
+      case TDWP_FP64: set_lds_limits<kP64>(); break;
+      case TDWP_FP32: set_lds_limits<kP32>(); break;
+      case TDWP_BF16X3: set_lds_limits<kPBF>(); break;
+      default: set_lds_limits<kPF16>(); break;
+    }
+  }
   TRY(dev_alloc(P, (void**)&P->d_normpart, (size_t)kNormChunk * P->n_wg_total * sizeof(double)));
   TRY(dev_alloc(P, (void**)&P->d_norms, P->packets.size() * kNormChunk * sizeof(double)));
   TRY(dev_alloc(P, (void**)&P->d_g, P->packets.size() * nR * sizeof(double)));
@@ -294,8 +401,8 @@ int ensure_staging(Plan* P, double** buf, size_t* cap, size_t need) {
 
 struct Timing {
   hipEvent_t ev[2];
-  double ms[4] = {0, 0, 0, 0};
-  long calls[4] = {0, 0, 0, 0};
+  double ms[5] = {0, 0, 0, 0, 0};
+  long calls[5] = {0, 0, 0, 0, 0};
 };
 
 int timed_begin(Plan* P, Timing* T) {
@@ -334,15 +441,22 @@ int flush_ring(Plan* P) {
   const double step = (c.ecol_max - c.ecol_min) / (nE - 1);
   for (size_t ip = 0; ip < P->packets.size(); ++ip) {
     auto& pk = P->packets[ip];
-    double* coef = P->d_coef + ip * 2 * nE * kRing;
+    double* coef = P->d_coef + ip * 2 * nE * P->ring_len;
     const int nq = nE * P->ring_count;
-    hipLaunchKernelGGL(k_coef, dim3((nq + 255) / 256), dim3(256), 0, P->stream, coef, nE,
-                       c.ecol_min, step, pk.pk.E_v0j0, P->E0, P->dE, P->ring_k0, P->ring_count);
-    const int epb = 8;
-    dim3 grid((pk.n_slice + 255) / 256, (nE + epb - 1) / epb);
-    hipLaunchKernelGGL(k_accumulate, grid, dim3(256), 0, P->stream, P->d_acc + pk.acc_off, coef,
-                       P->d_ring + pk.slice_off, P->slice_total, pk.n_slice, nE, epb,
-                       P->ring_count);
+    hipLaunchKernelGGL(k_coef, dim3((nq + 255) / 256), dim3(256), 0, P->stream, coef,
+                       P->ring_len, nE, c.ecol_min, step, pk.pk.E_v0j0, P->E0, P->dE,
+                       P->ring_k0, P->ring_count);
+    if (P->fast_accum) {
+      hipLaunchKernelGGL(k_accum_mfma, dim3((pk.n_slice + 31) / 32), dim3(256), 0, P->stream,
+                         P->d_acc + pk.acc_off, coef, P->ring_len, P->d_ring + pk.slice_off,
+                         P->slice_total, pk.n_slice, 2 * nE, P->ring_count);
+    } else {
+      const int epb = 8;
+      dim3 grid((pk.n_slice + 255) / 256, (nE + epb - 1) / epb);
+      hipLaunchKernelGGL(k_accumulate, grid, dim3(256), 0, P->stream, P->d_acc + pk.acc_off,
+                         coef, P->d_ring + pk.slice_off, P->slice_total, pk.n_slice, nE, epb,
+                         P->ring_count);
+    }
   }
   HIP_TRY(hipGetLastError());
   P->ring_k0 += P->ring_count;
@@ -364,7 +478,67 @@ int take_snapshots(Plan* P) {
   return TDWP_OK;
 }
 
+template <int PR>
+int fast_step(Plan* P, int chunk_row, Timing* T) {
+  using HT = typename HType<PR>::T;
+  const int first = (P->k == 0) ? 1 : 0;
+  const double* uk = P->d_u[P->cur];
+  double* uo = P->d_u[1 - P->cur];
+  HT* h = reinterpret_cast<HT*>(P->d_h);
+  const int nr = P->nr, nR = P->nR, ng = P->ng, ne = P->ne;
+  TRY(timed_begin(P, T));
+  for (auto& pk : P->packets) {
+    const long nlines = (long)(pk.n_values / nr);
+    hipLaunchKernelGGL(k_radr<PR>, dim3((unsigned)((nlines + kRadrLines - 1) / kRadrLines)),
+                       dim3(256), P->lds_radr, P->stream, uk + pk.off, h + pk.off, P->d_Trs,
+                       P->d_Trd, nr, P->nrhk, nlines);
+  }
+  HIP_TRY(hipGetLastError());
+  TRY(timed_end(P, T, 4));
+  TRY(timed_begin(P, T));
+  for (auto& pk : P->packets) {
+    const UnitInfo& U = P->units[pk.unit];
+    const size_t lds = ((size_t)2 * U.n_om * round_up(ng / 2, (int)ks_of(P->cfg.precision)) * 16 +
+                        (size_t)U.n_om * ng * 16) * sizeof(double);
+    hipLaunchKernelGGL(k_ang<PR>, dim3((nr + 15) / 16, nR, ne), dim3(256), lds, P->stream,
+                       uk + pk.off, h + pk.off, U.n_om, U.om_lo, ne, ng, nR, nr, P->d_Pc, P->ngk,
+                       U.d_U, U.d_ell, U.d_ang_off, U.d_ell_off, U.d_n_om_j, P->d_Br, P->d_BR,
+                       P->cfg.rot_cut);
+  }
+  HIP_TRY(hipGetLastError());
+  TRY(timed_end(P, T, 0));
+  TRY(timed_begin(P, T));
+  const int rt = 16 * P->ntr;
+  for (auto& pk : P->packets) {
+    const UnitInfo& U = P->units[pk.unit];
+    dim3 grid((nr + rt - 1) / rt, U.n_om * ng);
+    double* np = P->d_normpart + (size_t)chunk_row * P->n_wg_total + pk.wg_off;
+    if (P->ntr == 2)
+      hipLaunchKernelGGL((k_radR_epi<PR, 2>), grid, dim3(256), P->lds_radR, P->stream,
+                         uk + pk.off, uo + pk.off, h + pk.off, P->d_TRs, P->d_TRd, P->nRhk,
+                         P->d_V, P->d_D, ne, ng, nR, nr, P->E0, 1.0 / P->dE, first, np);
+    else
+      hipLaunchKernelGGL((k_radR_epi<PR, 1>), grid, dim3(256), P->lds_radR, P->stream,
+                         uk + pk.off, uo + pk.off, h + pk.off, P->d_TRs, P->d_TRd, P->nRhk,
+                         P->d_V, P->d_D, ne, ng, nR, nr, P->E0, 1.0 / P->dE, first, np);
+  }
+  HIP_TRY(hipGetLastError());
+  TRY(timed_end(P, T, 1));
+  return TDWP_OK;
+}
+
+int after_step(Plan* P, Timing* T);
+
 int one_step(Plan* P, int chunk_row, Timing* T) {
+  if (P->fast) {
+    switch (P->cfg.precision) {
+      case TDWP_FP64: TRY(fast_step<kP64>(P, chunk_row, T)); break;
+      case TDWP_FP32: TRY(fast_step<kP32>(P, chunk_row, T)); break;
+      case TDWP_BF16X3: TRY(fast_step<kPBF>(P, chunk_row, T)); break;
+      default: TRY(fast_step<kPF16>(P, chunk_row, T)); break;
+    }
+    return after_step(P, T);
+  }
   const int first = (P->k == 0) ? 1 : 0;
   double* uk = P->d_u[P->cur];
   double* uo = P->d_u[1 - P->cur];
@@ -393,13 +567,18 @@ int one_step(Plan* P, int chunk_row, Timing* T) {
   }
   HIP_TRY(hipGetLastError());
   TRY(timed_end(P, T, 1));
+  return after_step(P, T);
+}
+
+// Swaps the packet buffers and records the slices of the new u_k.
+int after_step(Plan* P, Timing* T) {
   P->cur = 1 - P->cur;
   P->k += 1;
   // slices of u_k (new k): flush first if the ring is full or an elastic window opens
   bool opens = false;
   for (auto& pk : P->packets)
     if (!pk.snap_taken && pk.pk.k_min_elastic == P->k) opens = true;
-  if (P->ring_count == kRing || opens) {
+  if (P->ring_count == P->ring_len || opens) {
     TRY(timed_begin(P, T));
     TRY(flush_ring(P));
     TRY(take_snapshots(P));
@@ -470,6 +649,7 @@ int tdwp_plan(const tdwp_config* cfg, tdwp_plan_t* out) {
     (void)hipGetLastError();
     return TDWP_EDEVICE;
   }
+  query_lds_limit();
   Plan* P = new (std::nothrow) Plan();
   if (!P) return TDWP_ENOMEM;
   P->cfg = *cfg;
@@ -771,9 +951,9 @@ int tdwp_time_kernels(tdwp_plan_t p, long n_steps, int n_max, double* avg_us, ch
   (void)hipEventDestroy(T.ev[0]);
   (void)hipEventDestroy(T.ev[1]);
   if (st != TDWP_OK) return st;
-  static const char* kinds[4] = {"angular_pot", "radial_epi", "slices", "accumulate"};
+  static const char* kinds[5] = {"angular", "radial_R_epilogue", "slices", "accumulate", "radial_r"};
   std::string joined;
-  for (int i = 0; i < 4; ++i) {
+  for (int i = 0; i < 5; ++i) {
     if (i < n_max && avg_us) avg_us[i] = T.calls[i] ? 1000.0 * T.ms[i] / T.calls[i] : 0.0;
     if (i) joined += ";";
     joined += kinds[i];
@@ -782,7 +962,7 @@ int tdwp_time_kernels(tdwp_plan_t p, long n_steps, int n_max, double* avg_us, ch
     std::strncpy(names, joined.c_str(), names_len - 1);
     names[names_len - 1] = 0;
   }
-  return 4;
+  return 5;
 }
 
 void tdwp_destroy(tdwp_plan_t p) { free_plan(p); }
