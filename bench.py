@@ -32,20 +32,29 @@ PEAKS = {  # MI355X published dense peaks
 
 
 def kernel_model(spec, name, precision):
-    """Algorithmic work of one launch of kernel `name` on the workload, as
-    (bound, amount, unit, peak): flops for dense contractions, bytes for streams."""
+    """Algorithmic work of one launch of kernel `name` on this single-unit workload:
+    (bound, amount, unit, peak).  Flops count the executed multiply-adds of the
+    even/odd-split contractions (2 per MAC); bytes count each HBM array the
+    kernel must touch once (packet FP64, H-partials FP64 or FP32, potential FP64)."""
     nr, nR, ng, ne = spec["n_r"], spec["n_R"], spec["n_gamma"], spec["n_elec"]
-    n_om = sum(u["omega_max"] + 1 for u in spec["units"])   # parity-even units: 0..omega_max
+    n_om = sum(u["omega_max"] + 1 for u in spec["units"])
     values = n_om * ne * ng * nR * nr
-    if name == "radial_epi":
-        flops = values * 2.0 * (nR + nr)
-        return "alu", flops / 1e12, "TFLOP/s", PEAKS["fp64"][0]
-    if name == "angular_pot":
-        flops = values * 4.0 * ng
-        return "alu", flops / 1e12, "TFLOP/s", PEAKS["fp64"][0]
-    if name == "slices":
-        return "hbm", values * 8.0 / 1e9, "GB/s", PEAKS["hbm"][0]
-    return None
+    hb = 8 if precision == "fp64" else 4
+    fp64 = precision == "fp64"
+    if name == "radial_R_epilogue":
+        # T_R split: nR flops per value; bytes: u_k, h, u_{k-1}, V, u_{k+1}
+        flops, byts = values * nR, values * (8 + hb + 8 + 8 * ne * (ne + 1) / 2 / (n_om * ne) + 8)
+    elif name == "radial_r":
+        flops, byts = values * nr, values * (8 + hb)
+    elif name == "angular":
+        flops, byts = values * 2 * ng, values * (8 + 2 * hb)
+    elif name == "slices":
+        flops, byts = values * 4, values * 8
+    else:
+        return None
+    if fp64 and flops / byts > PEAKS["fp64"][0] * 1e3 / PEAKS["hbm"][0]:
+        return "mfma", flops / 1e12, "TFLOP/s", PEAKS["fp64"][0], byts
+    return "hbm", byts / 1e9, "GB/s", PEAKS["hbm"][0], byts
 
 
 def cpu_baseline(spec, budget_s=15.0):
@@ -82,9 +91,14 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=400)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--precision", default="fp64")
+    ap.add_argument("--precision", default="fp32",
+                    help="contraction precision of the timed form: fp64, fp32, bf16x3, fp16x3")
+    ap.add_argument("--no-fp64-reference", action="store_true",
+                    help="skip timing the plain FP64 form beside a mixed form")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-steps", type=int, default=50)
+    ap.add_argument("--copy-calibration", type=int, default=0,
+                    help="also run one device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
@@ -99,31 +113,45 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     spec = config(2)
-    plan, _ = problem.build(spec, precision=args.precision)
     values = spec["n_R"] * spec["n_r"] * spec["n_gamma"]
-    plan.propagate(args.warmup, norms=False)
-    stream = torch.cuda.current_stream()
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    e0.record(stream)
-    plan.propagate(args.steps, norms=False)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms = e0.elapsed_time(e1)
-    steps_per_s = args.steps / (ms / 1e3)
 
+    def timed(precision, steps, warmup):
+        plan, _ = problem.build(spec, precision=precision)
+        plan.propagate(warmup, norms=False)
+        stream = torch.cuda.current_stream()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record(stream)
+        plan.propagate(steps, norms=False)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return plan, e0.elapsed_time(e1), time.perf_counter() - t0
+
+    plan, ms, wall = timed(args.precision, args.steps, args.warmup)
+    steps_per_s = args.steps / (ms / 1e3)
     kt = plan.time_kernels(args.kernel_steps)
     per_step = {k: v for k, v in kt.items()}
     dom = max((k for k in per_step if kernel_model(spec, k, args.precision)), key=lambda k: per_step[k])
-    bound, amount, unit, peak = kernel_model(spec, dom, args.precision)
+    bound, amount, unit, peak, _ = kernel_model(spec, dom, args.precision)
     achieved = amount / (per_step[dom] * 1e-6)
     roofline = dict(bound=bound, achieved=round(achieved, 3), peak=peak, unit=unit,
                     frac=round(achieved / peak, 4), traffic=None, kernel=dom,
                     kernel_avg_us=round(per_step[dom], 2),
                     kernels_avg_us={k: round(v, 2) for k, v in per_step.items()})
     plan.close()
+    fp64_rate = None
+    if args.precision != "fp64" and not args.no_fp64_reference:
+        p64, ms64, _ = timed("fp64", args.steps, args.warmup)
+        p64.close()
+        fp64_rate = args.steps / (ms64 / 1e3)
+    if args.copy_calibration:
+        n = args.copy_calibration * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -145,6 +173,8 @@ def main():
         "config": {"workload": "J=0 A+BC LEPS, R x r x gamma = 256x192x80, 1 state, 1 packet",
                    "precision": args.precision, "grid_values": values,
                    "grid_pt_steps_per_s": round(steps_per_s * values, 1),
+                   "fp64_steps_per_s": round(fp64_rate, 2) if fp64_rate else None,
+                   "speedup_vs_fp64": round(steps_per_s / fp64_rate, 3) if fp64_rate else None,
                    "wall_s": round(wall, 3)},
         "roofline": roofline,
         "cpu_baseline": cpu,
