@@ -22,6 +22,12 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+WORKLOAD_NAMES = {
+    2: "J=0 A+BC LEPS, R x r x gamma = 256x192x80, 1 state, 1 packet",
+    3: "J=20 Omega 0..8, 2 coupled states, 192x160x64",
+    4: "21 partial waves J=0..40 (Omega<=6) x 3 packets, 128x128x48",
+    5: "J=4 Omega 0..4, 3 coupled states, 256x256x96 (tabulated V)",
+}
 METRIC = "Chebyshev steps/s (grid-pt·steps/s) mixed vs FP64 at ≤1e-3 |ΔP(E)|"
 PEAKS = {  # MI355X published dense peaks
     "hbm": (8000.0, "GB/s"),
@@ -37,13 +43,14 @@ def kernel_model(spec, name, precision):
     even/odd-split contractions (2 per MAC); bytes count each HBM array the
     kernel must touch once (packet FP64, H-partials FP64 or FP32, potential FP64)."""
     nr, nR, ng, ne = spec["n_r"], spec["n_R"], spec["n_gamma"], spec["n_elec"]
-    n_om = sum(u["omega_max"] + 1 for u in spec["units"])
-    values = n_om * ne * ng * nR * nr
+    n_blk = sum((u["omega_max"] - (0 if u["parity"] * (-1) ** u["J"] == 1 else 1) + 1) * u["n_packets"]
+                for u in spec["units"])
+    values = n_blk * ne * ng * nR * nr
     hb = 8 if precision == "fp64" else 4
     fp64 = precision == "fp64"
     if name == "radial_R_epilogue":
         # T_R split: nR flops per value; bytes: u_k, h, u_{k-1}, V, u_{k+1}
-        flops, byts = values * nR, values * (8 + hb + 8 + 8 * ne * (ne + 1) / 2 / (n_om * ne) + 8)
+        flops, byts = values * nR, values * (8 + hb + 8 + 8 * ne * (ne + 1) / 2 / (n_blk * ne) + 8)
     elif name == "radial_r":
         flops, byts = values * nr, values * (8 + hb)
     elif name == "angular":
@@ -97,6 +104,8 @@ def main():
                     help="skip timing the plain FP64 form beside a mixed form")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-steps", type=int, default=50)
+    ap.add_argument("--workload", type=int, default=2,
+                    help="workload number 1..5 (default 2: J=0 256x192x80)")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="also run one device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -112,8 +121,10 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
-    spec = config(2)
-    values = spec["n_R"] * spec["n_r"] * spec["n_gamma"]
+    spec = config(args.workload)
+    values = sum(
+        (u["omega_max"] - (0 if u["parity"] * (-1) ** u["J"] == 1 else 1) + 1) * u["n_packets"]
+        for u in spec["units"]) * spec["n_elec"] * spec["n_R"] * spec["n_r"] * spec["n_gamma"]
 
     def timed(precision, steps, warmup):
         plan, _ = problem.build(spec, precision=precision)
@@ -154,7 +165,7 @@ def main():
         torch.cuda.synchronize()
 
     cpu = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and args.workload == 2:
         cpu = cpu_baseline(spec)
 
     out = {
@@ -170,7 +181,7 @@ def main():
         "vs_baseline": None,
         "dtype": {"fp64": "f64", "fp32": "f32+f64", "bf16x3": "bf16x3+f64", "fp16x3": "f16x3+f64"}[args.precision],
         "data": "synthetic",
-        "config": {"workload": "J=0 A+BC LEPS, R x r x gamma = 256x192x80, 1 state, 1 packet",
+        "config": {"workload": WORKLOAD_NAMES.get(args.workload, spec["name"]),
                    "precision": args.precision, "grid_values": values,
                    "grid_pt_steps_per_s": round(steps_per_s * values, 1),
                    "fp64_steps_per_s": round(fp64_rate, 2) if fp64_rate else None,

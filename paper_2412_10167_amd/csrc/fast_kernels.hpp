@@ -22,333 +22,537 @@
 
 namespace tdwp {
 
+// Per-packet description for the batched launches: one launch of each pass
+// covers every packet of every unit of the plan.
+struct PkDesc {
+  unsigned long off;      // offset of the packet in u / h (values)
+  unsigned long wg_off;   // first norm partial of the packet
+  int n_om, om_lo;
+  const double* U;        // angular blocks of the packet's unit
+  const double* ell;
+  const int* ang_off;
+  const int* ell_off;
+  const int* n_om_j;
+  int n_U, n_ell;         // sizes of U and ell (staged into LDS by k_ang)
+};
+
+// Index p with start[p] <= b < start[p + 1] (start has n + 1 entries).
+__device__ __forceinline__ int find_packet(const int* __restrict__ start, int n, int b) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (start[mid] <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
 constexpr int kRadrLines = 32;   // lines of r per k_radr workgroup (2 M-tiles)
-constexpr int kRadRMaxAcc = 12;  // 16x16 accumulators per wave in k_radR_epi (checked on the host)
+
+// Operand fragments of CH consecutive k-steps are loaded together, so one
+// memory latency is paid per CH matrix-core steps instead of per step.
+template <int P> struct Chunk { static constexpr int CH = (Mma<P>::KS == 4) ? 8 : 2; };
+
+template <int P> __host__ __device__ constexpr int tile_ld(int kp) {
+  return kp + (P == kPBF || P == kPF16 ? 8 : 1);
+}
 
 // ---- h = T_r u along r --------------------------------------------------------
+// One workgroup per 32 lines (2 M-tiles) of length n_r.  LDS holds the sum and
+// difference halves of the lines in compute format; the half-size operators come
+// from global tables in compute format (symmetric, so their rows are the
+// transposed B operand).  Wave w takes M-tile w % 2 and N-tiles w/2, w/2 + 2, ...
+// With record != 0 the workgroup also writes the flux line (a . u, d . u via the
+// sum/difference halves of the flux rows) and, for lines at R index m_inf, the
+// R_inf line of every packet into the ring row (the same layout k_slices uses).
+struct SliceArgs {
+  int record;
+  int slices_only;                 // record and return (no T_r contraction)
+  const long* line_start;          // first line of each packet (n_pk + 1 entries)
+  const unsigned long* slice_off;  // packet slice offsets in a ring row
+  int n_pk, nR, m_inf;
+  const double* a_s;               // flux rows split into sum / difference halves
+  const double* a_d;
+  const double* d_s;
+  const double* d_d;
+  double inv_sqrt_dR;
+  double* ring_row;
+};
+
 template <int P>
 __global__ __launch_bounds__(256) void k_radr(const double* __restrict__ u,
                                               typename HType<P>::T* __restrict__ h,
-                                              const double* __restrict__ Ts,
-                                              const double* __restrict__ Td, int nr, int nhk,
-                                              long nlines) {
+                                              const typename Fmt<P>::E* __restrict__ Ts,
+                                              const typename Fmt<P>::E* __restrict__ Td,
+                                              int ldt, int pst, int nr, long nlines,
+                                              SliceArgs sa) {
   using M = Mma<P>;
-  extern __shared__ double lds[];
+  using F = Fmt<P>;
+  using E = typename F::E;
+  constexpr int CH = Chunk<P>::CH;
+  extern __shared__ __align__(16) double lds[];
   const int nh = nr >> 1;
   const int kp = round_up(nh, M::KS);
-  const int ld = kp + 1;
-  double* S = lds;
-  double* Dd = lds + kRadrLines * ld;
+  const int ld = tile_ld<P>(kp);
+  const int ps = kRadrLines * ld;
+  E* S = reinterpret_cast<E*>(lds);
+  E* Dd = S + F::PLANES * ps;
   const long line0 = (long)blockIdx.x * kRadrLines;
-  for (int q = threadIdx.x; q < kRadrLines * kp; q += blockDim.x) {
-    const int li = q / kp, k = q % kp;
+  // wave w loads lines w, w+4, ...; lanes run along the half line
+  for (int li = threadIdx.x >> 6; li < kRadrLines; li += 4) {
     const long gl = line0 + li;
-    double a = 0.0, b = 0.0;
-    if (gl < nlines && k < nh) {
-      const double* p = u + gl * nr;
-      a = p[k];
-      b = p[nr - 1 - k];
+    const double* p = u + gl * nr;
+    int pkx = 0;
+    long local = 0;
+    bool rinf = false;
+    if (sa.record && gl < nlines) {
+      int lo = 0, hi = sa.n_pk - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (sa.line_start[mid] <= gl) lo = mid;
+        else hi = mid - 1;
+      }
+      pkx = lo;
+      local = gl - sa.line_start[lo];
+      rinf = (local % sa.nR) == sa.m_inf;
     }
-    S[li * ld + k] = a + b;
-    Dd[li * ld + k] = a - b;
+    double sv = 0.0, sd = 0.0;
+    double* wline = nullptr;
+    if (rinf) {
+      const long nsv = sa.line_start[pkx + 1] - sa.line_start[pkx];
+      wline = sa.ring_row + sa.slice_off[pkx] + 2 * nsv + (local / sa.nR) * nr;
+    }
+    for (int k = threadIdx.x & 63; k < kp; k += 64) {
+      double a = 0.0, b = 0.0;
+      if (gl < nlines && k < nh) {
+        a = p[k];
+        b = p[nr - 1 - k];
+        if (sa.record) {
+          sv += sa.a_s[k] * (a + b) + sa.a_d[k] * (a - b);
+          sd += sa.d_s[k] * (a + b) + sa.d_d[k] * (a - b);
+          if (rinf) {
+            wline[k] = a * sa.inv_sqrt_dR;
+            wline[nr - 1 - k] = b * sa.inv_sqrt_dR;
+          }
+        }
+      }
+      F::put(S, ps, li * ld + k, a + b);
+      F::put(Dd, ps, li * ld + k, a - b);
+    }
+    if (sa.record && gl < nlines) {
+      for (int off = 32; off > 0; off >>= 1) {
+        sv += __shfl_down(sv, off, 64);
+        sd += __shfl_down(sd, off, 64);
+      }
+      if ((threadIdx.x & 63) == 0) {
+        const long nsv = sa.line_start[pkx + 1] - sa.line_start[pkx];
+        double* out = sa.ring_row + sa.slice_off[pkx];
+        out[local] = sv;
+        out[nsv + local] = sd;
+      }
+    }
   }
+  if (sa.slices_only) return;
   __syncthreads();
   const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int NT = (nh + 15) >> 4;
   const int mt = w & 1;
-  const double* Sw = S + (16 * mt) * ld;
-  const double* Dw = Dd + (16 * mt) * ld;
-  auto As = [&](int i, int k) { return Sw[i * ld + k]; };
-  auto Ad = [&](int i, int k) { return Dw[i * ld + k]; };
-  for (int ntb = (w >> 1); ntb < NT; ntb += 8) {
-    typename M::acc_t cs[4], cd[4];
+  const E* Sw = S + 16 * mt * ld;
+  const E* Dw = Dd + 16 * mt * ld;
+  for (int nt = (w >> 1); nt < NT; nt += 2) {
+    typename M::acc_t cs = M::zero(), cd = M::zero();
+    const E* Bs = Ts + (size_t)nt * 16 * ldt;
+    const E* Bd = Td + (size_t)nt * 16 * ldt;
+    for (int k0 = 0; k0 < kp; k0 += CH * M::KS) {
+      typename M::frag_t bs[CH], bd[CH];
 #pragma unroll
-    for (int g = 0; g < 4; ++g) {
-      cs[g] = M::zero();
-      cd[g] = M::zero();
-    }
-    for (int k0 = 0; k0 < kp; k0 += M::KS) {
-      const auto fs = M::load_a(As, k0, l);
-      const auto fd = M::load_a(Ad, k0, l);
-#pragma unroll
-      for (int g = 0; g < 4; ++g) {
-        const int nt = ntb + 2 * g;
-        if (nt < NT) {
-          auto Bs = [&](int k, int j) { return Ts[(size_t)k * nhk + nt * 16 + j]; };
-          auto Bd = [&](int k, int j) { return Td[(size_t)k * nhk + nt * 16 + j]; };
-          M::mma(cs[g], fs, M::load_b(Bs, k0, l));
-          M::mma(cd[g], fd, M::load_b(Bd, k0, l));
+      for (int c = 0; c < CH; ++c)
+        if (k0 + c * M::KS < kp) {
+          bs[c] = F::frag(Bs, ldt, pst, l, k0 + c * M::KS);
+          bd[c] = F::frag(Bd, ldt, pst, l, k0 + c * M::KS);
         }
-      }
-    }
 #pragma unroll
-    for (int g = 0; g < 4; ++g) {
-      const int nt = ntb + 2 * g;
-      if (nt >= NT) continue;
-      const int a = nt * 16 + (l & 15);
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const long gl = line0 + 16 * mt + M::row(l, v);
-        if (gl < nlines && a < nh) {
-          const double ys = (double)cs[g][v] * M::kUnscale;
-          const double yd = (double)cd[g][v] * M::kUnscale;
-          h[gl * nr + a] = (typename HType<P>::T)(ys + yd);
-          h[gl * nr + nr - 1 - a] = (typename HType<P>::T)(ys - yd);
+      for (int c = 0; c < CH; ++c)
+        if (k0 + c * M::KS < kp) {
+          M::mma(cs, F::frag(Sw, ld, ps, l, k0 + c * M::KS), bs[c]);
+          M::mma(cd, F::frag(Dw, ld, ps, l, k0 + c * M::KS), bd[c]);
         }
+    }
+    const int a = nt * 16 + (l & 15);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const long gl = line0 + 16 * mt + M::row(l, v);
+      if (gl < nlines && a < nh) {
+        const double ys = (double)cs[v] * M::kUnscale;
+        const double yd = (double)cd[v] * M::kUnscale;
+        h[gl * nr + a] = (typename HType<P>::T)(ys + yd);
+        h[gl * nr + nr - 1 - a] = (typename HType<P>::T)(ys - yd);
       }
     }
   }
 }
 
 // ---- h += angular + Coriolis terms -----------------------------------------------
-// One workgroup per (r tile of 16, R index m, elec l) of one packet; all helicities.
-// Pc: [omega][class][jj][n'] = P^omega[omega + class + 2 jj][n'] (n' < ng/2), zero padded
-// to ngk x ngk per (omega, class).
-template <int P>
-__global__ __launch_bounds__(256) void k_ang(const double* __restrict__ u,
-                                             typename HType<P>::T* __restrict__ h, int n_om,
-                                             int om_lo, int ne, int ng, int nR, int nr,
-                                             const double* __restrict__ Pc, int ngk,
-                                             const double* __restrict__ U,
-                                             const double* __restrict__ ell,
-                                             const int* __restrict__ ang_off,
-                                             const int* __restrict__ ell_off,
-                                             const int* __restrict__ n_om_j,
+// One workgroup per (r tile of 16 NT columns, R index m, elec l) of one packet,
+// all helicities.  Pc / PcT: [omega][class][jj][n'] and [omega][class][n'][jj]
+// with P^omega[omega + class + 2 jj][n'] (n' < ng/2), compute format, zero padded
+// to ngk x ngk.  LDS tiles X[o][class][t][n'] (sums / differences of mirrored
+// nodes) are replaced by the FBR coefficients C[o][class][t][jj] once every wave
+// has finished reading them (forward results are held in registers meanwhile).
+constexpr int kAngMaxAcc = 12;   // 16x16 accumulators per wave held across the barrier
+
+__device__ __forceinline__ int n_class(int ng, int Om, int c) {
+  const int top = ng - 1 - (Om + c);
+  return top >= 0 ? top / 2 + 1 : 0;
+}
+
+template <int P, int NT, int MAXOM>
+__global__ __launch_bounds__(256) void k_ang(const double* __restrict__ u_all,
+                                             typename HType<P>::T* __restrict__ h_all,
+                                             const PkDesc* __restrict__ pks,
+                                             const int* __restrict__ blk_start, int n_pk, int ne,
+                                             int ng, int nR, int nr,
+                                             const typename Fmt<P>::E* __restrict__ Pc,
+                                             const typename Fmt<P>::E* __restrict__ PcT,
+                                             int ngk, int psp,
                                              const double* __restrict__ Br,
                                              const double* __restrict__ BR, double rot_cut) {
   using M = Mma<P>;
-  extern __shared__ double lds[];
+  using F = Fmt<P>;
+  using E = typename F::E;
+  constexpr int CH = Chunk<P>::CH;
+  constexpr int RT = 16 * NT;
+  constexpr int RES = kAngMaxAcc / NT;
+  extern __shared__ __align__(16) double lds[];
+  const int pk = find_packet(blk_start, n_pk, blockIdx.x);
+  const int local = blockIdx.x - blk_start[pk];
+  const PkDesc d = pks[pk];
+  const double* __restrict__ u = u_all + d.off;
+  typename HType<P>::T* __restrict__ h = h_all + d.off;
+  const int n_om = d.n_om, om_lo = d.om_lo;
+  const int nrt = (nr + RT - 1) / RT;
   const int ngh = ng >> 1;
   const int kpa = round_up(ngh, M::KS);
-  const int i0 = blockIdx.x * 16;
-  const int m = blockIdx.y;
-  const int le = blockIdx.z;
+  const int ld = tile_ld<P>(kpa);
+  const int tile = RT * ld;                 // one (o, class) tile, per plane
+  const int ps = n_om * 2 * tile;           // plane stride
+  const int i0 = (local % nrt) * RT;
+  const int m = (local / nrt) % nR;
+  const int le = local / (nrt * nR);
   const size_t plane = (size_t)nR * nr;
-  double* Xp = lds;                               // [o][kpa][16]
-  double* Xm = Xp + (size_t)n_om * kpa * 16;      // [o][kpa][16]
-  double* C = Xm + (size_t)n_om * kpa * 16;       // [o][ng][16]
-  for (int q = threadIdx.x; q < n_om * kpa * 16; q += blockDim.x) {
-    const int t = q & 15, k = (q >> 4) % kpa, o = (q >> 4) / kpa;
-    const int i = i0 + t;
-    double a = 0.0, b = 0.0;
-    if (k < ngh && i < nr) {
-      const size_t col = (size_t)(o * ne + le) * ng;
-      a = u[(col + k) * plane + (size_t)m * nr + i];
-      b = u[(col + ng - 1 - k) * plane + (size_t)m * nr + i];
-    }
-    Xp[q] = a + b;
-    Xm[q] = a - b;
-  }
-  for (int q = threadIdx.x; q < n_om * ng * 16; q += blockDim.x) C[q] = 0.0;
-  __syncthreads();
-  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
-  // forward: C[o][Omega + c + 2jj][t] = sum_n' Pc[Omega][c][jj][n'] X_c[o][n'][t]
+  E* X = reinterpret_cast<E*>(lds);         // [o][class][t][k], then C
+  // angular blocks of the unit, after the tiles (16-byte aligned)
+  double* Ul = lds + (((size_t)F::PLANES * ps * sizeof(E) + 15) / 16) * 2;
+  double* elll = Ul + d.n_U;
+  for (int q = threadIdx.x; q < d.n_U; q += blockDim.x) Ul[q] = d.U[q];
+  for (int q = threadIdx.x; q < d.n_ell; q += blockDim.x) elll[q] = d.ell[q];
   {
-    int item = 0;
+    const int t = threadIdx.x % RT, k_first = threadIdx.x / RT;
+    constexpr int kstep = 256 / RT;
+    const int i = i0 + t;
+    const double* ub = u + (size_t)m * nr + i;
     for (int o = 0; o < n_om; ++o) {
-      const int Om = om_lo + o;
-      for (int c = 0; c < 2; ++c) {
-        const int njc = (ng - 1 - (Om + c)) >= 0 ? (ng - 1 - (Om + c)) / 2 + 1 : 0;
-        for (int mt = 0; mt * 16 < njc; ++mt, ++item) {
-          if ((item & 3) != w) continue;
-          const double* Ab = Pc + ((size_t)(Om * 2 + c) * ngk + mt * 16) * ngk;
-          const double* Bb = (c ? Xm : Xp) + (size_t)o * kpa * 16;
-          auto A = [&](int i, int k) { return Ab[(size_t)i * ngk + k]; };
-          auto B = [&](int k, int j) { return Bb[k * 16 + j]; };
-          typename M::acc_t acc = M::zero();
-          for (int k0 = 0; k0 < kpa; k0 += M::KS) M::mma(acc, M::load_a(A, k0, l), M::load_b(B, k0, l));
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int jj = mt * 16 + M::row(l, v);
-            if (jj < njc) C[((size_t)o * ng + Om + c + 2 * jj) * 16 + (l & 15)] = (double)acc[v] * M::kUnscale;
-          }
+      const size_t col = (size_t)(o * ne + le) * ng;
+      E* x0 = X + (o * 2 + 0) * tile + t * ld;
+      E* x1 = X + (o * 2 + 1) * tile + t * ld;
+      for (int k = k_first; k < kpa; k += kstep) {
+        double a = 0.0, b = 0.0;
+        if (k < ngh && i < nr) {
+          a = ub[(col + k) * plane];
+          b = ub[(col + ng - 1 - k) * plane];
         }
+        F::put(x0, ps, k, a + b);
+        F::put(x1, ps, k, a - b);
       }
     }
   }
   __syncthreads();
-  // Omega mixing at fixed j: U diag(min(B_r j(j+1) + B_R ell_a, rot_cut)) U^T
-  const double bR = BR[m];
-  for (int q = threadIdx.x; q < ng * 16; q += blockDim.x) {
-    const int t = q & 15, j = q >> 4;
-    const int nj = n_om_j[j];
-    if (nj <= 0 || i0 + t >= nr) continue;
-    const double rot = Br[i0 + t] * (double)j * (double)(j + 1);
-    const double* Uj = U + ang_off[j];
-    const double* lj = ell + ell_off[j];
-    double cv[kMaxOmega], tt[kMaxOmega];
-    for (int a = 0; a < nj; ++a) cv[a] = C[((size_t)a * ng + j) * 16 + t];
-    for (int b = 0; b < nj; ++b) {
-      double s = 0.0;
-      for (int a = 0; a < nj; ++a) s += Uj[a * nj + b] * cv[a];
-      double e = rot + bR * lj[b];
-      if (rot_cut > 0.0) e = fmin(e, rot_cut);
-      tt[b] = s * e;
-    }
-    for (int a = 0; a < nj; ++a) {
-      double s = 0.0;
-      for (int b = 0; b < nj; ++b) s += Uj[a * nj + b] * tt[b];
-      C[((size_t)a * ng + j) * 16 + t] = s;
+  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int mt_per = (kpa + 15) >> 4;   // forward M-tiles per (omega, class): rows up to kpa
+  const size_t tab = (size_t)ngk * ngk;
+  typename M::acc_t res[RES][NT];
+#pragma unroll
+  for (int r = 0; r < RES; ++r) {
+    const int it = w + 4 * r;
+    const int o = it / (2 * mt_per), c = (it / mt_per) & 1, mt = it % mt_per;
+    if (o >= n_om) break;
+    const int Om = om_lo + o;
+    const E* Ab = Pc + (size_t)(Om * 2 + c) * tab + (size_t)mt * 16 * ngk;
+    const E* Bb = X + (o * 2 + c) * tile;
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) res[r][nt] = M::zero();
+    for (int k0 = 0; k0 < kpa; k0 += CH * M::KS) {
+      typename M::frag_t fa[CH];
+#pragma unroll
+      for (int q = 0; q < CH; ++q)
+        if (k0 + q * M::KS < kpa) fa[q] = F::frag(Ab, ngk, psp, l, k0 + q * M::KS);
+#pragma unroll
+      for (int q = 0; q < CH; ++q)
+        if (k0 + q * M::KS < kpa) {
+#pragma unroll
+          for (int nt = 0; nt < NT; ++nt)
+            M::mma(res[r][nt], fa[q], F::frag(Bb + nt * 16 * ld, ld, ps, l, k0 + q * M::KS));
+        }
     }
   }
   __syncthreads();
-  // back: H_c[o][n'][t] = sum_jj Pc[Omega][c][jj][n'] C[o][Omega + c + 2jj][t]
-  {
-    int item = 0;
-    const int NTh = (ngh + 15) >> 4;
-    for (int o = 0; o < n_om; ++o) {
-      const int Om = om_lo + o;
-      const int nj0 = (ng - 1 - Om) >= 0 ? (ng - 1 - Om) / 2 + 1 : 0;
-      const int nj1 = (ng - 2 - Om) >= 0 ? (ng - 2 - Om) / 2 + 1 : 0;
-      const int kb = round_up(nj0 > nj1 ? nj0 : nj1, M::KS);
-      for (int mt = 0; mt < NTh; ++mt, ++item) {
-        if ((item & 3) != w) continue;
-        typename M::acc_t acc[2] = {M::zero(), M::zero()};
+  // C[o][class][t][jj], jj < kpa (rows past the class size come out zero:
+  // the table rows there are zero)
 #pragma unroll
-        for (int c = 0; c < 2; ++c) {
-          const int njc = c ? nj1 : nj0;
-          const double* Ab = Pc + (size_t)(Om * 2 + c) * ngk * ngk + mt * 16;
-          const double* Cb = C + ((size_t)o * ng + Om + c) * 16;
-          auto A = [&](int i, int k) { return Ab[(size_t)k * ngk + i]; };
-          auto B = [&](int k, int j) { return k < njc ? Cb[(size_t)(2 * k) * 16 + j] : 0.0; };
-          for (int k0 = 0; k0 < kb; k0 += M::KS) M::mma(acc[c], M::load_a(A, k0, l), M::load_b(B, k0, l));
-        }
-        const int t = l & 15;
-        const int i = i0 + t;
-        if (i >= nr) continue;
-        const size_t col = (size_t)(o * ne + le) * ng;
+  for (int r = 0; r < RES; ++r) {
+    const int it = w + 4 * r;
+    const int o = it / (2 * mt_per), c = (it / mt_per) & 1, mt = it % mt_per;
+    if (o >= n_om) break;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int n = mt * 16 + M::row(l, v);
-          if (n >= ngh) continue;
-          const double h0 = (double)acc[0][v] * M::kUnscale, h1 = (double)acc[1][v] * M::kUnscale;
-          const size_t ia = (col + n) * plane + (size_t)m * nr + i;
-          const size_t ib = (col + ng - 1 - n) * plane + (size_t)m * nr + i;
-          h[ia] = (typename HType<P>::T)((double)h[ia] + h0 + h1);
-          h[ib] = (typename HType<P>::T)((double)h[ib] + h0 - h1);
-        }
+    for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int jj = mt * 16 + M::row(l, v);
+        if (jj < kpa)
+          F::put(X, ps, (o * 2 + c) * tile + (nt * 16 + (l & 15)) * ld + jj,
+                 (double)res[r][nt][v] * M::kUnscale);
+      }
+  }
+  __syncthreads();
+  // Omega mixing at fixed j: U diag(min(B_r j(j+1) + B_R ell_a, rot_cut)) U^T
+  const double bR = BR[m];
+  for (int q = threadIdx.x; q < ng * RT; q += blockDim.x) {
+    const int t = q % RT, j = q / RT;
+    const int nj = d.n_om_j[j];
+    if (nj <= 0 || i0 + t >= nr) continue;
+    const double rot = Br[i0 + t] * (double)j * (double)(j + 1);
+    const double* Uj = Ul + d.ang_off[j];
+    const double* lj = elll + d.ell_off[j];
+    auto pos = [&](int a) {
+      const int Om = om_lo + a, c = (j + Om) & 1;
+      return (a * 2 + c) * tile + t * ld + (j - Om - c) / 2;
+    };
+    if (MAXOM == 1 || nj == 1) {   // a single helicity: U = [1]
+      double e = rot + bR * lj[0];
+      if (rot_cut > 0.0) e = fmin(e, rot_cut);
+      F::put(X, ps, pos(0), F::get(X, ps, pos(0)) * e);
+      continue;
+    }
+    if constexpr (MAXOM > 1) {
+      double cv[MAXOM], tt[MAXOM];
+      for (int a = 0; a < nj; ++a) cv[a] = F::get(X, ps, pos(a));
+      for (int b = 0; b < nj; ++b) {
+        double sacc = 0.0;
+        for (int a = 0; a < nj; ++a) sacc += Uj[a * nj + b] * cv[a];
+        double e = rot + bR * lj[b];
+        if (rot_cut > 0.0) e = fmin(e, rot_cut);
+        tt[b] = sacc * e;
+      }
+      for (int a = 0; a < nj; ++a) {
+        double sacc = 0.0;
+        for (int b = 0; b < nj; ++b) sacc += Uj[a * nj + b] * tt[b];
+        F::put(X, ps, pos(a), sacc);
+      }
+    }
+  }
+  __syncthreads();
+  // back: H_c[o][n'][t] = sum_jj PcT[Omega][c][n'][jj] C[o][c][t][jj]
+  const int NTh = (ngh + 15) >> 4;
+  for (int it = w; it < n_om * NTh; it += 4) {
+    const int o = it / NTh, mt = it % NTh;
+    const int Om = om_lo + o;
+    const int nj0 = n_class(ng, Om, 0), nj1 = n_class(ng, Om, 1);
+    const int kb = round_up(nj0 > nj1 ? nj0 : nj1, M::KS);
+    typename M::acc_t acc[2][NT];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const E* Ab = PcT + (size_t)(Om * 2 + c) * tab + (size_t)mt * 16 * ngk;
+      const E* Bb = X + (o * 2 + c) * tile;
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) acc[c][nt] = M::zero();
+      for (int k0 = 0; k0 < kb; k0 += CH * M::KS) {
+        typename M::frag_t fa[CH];
+#pragma unroll
+        for (int q = 0; q < CH; ++q)
+          if (k0 + q * M::KS < kb) fa[q] = F::frag(Ab, ngk, psp, l, k0 + q * M::KS);
+#pragma unroll
+        for (int q = 0; q < CH; ++q)
+          if (k0 + q * M::KS < kb) {
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt)
+              M::mma(acc[c][nt], fa[q], F::frag(Bb + nt * 16 * ld, ld, ps, l, k0 + q * M::KS));
+          }
+      }
+    }
+    const size_t col = (size_t)(o * ne + le) * ng;
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+      const int i = i0 + nt * 16 + (l & 15);
+      if (i >= nr) continue;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int n = mt * 16 + M::row(l, v);
+        if (n >= ngh) continue;
+        const double h0 = (double)acc[0][nt][v] * M::kUnscale;
+        const double h1 = (double)acc[1][nt][v] * M::kUnscale;
+        const size_t ia = (col + n) * plane + (size_t)m * nr + i;
+        const size_t ib = (col + ng - 1 - n) * plane + (size_t)m * nr + i;
+        h[ia] = (typename HType<P>::T)((double)h[ia] + h0 + h1);
+        h[ib] = (typename HType<P>::T)((double)h[ib] + h0 - h1);
       }
     }
   }
 }
 
 // ---- T_R along R, potential, scaling, recursion, damping, norm partial ---------------
-// One workgroup per (r tile of 16*NTR, slab (omega, gamma)) of one packet, all elec.
-template <int P, int NTR>
+// One workgroup per (r tile of 16 columns, slab (omega, gamma)) of one packet, all
+// elec.  The raw FP64 tile X[elec][R][t] stays in LDS for the epilogue; per elec
+// the sum/difference operand (rows t, contraction over R) is built in compute
+// format, and each M-tile work item finishes rows a and n_R-1-a from its
+// accumulators.
+template <int P>
 __global__ __launch_bounds__(256) void k_radR_epi(
-    const double* __restrict__ uk, double* __restrict__ uprev,
-    const typename HType<P>::T* __restrict__ h, const double* __restrict__ Ts,
-    const double* __restrict__ Td, int nhk, const double* __restrict__ V,
+    const double* __restrict__ uk_all, double* __restrict__ uprev_all,
+    const typename HType<P>::T* __restrict__ h_all, const PkDesc* __restrict__ pks,
+    const int* __restrict__ blk_start, int n_pk, const typename Fmt<P>::E* __restrict__ Ts,
+    const typename Fmt<P>::E* __restrict__ Td, int ldt, int pst, const double* __restrict__ V,
     const double* __restrict__ D, int ne, int ng, int nR, int nr, double E0, double inv_dE,
-    int first, double* __restrict__ normpart) {
+    int first, double* __restrict__ normpart_row) {
   using M = Mma<P>;
-  constexpr int RT = 16 * NTR;
-  extern __shared__ double lds[];
+  using F = Fmt<P>;
+  using E = typename F::E;
+  constexpr int CH = Chunk<P>::CH;
+  constexpr int RT = 16;
+  extern __shared__ __align__(16) double lds[];
   __shared__ double red[4];
+  const int pk = find_packet(blk_start, n_pk, blockIdx.x);
+  const int local = blockIdx.x - blk_start[pk];
+  const PkDesc dsc = pks[pk];
+  const double* __restrict__ uk = uk_all + dsc.off;
+  double* __restrict__ uprev = uprev_all + dsc.off;
+  const typename HType<P>::T* __restrict__ h = h_all + dsc.off;
+  const int nrt = (nr + RT - 1) / RT;
   const int nh = nR >> 1;
   const int kp = round_up(nh, M::KS);
-  const int i0 = blockIdx.x * RT;
-  const int o = blockIdx.y / ng, n = blockIdx.y % ng;
+  const int ld = tile_ld<P>(kp);
+  const int ps = 2 * RT * ld;
+  const int i0 = (local % nrt) * RT;
+  const int slab = local / nrt;
+  const int o = slab / ng, n = slab % ng;
   const size_t plane = (size_t)nR * nr;
-  double* S = lds;                        // [l][kp][RT]
-  double* Dd = lds + (size_t)ne * kp * RT;  // [l][kp][RT]
-  for (int q = threadIdx.x; q < ne * kp * RT; q += blockDim.x) {
-    const int t = q % RT, b = (q / RT) % kp, le = q / (RT * kp);
-    const int i = i0 + t;
-    double a = 0.0, c = 0.0;
-    if (b < nh && i < nr) {
-      const double* base = uk + ((size_t)(o * ne + le) * ng + n) * plane + i;
-      a = base[(size_t)b * nr];
-      c = base[(size_t)(nR - 1 - b) * nr];
+  double* X = lds;                                             // [le][nR][RT]
+  E* SD = reinterpret_cast<E*>(lds + (size_t)ne * nR * RT);    // S^T [t][k], then D^T
+  {
+    const int tt = threadIdx.x & 15, r0 = threadIdx.x >> 4;
+    const int ii = i0 + tt;
+    for (int le = 0; le < ne; ++le) {
+      const double* src = uk + ((size_t)(o * ne + le) * ng + n) * plane + ii;
+      double* dst = X + (size_t)le * nR * RT + tt;
+      for (int mm = r0; mm < nR; mm += 16) dst[mm * RT] = (ii < nr) ? src[(size_t)mm * nr] : 0.0;
     }
-    S[q] = a + c;
-    Dd[q] = a - c;
   }
-  __syncthreads();
   const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int MT = (nh + 15) >> 4;
-  // Work items (elec, g in {sum, diff}, M-tile), NTR accumulators each, item it on
-  // wave it % 4.  Results stay in registers until every wave has read S and Dd.
-  const int n_items = ne * 2 * MT;
-  constexpr int RES = kRadRMaxAcc / NTR;
-  typename M::acc_t res[RES][NTR];
-#pragma unroll
-  for (int r = 0; r < RES; ++r) {
-    const int it = w + 4 * r;
-    if (it >= n_items) break;
-    const int mt = it % MT, g = (it / MT) & 1, le = it / (2 * MT);
-    const double* Ab = (g ? Td : Ts) + (size_t)(mt * 16) * nhk;
-    const double* Bb = (g ? Dd : S) + (size_t)le * kp * RT;
-    auto A = [&](int i, int k) { return Ab[(size_t)i * nhk + k]; };
-#pragma unroll
-    for (int nt = 0; nt < NTR; ++nt) res[r][nt] = M::zero();
-    for (int k0 = 0; k0 < kp; k0 += M::KS) {
-      const auto fa = M::load_a(A, k0, l);
-#pragma unroll
-      for (int nt = 0; nt < NTR; ++nt) {
-        auto B = [&](int k, int j) { return Bb[(size_t)k * RT + nt * 16 + j]; };
-        M::mma(res[r][nt], fa, M::load_b(B, k0, l));
+  const int t = l & 15;
+  const int i = i0 + t;
+  double nsum = 0.0;
+  for (int le = 0; le < ne; ++le) {
+    __syncthreads();
+    const double* Xl = X + (size_t)le * nR * RT;
+    {
+      const int tt = threadIdx.x & 15;
+      for (int k = threadIdx.x >> 4; k < kp; k += 16) {
+        double a = 0.0, b = 0.0;
+        if (k < nh) {
+          a = Xl[k * RT + tt];
+          b = Xl[(nR - 1 - k) * RT + tt];
+        }
+        F::put(SD, ps, tt * ld + k, a + b);
+        F::put(SD, ps, RT * ld + tt * ld + k, a - b);
       }
     }
-  }
-  __syncthreads();
+    __syncthreads();
+    for (int mt = w; mt < MT; mt += 4) {
+      const E* As = Ts + (size_t)mt * 16 * ldt;
+      const E* Ad = Td + (size_t)mt * 16 * ldt;
+      typename M::acc_t cs = M::zero(), cd = M::zero();
+      for (int k0 = 0; k0 < kp; k0 += CH * M::KS) {
+        typename M::frag_t fs[CH], fd[CH];
 #pragma unroll
-  for (int r = 0; r < RES; ++r) {
-    const int it = w + 4 * r;
-    if (it >= n_items) break;
-    const int mt = it % MT, g = (it / MT) & 1, le = it / (2 * MT);
-    double* Y = (g ? Dd : S) + (size_t)le * kp * RT;
+        for (int q = 0; q < CH; ++q)
+          if (k0 + q * M::KS < kp) {
+            fs[q] = F::frag(As, ldt, pst, l, k0 + q * M::KS);
+            fd[q] = F::frag(Ad, ldt, pst, l, k0 + q * M::KS);
+          }
 #pragma unroll
-    for (int nt = 0; nt < NTR; ++nt)
+        for (int q = 0; q < CH; ++q)
+          if (k0 + q * M::KS < kp) {
+            M::mma(cs, fs[q], F::frag(SD, ld, ps, l, k0 + q * M::KS));
+            M::mma(cd, fd[q], F::frag(SD + RT * ld, ld, ps, l, k0 + q * M::KS));
+          }
+      }
+      if (i >= nr) continue;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int a = mt * 16 + M::row(l, v);
-        if (a < kp) Y[(size_t)a * RT + nt * 16 + (l & 15)] = (double)res[r][nt][v] * M::kUnscale;
+        if (a >= nh) continue;
+        const double ys = (double)cs[v] * M::kUnscale, yd = (double)cd[v] * M::kUnscale;
+#pragma unroll
+        for (int side = 0; side < 2; ++side) {
+          const int mm = side ? nR - 1 - a : a;
+          const size_t pt = (size_t)n * plane + (size_t)mm * nr + i;
+          const size_t idx = (size_t)(o * ne + le) * ng * plane + pt;
+          const double ukv = Xl[mm * RT + t];
+          double sacc = (side ? ys - yd : ys + yd) + (double)h[idx];
+          for (int l2 = 0; l2 < ne; ++l2) {
+            const int a0 = le < l2 ? le : l2, a1 = le < l2 ? l2 : le;
+            const int pi = a0 * ne - a0 * (a0 - 1) / 2 + (a1 - a0);
+            sacc += V[(size_t)pi * ng * plane + pt] * X[((size_t)l2 * nR + mm) * RT + t];
+          }
+          const double wv = (sacc - E0 * ukv) * inv_dE;
+          const double dmp = D[(size_t)mm * nr + i];
+          const double un = first ? dmp * wv : dmp * (2.0 * wv - dmp * uprev[idx]);
+          uprev[idx] = un;
+          nsum += un * un;
+        }
       }
-  }
-  __syncthreads();
-  double nsum = 0.0;
-  for (int q = threadIdx.x; q < ne * nR * RT; q += blockDim.x) {
-    const int t = q % RT, mm = (q / RT) % nR, le = q / (RT * nR);
-    const int i = i0 + t;
-    if (i >= nr) continue;
-    const int a = mm < nh ? mm : nR - 1 - mm;
-    const double ys = S[((size_t)le * kp + a) * RT + t];
-    const double yd = Dd[((size_t)le * kp + a) * RT + t];
-    const size_t pt = (size_t)n * plane + (size_t)mm * nr + i;
-    const size_t idx = (size_t)(o * ne + le) * ng * plane + pt;
-    double s = (mm < nh ? ys + yd : ys - yd) + (double)h[idx];
-    const double ukv = uk[idx];
-    for (int l2 = 0; l2 < ne; ++l2) {
-      const int a0 = le < l2 ? le : l2, a1 = le < l2 ? l2 : le;
-      const int pi = a0 * ne - a0 * (a0 - 1) / 2 + (a1 - a0);
-      const double ul2 = (l2 == le) ? ukv : uk[(size_t)(o * ne + l2) * ng * plane + pt];
-      s += V[(size_t)pi * ng * plane + pt] * ul2;
     }
-    const double wv = (s - E0 * ukv) * inv_dE;
-    const double d = D[(size_t)mm * nr + i];
-    const double un = first ? d * wv : d * (2.0 * wv - d * uprev[idx]);
-    uprev[idx] = un;
-    nsum += un * un;
   }
   for (int off = 32; off > 0; off >>= 1) nsum += __shfl_down(nsum, off, 64);
   if (l == 0) red[w] = nsum;
   __syncthreads();
-  if (threadIdx.x == 0) normpart[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+  if (threadIdx.x == 0) normpart_row[dsc.wg_off + local] = red[0] + red[1] + red[2] + red[3];
+}
+
+// Converts an FP64 operator table to compute format (planes ps elements apart).
+template <int P>
+__global__ void k_to_format(const double* __restrict__ src, typename Fmt<P>::E* __restrict__ dst,
+                            size_t n, int ps) {
+  const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < n) Fmt<P>::put(dst, ps, (int)q, src[q]);
 }
 
 // ---- energy accumulation: acc[c e][s] += sum_b coef[c e][b] ring[b][s] ----------------
 // M = 2 n_E rows (real and imaginary parts), K = buffered steps, N = slice values.
 // One workgroup per 32 slice values; wave w owns M-tiles w, w+4, ...
 constexpr int kAccMaxMT = 8;   // M-tiles per wave (2 n_E <= 512)
-__global__ __launch_bounds__(256) void k_accum_mfma(double* __restrict__ acc,
-                                                    const double* __restrict__ coef, int ldc,
-                                                    const double* __restrict__ ring,
-                                                    size_t ring_stride, int n_slice, int rows,
-                                                    int count) {
+struct AccDesc {
+  unsigned long acc_off;    // accumulators of the packet [2 n_E][n_slice]
+  unsigned long slice_off;  // the packet's slice values in a ring row
+  int n_slice;
+};
+
+__global__ __launch_bounds__(256) void k_accum_mfma(double* __restrict__ acc_all,
+                                                    const double* __restrict__ coef_all, int ldc,
+                                                    const double* __restrict__ ring_all,
+                                                    size_t ring_stride,
+                                                    const AccDesc* __restrict__ ads,
+                                                    const int* __restrict__ blk_start, int n_pk,
+                                                    int rows, int count) {
   using M = Mma<kP64>;
   const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int s0 = blockIdx.x * 32;
+  const int pk = find_packet(blk_start, n_pk, blockIdx.x);
+  const AccDesc ad = ads[pk];
+  double* __restrict__ acc = acc_all + ad.acc_off;
+  const double* __restrict__ coef = coef_all + (size_t)pk * rows * ldc;
+  const double* __restrict__ ring = ring_all + ad.slice_off;
+  const int n_slice = ad.n_slice;
+  const int s0 = (blockIdx.x - blk_start[pk]) * 32;
   const int MT = (rows + 15) >> 4;
   M::acc_t c[kAccMaxMT][2];
 #pragma unroll

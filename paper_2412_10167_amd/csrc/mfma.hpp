@@ -124,6 +124,63 @@ template <> struct Mma<kPF16> {
   }
 };
 
+
+// Compute-format storage of contraction operands, in LDS and for the operator
+// tables: FP64, FP32, or hi/lo planes of bf16 / fp16 (plane stride ps elements).
+// Tiles are "k-contiguous": element (row r, contraction index k) at r*ld + k, for
+// the A operand (rows = output rows) and for the B operand stored transposed
+// (rows = output columns).  Split formats need ld and ps multiples of 8.
+template <int P> struct Fmt;
+
+template <> struct Fmt<kP64> {
+  using E = double;
+  using M = Mma<kP64>;
+  static constexpr int PLANES = 1, PAD = 1;
+  __device__ static M::frag_t frag(const E* t, int ld, int ps, int l, int k0) {
+    (void)ps;
+    return t[(l & 15) * ld + k0 + (l >> 4)];
+  }
+  __device__ static void put(E* t, int ps, int idx, double x) { (void)ps; t[idx] = x; }
+  __device__ static double get(const E* t, int ps, int idx) { (void)ps; return t[idx]; }
+};
+
+template <> struct Fmt<kP32> {
+  using E = float;
+  using M = Mma<kP32>;
+  static constexpr int PLANES = 1, PAD = 1;
+  __device__ static M::frag_t frag(const E* t, int ld, int ps, int l, int k0) {
+    (void)ps;
+    return t[(l & 15) * ld + k0 + (l >> 4)];
+  }
+  __device__ static void put(E* t, int ps, int idx, double x) { (void)ps; t[idx] = (float)x; }
+  __device__ static double get(const E* t, int ps, int idx) { (void)ps; return (double)t[idx]; }
+};
+
+template <class S, class V, int PR> struct SplitFmt {
+  using E = S;
+  using M = Mma<PR>;
+  static constexpr int PLANES = 2, PAD = 8;
+  static constexpr float kScale = PR == kPF16 ? 1024.0f : 1.0f;
+  __device__ static typename M::frag_t frag(const E* t, int ld, int ps, int l, int k0) {
+    const int off = (l & 15) * ld + k0 + 8 * (l >> 4);
+    typename M::frag_t f;
+    f.hi = *reinterpret_cast<const V*>(t + off);
+    f.lo = *reinterpret_cast<const V*>(t + ps + off);
+    return f;
+  }
+  __device__ static void put(E* t, int ps, int idx, double x) {
+    const float v = (float)x * kScale;
+    const E h = (E)v;
+    t[idx] = h;
+    t[ps + idx] = (E)(v - (float)h);
+  }
+  __device__ static double get(const E* t, int ps, int idx) {
+    return ((double)(float)t[idx] + (double)(float)t[ps + idx]) / (double)kScale;
+  }
+};
+template <> struct Fmt<kPBF> : SplitFmt<__bf16, v8bf, kPBF> {};
+template <> struct Fmt<kPF16> : SplitFmt<_Float16, v8h, kPF16> {};
+
 // Per-precision element type of the H u partial sums kept in HBM between passes.
 template <int P> struct HType { using T = float; };
 template <> struct HType<kP64> { using T = double; };

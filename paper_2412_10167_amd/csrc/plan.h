@@ -76,6 +76,7 @@ struct tdwp_plan_s {
   bool fast = false;
   bool fast_accum = false;
   int ntr = 1;               // 16-column tiles per k_radR_epi workgroup
+  int nta = 1;               // 16-column tiles per k_ang workgroup
   int nrhk = 0, nRhk = 0, ngk = 0;
   size_t lds_radr = 0, lds_ang = 0, lds_radR = 0;
   std::vector<double> Trs, Trd, TRs, TRd, Pc;
@@ -84,10 +85,19 @@ struct tdwp_plan_s {
   double* d_TRs = nullptr;
   double* d_TRd = nullptr;
   double* d_Pc = nullptr;
+  std::vector<double> PcT;
+  // operator tables in the compute format of the plan's precision
+  void* d_TrsF = nullptr;
+  void* d_TrdF = nullptr;
+  void* d_TRsF = nullptr;
+  void* d_TRdF = nullptr;
+  void* d_PcF = nullptr;
+  void* d_PcTF = nullptr;
   // propagation state
   long k = 0;
   int cur = 0;               // u_k lives in d_u[cur], u_{k-1} in d_u[1 - cur]
   int ring_count = 0;
+  long rec_k = -1;           // highest Chebyshev index whose slices are recorded
   int ring_len = tdwp::kRing;
   long ring_k0 = 0;
   // device
@@ -103,6 +113,7 @@ struct tdwp_plan_s {
   double* d_Br = nullptr;
   double* d_BR = nullptr;
   double* d_arow = nullptr;
+  double* d_flux_split = nullptr;   // a_s, a_d, d_s, d_d (n_r/2 each)
   double* d_drow = nullptr;
   double* d_ring = nullptr;
   double* d_acc = nullptr;
@@ -115,6 +126,17 @@ struct tdwp_plan_s {
   double* d_out = nullptr;        // staging for analysis outputs
   size_t out_cap = 0;
   double* d_g = nullptr;          // [n_packets][n_R]
+  // batched-launch index maps (one launch per pass covers every packet)
+  void* d_pkdesc = nullptr;       // PkDesc[n_packets]
+  int* d_blk_ang = nullptr;       // block prefix sums per packet, k_ang
+  int* d_blk_radR = nullptr;      // block prefix sums per packet, k_radR_epi
+  void* d_accdesc = nullptr;      // AccDesc[n_packets]
+  int* d_blk_acc = nullptr;       // block prefix sums per packet, k_accum_mfma
+  long* d_line_start = nullptr;   // first r-line of each packet (n_packets + 1)
+  unsigned long* d_slice_off = nullptr;
+  double* d_E = nullptr;          // E_v0j0 per packet
+  int blocks_ang = 0, blocks_radR = 0, blocks_acc = 0;
+  size_t lds_ang_max = 0;
   size_t* d_wg_off = nullptr;     // per packet: first norm partial
   int* d_n_wg = nullptr;          // per packet: number of norm partials
   std::vector<void*> allocations;

@@ -160,12 +160,26 @@ __global__ void k_radial_epi(const double* __restrict__ uk, double* __restrict__
 
 // Flux line (a . u, d . u along r for every (omega, elec, gamma, R)) and the
 // R_inf line of one packet into its slot of a ring row.  One wavefront per line.
-__global__ void k_slices(const double* __restrict__ u, int nlines, int nR, int nr, int m_inf,
-                         const double* __restrict__ arow, const double* __restrict__ drow,
-                         double inv_sqrt_dR, double* __restrict__ out) {
-  const int line = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+// Lines of every packet are contiguous (line_start[p] .. line_start[p+1]);
+// slice_off[p] places the packet's values in the ring row.
+__global__ void k_slices(const double* __restrict__ u_all, const long* __restrict__ line_start,
+                         const unsigned long* __restrict__ slice_off, int n_pk, int nR, int nr,
+                         int m_inf, const double* __restrict__ arow,
+                         const double* __restrict__ drow, double inv_sqrt_dR,
+                         double* __restrict__ ring_row) {
+  const long gline = ((long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int lane = threadIdx.x & 63;
-  if (line >= nlines) return;
+  if (gline >= line_start[n_pk]) return;
+  int lo = 0, hi = n_pk - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (line_start[mid] <= gline) lo = mid;
+    else hi = mid - 1;
+  }
+  const int nlines = (int)(line_start[lo + 1] - line_start[lo]);
+  const int line = (int)(gline - line_start[lo]);
+  const double* u = u_all + (size_t)line_start[lo] * nr;
+  double* out = ring_row + slice_off[lo];
   const double* p = u + (size_t)line * nr;
   double sv = 0.0, sd = 0.0;
   for (int i = lane; i < nr; i += 64) {
@@ -188,12 +202,16 @@ __global__ void k_slices(const double* __restrict__ u, int nlines, int nR, int n
 // Chebyshev energy coefficients c_k(E) = (2 - delta_k0) e^{-ik theta}/(dE sin theta),
 // theta = arccos((E_col + E_v0j0 - E0)/dE), for k = k0 .. k0 + count - 1.
 // coef layout [2][n_E][kRing] (real, imaginary).
-__global__ void k_coef(double* __restrict__ coef, int ldc, int nE, double ecol_min,
-                       double ecol_step, double E_v0j0, double E0, double dE, long k0, int count) {
+// One launch for every packet: coef[p][2][n_E][ldc] with the packet's E_v0j0.
+__global__ void k_coef(double* __restrict__ coef_all, int ldc, int nE, double ecol_min,
+                       double ecol_step, const double* __restrict__ E_v0j0, int n_pk, double E0,
+                       double dE, long k0, int count) {
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= nE * count) return;
-  const int e = q / count, b = q % count;
-  const double Es = (ecol_min + e * ecol_step + E_v0j0 - E0) / dE;
+  if (q >= nE * count * n_pk) return;
+  const int p = q / (nE * count);
+  const int e = (q / count) % nE, b = q % count;
+  double* coef = coef_all + (size_t)p * 2 * nE * ldc;
+  const double Es = (ecol_min + e * ecol_step + E_v0j0[p] - E0) / dE;
   const double th = acos(Es);
   const long kk = k0 + b;
   const double f = (kk == 0 ? 1.0 : 2.0) / (dE * sin(th));

@@ -221,31 +221,79 @@ int build_tables(Plan* P) {
           for (int n = 0; n < ngh; ++n)
             P->Pc[(((size_t)om * 2 + c) * ngk + jj) * ngk + n] =
                 P->Ptab[((size_t)om * P->ng + om + c + 2 * jj) * P->ng + n];
+    P->PcT.assign(P->Pc.size(), 0.0);
+    for (size_t b = 0; b < (size_t)(P->max_om + 1) * 2; ++b)
+      for (int x = 0; x < ngk; ++x)
+        for (int y = 0; y < ngk; ++y)
+          P->PcT[(b * ngk + y) * ngk + x] = P->Pc[(b * ngk + x) * ngk + y];
   }
   return TDWP_OK;
 }
 
 size_t ks_of(int prec) { return (prec == TDWP_BF16X3 || prec == TDWP_FP16X3) ? 32 : 4; }
 
-// Decides whether the matrix-core kernels apply and sizes their LDS.
+size_t elem_bytes(int prec) {
+  return prec == TDWP_FP64 ? 8 : (prec == TDWP_FP32 ? 4 : 2);
+}
+int planes_of(int prec) { return (prec == TDWP_BF16X3 || prec == TDWP_FP16X3) ? 2 : 1; }
+int ld_of(int prec, int kp) { return kp + ((prec == TDWP_BF16X3 || prec == TDWP_FP16X3) ? 8 : 1); }
+
+// Decides whether the matrix-core kernels apply and sizes their tiles and LDS.
 void choose_fast_path(Plan* P) {
   P->fast = false;
   if (P->nr % 2 || P->nR % 2 || P->ng % 2) return;
-  const size_t ks = ks_of(P->cfg.precision);
-  const size_t kpr = round_up(P->nr / 2, (int)ks), kpR = round_up(P->nR / 2, (int)ks);
-  const size_t kpa = round_up(P->ng / 2, (int)ks);
+  const int prec = P->cfg.precision;
+  const int ks = (int)ks_of(prec);
+  const size_t eb = elem_bytes(prec) * planes_of(prec);
+  const int kpr = round_up(P->nr / 2, ks), kpR = round_up(P->nR / 2, ks);
+  const int kpa = round_up(P->ng / 2, ks);
+  const size_t soft = std::min<size_t>(80 * 1024, kLdsMax);   // two workgroups per CU
   int max_om = 0;
   for (auto& U : P->units) max_om = std::max(max_om, U.n_om);
-  P->lds_radr = (size_t)2 * kRadrLines * (kpr + 1) * sizeof(double);
-  P->lds_ang = ((size_t)2 * max_om * kpa * 16 + (size_t)max_om * P->ng * 16) * sizeof(double);
-  const int MT = (P->nR / 2 + 15) / 16;
-  const int per_wave = (P->ne * 2 * MT + 3) / 4;
-  P->ntr = (P->ne == 1 && per_wave * 2 <= kRadRMaxAcc && P->nr >= 32) ? 2 : 1;
-  if (per_wave * P->ntr > kRadRMaxAcc) return;
-  P->lds_radR = (size_t)2 * P->ne * kpR * 16 * P->ntr * sizeof(double);
-  if ((P->nr / 2 + 15) / 16 > 32) return;
+  P->lds_radr = (size_t)2 * kRadrLines * ld_of(prec, kpr) * eb;
+  const int mt_per = (kpa + 15) / 16;
+  const int per_wave = (max_om * 2 * mt_per + 3) / 4;
+  size_t ang_tab = 0;
+  for (auto& U : P->units) ang_tab = std::max(ang_tab, (U.ang_U.size() + U.ang_ell.size()) * sizeof(double));
+  P->nta = 0;
+  for (int nt : {4, 2, 1}) {
+    const size_t lds = ((size_t)max_om * 2 * 16 * nt * ld_of(prec, kpa) * eb + 15) / 16 * 16 + ang_tab;
+    if (per_wave * nt > kAngMaxAcc) continue;
+    if (lds <= soft || (nt == 1 && lds <= kLdsMax)) {
+      P->nta = nt;
+      P->lds_ang = lds;
+      break;
+    }
+  }
+  if (P->nta == 0) return;
+  P->ntr = 1;
+  P->lds_radR = (size_t)P->ne * P->nR * 16 * sizeof(double) + (size_t)2 * 16 * ld_of(prec, kpR) * eb;
   if (P->lds_radr > kLdsMax || P->lds_ang > kLdsMax || P->lds_radR > kLdsMax) return;
   P->fast = true;
+}
+
+template <int PR>
+int upload_formatted(Plan* P, void** dst, const std::vector<double>& src) {
+  using E = typename Fmt<PR>::E;
+  double* tmp = nullptr;
+  TRY(alloc_copy(P, &tmp, src));
+  TRY(dev_alloc(P, dst, src.size() * Fmt<PR>::PLANES * sizeof(E)));
+  hipLaunchKernelGGL(k_to_format<PR>, dim3((unsigned)((src.size() + 255) / 256)), dim3(256), 0,
+                     P->stream, tmp, (E*)*dst, src.size(), (int)src.size());
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(P->stream));
+  return TDWP_OK;
+}
+
+template <int PR>
+int upload_tables(Plan* P) {
+  TRY(upload_formatted<PR>(P, &P->d_TrsF, P->Trs));
+  TRY(upload_formatted<PR>(P, &P->d_TrdF, P->Trd));
+  TRY(upload_formatted<PR>(P, &P->d_TRsF, P->TRs));
+  TRY(upload_formatted<PR>(P, &P->d_TRdF, P->TRd));
+  TRY(upload_formatted<PR>(P, &P->d_PcF, P->Pc));
+  TRY(upload_formatted<PR>(P, &P->d_PcTF, P->PcT));
+  return TDWP_OK;
 }
 
 // Raises the dynamic-LDS limit of the matrix-core kernels above the 64 KB
@@ -254,8 +302,10 @@ void choose_fast_path(Plan* P) {
 template <int PR>
 void set_lds_limits() {
   if (kLdsMax <= 64 * 1024) return;
-  const void* fns[4] = {(const void*)k_radr<PR>, (const void*)k_ang<PR>,
-                        (const void*)k_radR_epi<PR, 1>, (const void*)k_radR_epi<PR, 2>};
+  const void* fns[8] = {(const void*)k_radr<PR>, (const void*)k_ang<PR, 1, 1>,
+                        (const void*)k_ang<PR, 2, 1>, (const void*)k_ang<PR, 4, 1>,
+                        (const void*)k_ang<PR, 1, kMaxOmega>, (const void*)k_ang<PR, 2, kMaxOmega>,
+                        (const void*)k_ang<PR, 4, kMaxOmega>, (const void*)k_radR_epi<PR>};
   for (const void* f : fns) {
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsMax);
     if (e != hipSuccess) {
@@ -362,16 +412,27 @@ int layout_and_allocate(Plan* P) {
   TRY(dev_alloc(P, (void**)&P->d_snap, P->snap_total * sizeof(double)));
   TRY(dev_alloc(P, (void**)&P->d_coef, P->packets.size() * 2 * nE * P->ring_len * sizeof(double)));
   if (P->fast) {
+    {
+      const int h2 = nr / 2;
+      std::vector<double> fs((size_t)4 * h2);
+      for (int k = 0; k < h2; ++k) {
+        fs[k] = 0.5 * (P->arow[k] + P->arow[nr - 1 - k]);
+        fs[h2 + k] = 0.5 * (P->arow[k] - P->arow[nr - 1 - k]);
+        fs[2 * h2 + k] = 0.5 * (P->drow[k] + P->drow[nr - 1 - k]);
+        fs[3 * h2 + k] = 0.5 * (P->drow[k] - P->drow[nr - 1 - k]);
+      }
+      TRY(alloc_copy(P, &P->d_flux_split, fs));
+    }
     TRY(alloc_copy(P, &P->d_Trs, P->Trs));
     TRY(alloc_copy(P, &P->d_Trd, P->Trd));
     TRY(alloc_copy(P, &P->d_TRs, P->TRs));
     TRY(alloc_copy(P, &P->d_TRd, P->TRd));
     TRY(alloc_copy(P, &P->d_Pc, P->Pc));
     switch (P->cfg.precision) {
-      case TDWP_FP64: set_lds_limits<kP64>(); break;
-      case TDWP_FP32: set_lds_limits<kP32>(); break;
-      case TDWP_BF16X3: set_lds_limits<kPBF>(); break;
-      default: set_lds_limits<kPF16>(); break;
+      case TDWP_FP64: set_lds_limits<kP64>(); TRY(upload_tables<kP64>(P)); break;
+      case TDWP_FP32: set_lds_limits<kP32>(); TRY(upload_tables<kP32>(P)); break;
+      case TDWP_BF16X3: set_lds_limits<kPBF>(); TRY(upload_tables<kPBF>(P)); break;
+      default: set_lds_limits<kPF16>(); TRY(upload_tables<kPF16>(P)); break;
     }
   }
   TRY(dev_alloc(P, (void**)&P->d_normpart, (size_t)kNormChunk * P->n_wg_total * sizeof(double)));
@@ -385,6 +446,46 @@ int layout_and_allocate(Plan* P) {
   }
   TRY(alloc_copy(P, &P->d_wg_off, wg_off));
   TRY(alloc_copy(P, &P->d_n_wg, n_wg));
+  // batched-launch index maps
+  std::vector<long> line_start(1, 0);
+  std::vector<unsigned long> slice_off;
+  std::vector<int> blk_acc(1, 0);
+  std::vector<AccDesc> ad;
+  for (auto& pk : P->packets) {
+    line_start.push_back(line_start.back() + pk.n_sv);
+    slice_off.push_back(pk.slice_off);
+    blk_acc.push_back(blk_acc.back() + (pk.n_slice + 31) / 32);
+    ad.push_back(AccDesc{pk.acc_off, pk.slice_off, pk.n_slice});
+  }
+  P->blocks_acc = blk_acc.back();
+  TRY(alloc_copy(P, &P->d_line_start, line_start));
+  TRY(alloc_copy(P, &P->d_slice_off, slice_off));
+  TRY(alloc_copy(P, &P->d_blk_acc, blk_acc));
+  AccDesc* dad = nullptr;
+  TRY(alloc_copy(P, &dad, ad));
+  P->d_accdesc = dad;
+  TRY(dev_alloc(P, (void**)&P->d_E, P->packets.size() * sizeof(double)));
+  if (P->fast) {
+    std::vector<PkDesc> pd;
+    std::vector<int> ba(1, 0), br(1, 0);
+    const int nrt_a = (nr + 16 * P->nta - 1) / (16 * P->nta);
+    const int nrt_r = (nr + 16 * P->ntr - 1) / (16 * P->ntr);
+    P->lds_ang_max = P->lds_ang;
+    for (auto& pk : P->packets) {
+      const UnitInfo& U = P->units[pk.unit];
+      pd.push_back(PkDesc{pk.off, pk.wg_off, U.n_om, U.om_lo, U.d_U, U.d_ell, U.d_ang_off,
+                          U.d_ell_off, U.d_n_om_j, (int)U.ang_U.size(), (int)U.ang_ell.size()});
+      ba.push_back(ba.back() + nrt_a * nR * ne);
+      br.push_back(br.back() + nrt_r * U.n_om * ng);
+    }
+    P->blocks_ang = ba.back();
+    P->blocks_radR = br.back();
+    PkDesc* dpd = nullptr;
+    TRY(alloc_copy(P, &dpd, pd));
+    P->d_pkdesc = dpd;
+    TRY(alloc_copy(P, &P->d_blk_ang, ba));
+    TRY(alloc_copy(P, &P->d_blk_radR, br));
+  }
   return TDWP_OK;
 }
 
@@ -422,14 +523,12 @@ int timed_end(Plan* P, Timing* T, int kind) {
 }
 
 int record_slices(Plan* P, int row) {
-  const double* u = P->d_u[P->cur];
-  for (auto& pk : P->packets) {
-    const int nlines = pk.n_sv;
-    const int blocks = (nlines * 64 + 255) / 256;
-    hipLaunchKernelGGL(k_slices, dim3(blocks), dim3(256), 0, P->stream, u + pk.off, nlines, P->nR,
-                       P->nr, P->m_inf, P->d_arow, P->d_drow, 1.0 / std::sqrt(P->dR),
-                       P->d_ring + (size_t)row * P->slice_total + pk.slice_off);
-  }
+  const long nlines = (long)(P->n_total / P->nr);
+  const long threads = nlines * 64;
+  hipLaunchKernelGGL(k_slices, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, P->stream,
+                     P->d_u[P->cur], P->d_line_start, P->d_slice_off, (int)P->packets.size(),
+                     P->nR, P->nr, P->m_inf, P->d_arow, P->d_drow, 1.0 / std::sqrt(P->dR),
+                     P->d_ring + (size_t)row * P->slice_total);
   HIP_TRY(hipGetLastError());
   return TDWP_OK;
 }
@@ -439,23 +538,23 @@ int flush_ring(Plan* P) {
   const tdwp_config& c = P->cfg;
   const int nE = c.n_energy;
   const double step = (c.ecol_max - c.ecol_min) / (nE - 1);
-  for (size_t ip = 0; ip < P->packets.size(); ++ip) {
-    auto& pk = P->packets[ip];
-    double* coef = P->d_coef + ip * 2 * nE * P->ring_len;
-    const int nq = nE * P->ring_count;
-    hipLaunchKernelGGL(k_coef, dim3((nq + 255) / 256), dim3(256), 0, P->stream, coef,
-                       P->ring_len, nE, c.ecol_min, step, pk.pk.E_v0j0, P->E0, P->dE,
-                       P->ring_k0, P->ring_count);
-    if (P->fast_accum) {
-      hipLaunchKernelGGL(k_accum_mfma, dim3((pk.n_slice + 31) / 32), dim3(256), 0, P->stream,
-                         P->d_acc + pk.acc_off, coef, P->ring_len, P->d_ring + pk.slice_off,
-                         P->slice_total, pk.n_slice, 2 * nE, P->ring_count);
-    } else {
+  const int np = (int)P->packets.size();
+  const int nq = nE * P->ring_count * np;
+  hipLaunchKernelGGL(k_coef, dim3((nq + 255) / 256), dim3(256), 0, P->stream, P->d_coef,
+                     P->ring_len, nE, c.ecol_min, step, P->d_E, np, P->E0, P->dE, P->ring_k0,
+                     P->ring_count);
+  if (P->fast_accum) {
+    hipLaunchKernelGGL(k_accum_mfma, dim3(P->blocks_acc), dim3(256), 0, P->stream, P->d_acc,
+                       P->d_coef, P->ring_len, P->d_ring, P->slice_total,
+                       (const AccDesc*)P->d_accdesc, P->d_blk_acc, np, 2 * nE, P->ring_count);
+  } else {
+    for (size_t ip = 0; ip < P->packets.size(); ++ip) {
+      auto& pk = P->packets[ip];
       const int epb = 8;
       dim3 grid((pk.n_slice + 255) / 256, (nE + epb - 1) / epb);
       hipLaunchKernelGGL(k_accumulate, grid, dim3(256), 0, P->stream, P->d_acc + pk.acc_off,
-                         coef, P->d_ring + pk.slice_off, P->slice_total, pk.n_slice, nE, epb,
-                         P->ring_count);
+                         P->d_coef + ip * 2 * nE * P->ring_len, P->d_ring + pk.slice_off,
+                         P->slice_total, pk.n_slice, nE, epb, P->ring_count);
     }
   }
   HIP_TRY(hipGetLastError());
@@ -478,50 +577,80 @@ int take_snapshots(Plan* P) {
   return TDWP_OK;
 }
 
+// Before slices of the current k are recorded: flush a full ring, and flush
+// then snapshot where an elastic-channel window opens at this k.
+int prepare_record(Plan* P, Timing* T) {
+  bool opens = false;
+  for (auto& pk : P->packets)
+    if (!pk.snap_taken && pk.pk.k_min_elastic == P->k) opens = true;
+  if (P->ring_count == P->ring_len || opens) {
+    TRY(timed_begin(P, T));
+    TRY(flush_ring(P));
+    TRY(take_snapshots(P));
+    TRY(timed_end(P, T, 3));
+  }
+  return TDWP_OK;
+}
+
 template <int PR>
 int fast_step(Plan* P, int chunk_row, Timing* T) {
   using HT = typename HType<PR>::T;
+  using E = typename Fmt<PR>::E;
   const int first = (P->k == 0) ? 1 : 0;
   const double* uk = P->d_u[P->cur];
   double* uo = P->d_u[1 - P->cur];
   HT* h = reinterpret_cast<HT*>(P->d_h);
   const int nr = P->nr, nR = P->nR, ng = P->ng, ne = P->ne;
+  const int np = (int)P->packets.size();
+  const PkDesc* pkd = (const PkDesc*)P->d_pkdesc;
+  const bool rec = P->rec_k < P->k;
+  if (rec) TRY(prepare_record(P, T));
   TRY(timed_begin(P, T));
-  for (auto& pk : P->packets) {
-    const long nlines = (long)(pk.n_values / nr);
+  {
+    const long nlines = (long)(P->n_total / nr);
+    const int h2 = nr / 2;
+    SliceArgs sa{rec ? 1 : 0, 0, P->d_line_start, P->d_slice_off, np, nR, P->m_inf,
+                 P->d_flux_split, P->d_flux_split + h2, P->d_flux_split + 2 * h2,
+                 P->d_flux_split + 3 * h2, 1.0 / std::sqrt(P->dR),
+                 P->d_ring + (size_t)P->ring_count * P->slice_total};
     hipLaunchKernelGGL(k_radr<PR>, dim3((unsigned)((nlines + kRadrLines - 1) / kRadrLines)),
-                       dim3(256), P->lds_radr, P->stream, uk + pk.off, h + pk.off, P->d_Trs,
-                       P->d_Trd, nr, P->nrhk, nlines);
+                       dim3(256), P->lds_radr, P->stream, uk, h, (const E*)P->d_TrsF,
+                       (const E*)P->d_TrdF, P->nrhk, P->nrhk * P->nrhk, nr, nlines, sa);
   }
   HIP_TRY(hipGetLastError());
   TRY(timed_end(P, T, 4));
+  if (rec) {
+    P->ring_count += 1;
+    P->rec_k = P->k;
+  }
   TRY(timed_begin(P, T));
-  for (auto& pk : P->packets) {
-    const UnitInfo& U = P->units[pk.unit];
-    const size_t lds = ((size_t)2 * U.n_om * round_up(ng / 2, (int)ks_of(P->cfg.precision)) * 16 +
-                        (size_t)U.n_om * ng * 16) * sizeof(double);
-    hipLaunchKernelGGL(k_ang<PR>, dim3((nr + 15) / 16, nR, ne), dim3(256), lds, P->stream,
-                       uk + pk.off, h + pk.off, U.n_om, U.om_lo, ne, ng, nR, nr, P->d_Pc, P->ngk,
-                       U.d_U, U.d_ell, U.d_ang_off, U.d_ell_off, U.d_n_om_j, P->d_Br, P->d_BR,
-                       P->cfg.rot_cut);
+  {
+    const int psp = (int)P->Pc.size();
+    auto launch = [&](auto kern) {
+      hipLaunchKernelGGL(kern, dim3(P->blocks_ang), dim3(256), P->lds_ang_max, P->stream, uk, h,
+                         pkd, P->d_blk_ang, np, ne, ng, nR, nr, (const E*)P->d_PcF,
+                         (const E*)P->d_PcTF, P->ngk, psp, P->d_Br, P->d_BR, P->cfg.rot_cut);
+    };
+    int max_om = 0;
+    for (auto& U : P->units) max_om = std::max(max_om, U.n_om);
+    if (max_om == 1) {
+      if (P->nta == 4) launch(k_ang<PR, 4, 1>);
+      else if (P->nta == 2) launch(k_ang<PR, 2, 1>);
+      else launch(k_ang<PR, 1, 1>);
+    } else {
+      if (P->nta == 4) launch(k_ang<PR, 4, kMaxOmega>);
+      else if (P->nta == 2) launch(k_ang<PR, 2, kMaxOmega>);
+      else launch(k_ang<PR, 1, kMaxOmega>);
+    }
   }
   HIP_TRY(hipGetLastError());
   TRY(timed_end(P, T, 0));
   TRY(timed_begin(P, T));
-  const int rt = 16 * P->ntr;
-  for (auto& pk : P->packets) {
-    const UnitInfo& U = P->units[pk.unit];
-    dim3 grid((nr + rt - 1) / rt, U.n_om * ng);
-    double* np = P->d_normpart + (size_t)chunk_row * P->n_wg_total + pk.wg_off;
-    if (P->ntr == 2)
-      hipLaunchKernelGGL((k_radR_epi<PR, 2>), grid, dim3(256), P->lds_radR, P->stream,
-                         uk + pk.off, uo + pk.off, h + pk.off, P->d_TRs, P->d_TRd, P->nRhk,
-                         P->d_V, P->d_D, ne, ng, nR, nr, P->E0, 1.0 / P->dE, first, np);
-    else
-      hipLaunchKernelGGL((k_radR_epi<PR, 1>), grid, dim3(256), P->lds_radR, P->stream,
-                         uk + pk.off, uo + pk.off, h + pk.off, P->d_TRs, P->d_TRd, P->nRhk,
-                         P->d_V, P->d_D, ne, ng, nR, nr, P->E0, 1.0 / P->dE, first, np);
-  }
+  double* nrow = P->d_normpart + (size_t)chunk_row * P->n_wg_total;
+  hipLaunchKernelGGL(k_radR_epi<PR>, dim3(P->blocks_radR), dim3(256), P->lds_radR, P->stream, uk,
+                     uo, h, pkd, P->d_blk_radR, np, (const E*)P->d_TRsF, (const E*)P->d_TRdF,
+                     P->nRhk, P->nRhk * P->nRhk, P->d_V, P->d_D, ne, ng, nR, nr, P->E0,
+                     1.0 / P->dE, first, nrow);
   HIP_TRY(hipGetLastError());
   TRY(timed_end(P, T, 1));
   return TDWP_OK;
@@ -570,23 +699,56 @@ int one_step(Plan* P, int chunk_row, Timing* T) {
   return after_step(P, T);
 }
 
-// Swaps the packet buffers and records the slices of the new u_k.
+// Swaps the packet buffers; the general path records the slices of the new u_k
+// here, the matrix-core path inside the next step's k_radr (or finish_slices).
 int after_step(Plan* P, Timing* T) {
   P->cur = 1 - P->cur;
   P->k += 1;
-  // slices of u_k (new k): flush first if the ring is full or an elastic window opens
-  bool opens = false;
-  for (auto& pk : P->packets)
-    if (!pk.snap_taken && pk.pk.k_min_elastic == P->k) opens = true;
-  if (P->ring_count == P->ring_len || opens) {
-    TRY(timed_begin(P, T));
-    TRY(flush_ring(P));
-    TRY(take_snapshots(P));
-    TRY(timed_end(P, T, 3));
-  }
+  if (P->fast) return TDWP_OK;
+  TRY(prepare_record(P, T));
   TRY(timed_begin(P, T));
   TRY(record_slices(P, P->ring_count));
   P->ring_count += 1;
+  P->rec_k = P->k;
+  TRY(timed_end(P, T, 2));
+  return TDWP_OK;
+}
+
+// Slices of u_k through k_radr's recording path (same arithmetic as in a step).
+template <int PR>
+int record_via_radr(Plan* P) {
+  using E = typename Fmt<PR>::E;
+  const int nr = P->nr, h2 = nr / 2;
+  const long nlines = (long)(P->n_total / nr);
+  SliceArgs sa{1, 1, P->d_line_start, P->d_slice_off, (int)P->packets.size(), P->nR, P->m_inf,
+               P->d_flux_split, P->d_flux_split + h2, P->d_flux_split + 2 * h2,
+               P->d_flux_split + 3 * h2, 1.0 / std::sqrt(P->dR),
+               P->d_ring + (size_t)P->ring_count * P->slice_total};
+  hipLaunchKernelGGL(k_radr<PR>, dim3((unsigned)((nlines + kRadrLines - 1) / kRadrLines)),
+                     dim3(256), P->lds_radr, P->stream, P->d_u[P->cur],
+                     reinterpret_cast<typename HType<PR>::T*>(P->d_h), (const E*)P->d_TrsF,
+                     (const E*)P->d_TrdF, P->nrhk, P->nrhk * P->nrhk, nr, nlines, sa);
+  HIP_TRY(hipGetLastError());
+  return TDWP_OK;
+}
+
+// Records the slices of the current u_k if that has not happened yet.
+int finish_slices(Plan* P, Timing* T) {
+  if (P->rec_k >= P->k) return TDWP_OK;
+  TRY(prepare_record(P, T));
+  TRY(timed_begin(P, T));
+  if (P->fast) {
+    switch (P->cfg.precision) {
+      case TDWP_FP64: TRY(record_via_radr<kP64>(P)); break;
+      case TDWP_FP32: TRY(record_via_radr<kP32>(P)); break;
+      case TDWP_BF16X3: TRY(record_via_radr<kPBF>(P)); break;
+      default: TRY(record_via_radr<kPF16>(P)); break;
+    }
+  } else {
+    TRY(record_slices(P, P->ring_count));
+  }
+  P->ring_count += 1;
+  P->rec_k = P->k;
   TRY(timed_end(P, T, 2));
   return TDWP_OK;
 }
@@ -620,11 +782,12 @@ int run_steps(Plan* P, long n_steps, double* norms_out, Timing* T) {
     done += chunk;
     if (bad) return TDWP_ERANGE;
   }
-  return TDWP_OK;
+  return finish_slices(P, T);
 }
 
 void reset_propagation(Plan* P) {
   P->k = 0;
+  P->rec_k = -1;
   P->cur = 0;
   P->ring_count = 0;
   P->ring_k0 = 0;
@@ -838,16 +1001,22 @@ int tdwp_set_initial_packet(tdwp_plan_t p, const tdwp_packet* pk, const double* 
   HIP_TRY(hipMemsetAsync(p->d_acc + P.acc_off, 0, (size_t)2 * p->cfg.n_energy * P.n_slice * sizeof(double), p->stream));
   HIP_TRY(hipMemsetAsync(p->d_snap + P.snap_off, 0, (size_t)2 * p->cfg.n_energy * P.n_w * sizeof(double), p->stream));
   P.snap_taken = (pk->k_min_elastic == 0);
-  // k = 0 slices of this packet into ring row 0
-  {
-    const int nlines = P.n_sv;
-    hipLaunchKernelGGL(k_slices, dim3((nlines * 64 + 255) / 256), dim3(256), 0, p->stream,
-                       p->d_u[p->cur] + P.off, nlines, nR, nr, p->m_inf, p->d_arow, p->d_drow,
-                       1.0 / std::sqrt(p->dR), p->d_ring + P.slice_off);
-    HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(p->d_E + ip, &pk->E_v0j0, sizeof(double), hipMemcpyHostToDevice, p->stream));
+  // k = 0 slices into ring row 0 (packets not yet set are overwritten when they are)
+  p->ring_count = 0;
+  if (p->fast) {
+    switch (p->cfg.precision) {
+      case TDWP_FP64: TRY(record_via_radr<kP64>(p)); break;
+      case TDWP_FP32: TRY(record_via_radr<kP32>(p)); break;
+      case TDWP_BF16X3: TRY(record_via_radr<kPBF>(p)); break;
+      default: TRY(record_via_radr<kPF16>(p)); break;
+    }
+  } else {
+    TRY(record_slices(p, 0));
   }
   p->ring_k0 = 0;
   p->ring_count = 1;
+  p->rec_k = 0;
   P.set = true;
   HIP_TRY(hipStreamSynchronize(p->stream));
   return TDWP_OK;
@@ -894,6 +1063,7 @@ int tdwp_state_to_state(tdwp_plan_t p, int unit, int slot, int n_ch, const tdwp_
     if (ch[f].elec < 0 || ch[f].elec >= p->ne || ch[f].j < 0 || ch[f].j > p->ng - 1) return TDWP_EINVAL;
     if (ch[f].omega < U.om_lo || ch[f].omega > U.om_hi) return TDWP_EINVAL;
   }
+  TRY(finish_slices(p, nullptr));
   TRY(flush_ring(p));
   const size_t need_out = (size_t)(n_ch + p->ne) * nE;
   TRY(ensure_staging(p, &p->d_out, &p->out_cap, need_out));
