@@ -139,6 +139,57 @@ int tdwp_diatomic_states(tdwp_plan_t p, const double* v_asym, int j, int n_state
  * Only TDWP_POT_TABLE is accepted by this entry point.  Resets propagation. */
 int tdwp_set_potential(tdwp_plan_t p, int mode, const double* v, size_t n_values);
 
+/* Options of the learned potential.  The network maps the three internuclear
+ * distances (r_AB, r_BC, r_AC) of a grid point to the packed upper triangle of
+ * its diabatic matrix (n_elec (n_elec+1)/2 outputs):
+ *   f = (d - 4 bohr)/3 bohr; a_k = silu(a_{k-1} W_k + b_k), k = 1..3, 128 units;
+ *   V = 0.1 hartree (a_3 W_4 + b_4);  silu(x) = x/(1 + e^-x).
+ * Parameters (FP32, flat): W1[3][128] b1[128] W2[128][128] b2 W3[128][128] b3
+ * W4[128][n_pair] b4[n_pair], W stored [in][out]; tdwp_mlp_n_params gives the
+ * count.  Training minimises the mean squared error of V/0.1 hartree with
+ * Adam (beta1 0.9, beta2 0.999, eps 1e-8) on minibatches taken in the order
+ * given; inference uses BF16 copies of the weights with FP32 accumulation. */
+typedef struct {
+  int n_samples;              /* training points                                       */
+  const long* sample_idx;     /* flat grid indices n*(n_R*n_r) + m*n_r + i, [n_samples] */
+  const float* init_params;   /* initial parameters                                    */
+  const int* order;           /* permutation of 0..n_samples-1; minibatch b of epoch e  */
+                              /* takes order[(e*n_samples + b*batch + j) % n_samples]   */
+  int batch;                  /* minibatch size, 1..4096                               */
+  int epochs;
+  double lr;                  /* Adam step size                                        */
+} tdwp_mlp_options;
+
+/* Number of parameters of the learned potential for this plan's n_elec. */
+int tdwp_mlp_n_params(tdwp_plan_t p);
+
+/* Trains the learned potential on the device from the tabulated potential v
+ * (same layout as tdwp_set_potential) and installs it: from now on every step
+ * evaluates the network at each grid point instead of reading a table.  E0 and
+ * dE follow from the Gershgorin bounds of the network's values on the grid
+ * (unless cfg.e_min/e_max were given).  report (may be NULL) receives
+ * [final training loss, RMS error over all grid entries (hartree), max abs error
+ * (hartree)].  Errors: EINVAL (sizes, options), EDEVICE. Resets propagation. */
+int tdwp_set_potential_mlp(tdwp_plan_t p, const double* v, size_t n_values,
+                           const tdwp_mlp_options* opt, double* report);
+
+/* Copies the current FP32 network parameters (after training) to params. */
+int tdwp_mlp_params(tdwp_plan_t p, float* params);
+
+/* Loss and gradient of the training objective for given parameters on n_pts
+ * points: dist [n_pts][3] internuclear distances (bohr), v [n_pts][n_pair]
+ * targets (hartree).  FP32 device kernels; grad has tdwp_mlp_n_params entries. */
+int tdwp_mlp_gradient(tdwp_plan_t p, const float* params, int n_pts, const double* dist,
+                      const double* v, double* loss, float* grad);
+
+/* Inference kernel on n_pts points with the plan's trained network (BF16
+ * weights): v_out [n_pts][n_pair] in hartree. */
+int tdwp_mlp_eval(tdwp_plan_t p, int n_pts, const double* dist, double* v_out);
+
+/* The network's potential on the plan's grid, v_out laid out like the table of
+ * tdwp_set_potential (the values every step uses after tdwp_set_potential_mlp). */
+int tdwp_mlp_grid(tdwp_plan_t p, double* v_out);
+
 /* Returns the (E_min, E_max) in use (after tdwp_set_potential). */
 int tdwp_spectral_bounds(tdwp_plan_t p, double* e_min, double* e_max);
 

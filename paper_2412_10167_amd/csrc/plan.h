@@ -139,6 +139,16 @@ struct tdwp_plan_s {
   size_t lds_ang_max = 0;
   size_t* d_wg_off = nullptr;     // per packet: first norm partial
   int* d_n_wg = nullptr;          // per packet: number of norm partials
+  // learned potential
+  int pot_mode = 0;               // TDWP_POT_TABLE or TDWP_POT_MLP
+  int mlp_nparams = 0;
+  float* d_mlp_theta = nullptr;   // FP32 master parameters
+  void* d_mlp_w = nullptr;        // packed BF16 weights (w1t, w2t, w3t, w4t)
+  float* d_mlp_b = nullptr;       // biases [3*128 + 16]
+  double* d_rg = nullptr;         // grids on the device (r, R, cos gamma)
+  double* d_Rg = nullptr;
+  double* d_xg = nullptr;
+  size_t lds_radR_mlp = 0;
   std::vector<void*> allocations;
 };
 

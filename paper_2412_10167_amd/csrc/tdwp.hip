@@ -14,6 +14,7 @@
 #include "host_tables.h"
 #include "plan.h"
 #include "fast_kernels.hpp"
+#include "mlp_kernels.hpp"
 #include "step_kernels.hpp"
 
 using namespace tdwp;
@@ -395,6 +396,9 @@ int layout_and_allocate(Plan* P) {
   TRY(alloc_copy(P, &P->d_P, P->Ptab));
   TRY(alloc_copy(P, &P->d_D, P->D));
   TRY(alloc_copy(P, &P->d_Br, P->Br));
+  TRY(alloc_copy(P, &P->d_rg, P->r));
+  TRY(alloc_copy(P, &P->d_Rg, P->R));
+  TRY(alloc_copy(P, &P->d_xg, P->x));
   TRY(alloc_copy(P, &P->d_BR, P->BR));
   TRY(alloc_copy(P, &P->d_arow, P->arow));
   TRY(alloc_copy(P, &P->d_drow, P->drow));
@@ -489,6 +493,27 @@ int layout_and_allocate(Plan* P) {
   return TDWP_OK;
 }
 
+// Device memory owned by one library call and released when it returns.
+struct Scratch {
+  std::vector<void*> ptrs;
+  ~Scratch() {
+    if (ptrs.empty()) return;
+    (void)hipDeviceSynchronize();   // no kernel may still use the memory
+    for (void* q : ptrs) (void)hipFree(q);
+  }
+  int get(void** out, size_t bytes) {
+    *out = nullptr;
+    hipError_t e = hipMalloc(out, bytes ? bytes : 8);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      *out = nullptr;
+      return e == hipErrorOutOfMemory ? TDWP_ENOMEM : TDWP_EDEVICE;
+    }
+    ptrs.push_back(*out);
+    return TDWP_OK;
+  }
+};
+
 int ensure_staging(Plan* P, double** buf, size_t* cap, size_t need) {
   if (*cap >= need) return TDWP_OK;
   void* p = nullptr;
@@ -577,6 +602,81 @@ int take_snapshots(Plan* P) {
   return TDWP_OK;
 }
 
+MlpNet mlp_net(Plan* P) {
+  const __bf16* w = (const __bf16*)P->d_mlp_w;
+  MlpNet N;
+  N.w1t = w;
+  N.w2t = w + kMlpH * 32;
+  N.w3t = N.w2t + kMlpH * kMlpH;
+  N.w4t = N.w3t + kMlpH * kMlpH;
+  N.b1 = P->d_mlp_b;
+  N.b2 = P->d_mlp_b + kMlpH;
+  N.b3 = P->d_mlp_b + 2 * kMlpH;
+  N.b4 = P->d_mlp_b + 3 * kMlpH;
+  N.npair = P->npair;
+  return N;
+}
+
+int mlp_param_count(int npair) {
+  return 3 * kMlpH + kMlpH + 2 * (kMlpH * kMlpH + kMlpH) + kMlpH * npair + npair;
+}
+
+// Device work buffers of one forward/backward pass on a batch of B points.
+struct MlpPass {
+  float *X, *T, *Z1, *A1, *Z2, *A2, *Z3, *A3, *Z4, *Y, *dZ4, *dZ3, *dZ2, *dZ1, *part;
+};
+
+int mlp_alloc_pass(Scratch& S, Plan* P, int B, MlpPass* q) {
+  const int np = P->npair;
+  const size_t sizes[15] = {(size_t)B * 3, (size_t)B * np, (size_t)B * kMlpH, (size_t)B * kMlpH,
+                            (size_t)B * kMlpH, (size_t)B * kMlpH, (size_t)B * kMlpH,
+                            (size_t)B * kMlpH, (size_t)B * np, (size_t)B * np, (size_t)B * np,
+                            (size_t)B * kMlpH, (size_t)B * kMlpH, (size_t)B * kMlpH,
+                            (size_t)(B * np + 255) / 256 + 1};
+  float** ptrs[15] = {&q->X, &q->T, &q->Z1, &q->A1, &q->Z2, &q->A2, &q->Z3, &q->A3, &q->Z4,
+                      &q->Y, &q->dZ4, &q->dZ3, &q->dZ2, &q->dZ1, &q->part};
+  for (int i = 0; i < 15; ++i) TRY(S.get((void**)ptrs[i], sizes[i] * sizeof(float)));
+  return TDWP_OK;
+}
+
+// Forward + backward on the batch already in q.X / q.T; gradient into g (layout of theta).
+int mlp_fwd_bwd(Plan* P, const float* th, float* g, int B, const MlpPass& q) {
+  const int np = P->npair, H = kMlpH;
+  const float* W1 = th;
+  const float* b1 = W1 + 3 * H;
+  const float* W2 = b1 + H;
+  const float* b2 = W2 + H * H;
+  const float* W3 = b2 + H;
+  const float* b3 = W3 + H * H;
+  const float* W4 = b3 + H;
+  const float* b4 = W4 + H * np;
+  float* gW1 = g;
+  float* gb1 = gW1 + 3 * H;
+  float* gW2 = gb1 + H;
+  float* gb2 = gW2 + H * H;
+  float* gW3 = gb2 + H;
+  float* gb3 = gW3 + H * H;
+  float* gW4 = gb3 + H;
+  float* gb4 = gW4 + H * np;
+  auto grid = [](long n) { return dim3((unsigned)((n + 255) / 256)); };
+  hipStream_t st = P->stream;
+  hipLaunchKernelGGL(k_dense_fwd, grid((long)B * H), dim3(256), 0, st, q.X, 3, W1, b1, H, B, q.Z1, q.A1, 1);
+  hipLaunchKernelGGL(k_dense_fwd, grid((long)B * H), dim3(256), 0, st, q.A1, H, W2, b2, H, B, q.Z2, q.A2, 1);
+  hipLaunchKernelGGL(k_dense_fwd, grid((long)B * H), dim3(256), 0, st, q.A2, H, W3, b3, H, B, q.Z3, q.A3, 1);
+  hipLaunchKernelGGL(k_dense_fwd, grid((long)B * np), dim3(256), 0, st, q.A3, H, W4, b4, np, B, q.Z4, q.Y, 0);
+  hipLaunchKernelGGL(k_mse_grad, grid((long)B * np), dim3(256), 0, st, q.Y, q.T, B * np,
+                     1.0f / (float)(B * np), q.dZ4, q.part);
+  hipLaunchKernelGGL(k_dense_bwd_w, grid((long)(H + 1) * np), dim3(256), 0, st, q.A3, q.dZ4, H, np, B, gW4, gb4);
+  hipLaunchKernelGGL(k_dense_bwd_data, grid((long)B * H), dim3(256), 0, st, q.dZ4, W4, H, np, B, q.Z3, q.dZ3);
+  hipLaunchKernelGGL(k_dense_bwd_w, grid((long)(H + 1) * H), dim3(256), 0, st, q.A2, q.dZ3, H, H, B, gW3, gb3);
+  hipLaunchKernelGGL(k_dense_bwd_data, grid((long)B * H), dim3(256), 0, st, q.dZ3, W3, H, H, B, q.Z2, q.dZ2);
+  hipLaunchKernelGGL(k_dense_bwd_w, grid((long)(H + 1) * H), dim3(256), 0, st, q.A1, q.dZ2, H, H, B, gW2, gb2);
+  hipLaunchKernelGGL(k_dense_bwd_data, grid((long)B * H), dim3(256), 0, st, q.dZ2, W2, H, H, B, q.Z1, q.dZ1);
+  hipLaunchKernelGGL(k_dense_bwd_w, grid((long)4 * H), dim3(256), 0, st, q.X, q.dZ1, 3, H, B, gW1, gb1);
+  HIP_TRY(hipGetLastError());
+  return TDWP_OK;
+}
+
 // Before slices of the current k are recorded: flush a full ring, and flush
 // then snapshot where an elastic-channel window opens at this k.
 int prepare_record(Plan* P, Timing* T) {
@@ -647,10 +747,19 @@ int fast_step(Plan* P, int chunk_row, Timing* T) {
   TRY(timed_end(P, T, 0));
   TRY(timed_begin(P, T));
   double* nrow = P->d_normpart + (size_t)chunk_row * P->n_wg_total;
-  hipLaunchKernelGGL(k_radR_epi<PR>, dim3(P->blocks_radR), dim3(256), P->lds_radR, P->stream, uk,
-                     uo, h, pkd, P->d_blk_radR, np, (const E*)P->d_TRsF, (const E*)P->d_TRdF,
-                     P->nRhk, P->nRhk * P->nRhk, P->d_V, P->d_D, ne, ng, nR, nr, P->E0,
-                     1.0 / P->dE, first, nrow);
+  if (P->pot_mode == TDWP_POT_MLP) {
+    const double mbc = P->cfg.mass_B + P->cfg.mass_C;
+    hipLaunchKernelGGL(k_radR_epi_mlp<PR>, dim3(P->blocks_radR), dim3(256), P->lds_radR_mlp,
+                       P->stream, uk, uo, h, pkd, P->d_blk_radR, np, (const E*)P->d_TRsF,
+                       (const E*)P->d_TRdF, P->nRhk, P->nRhk * P->nRhk, mlp_net(P), P->d_rg,
+                       P->d_Rg, P->d_xg, P->cfg.mass_C / mbc, P->cfg.mass_B / mbc, P->d_D, ne, ng,
+                       nR, nr, P->E0, 1.0 / P->dE, first, nrow);
+  } else {
+    hipLaunchKernelGGL(k_radR_epi<PR>, dim3(P->blocks_radR), dim3(256), P->lds_radR, P->stream,
+                       uk, uo, h, pkd, P->d_blk_radR, np, (const E*)P->d_TRsF,
+                       (const E*)P->d_TRdF, P->nRhk, P->nRhk * P->nRhk, P->d_V, P->d_D, ne, ng,
+                       nR, nr, P->E0, 1.0 / P->dE, first, nrow);
+  }
   HIP_TRY(hipGetLastError());
   TRY(timed_end(P, T, 1));
   return TDWP_OK;
@@ -801,6 +910,8 @@ void reset_propagation(Plan* P) {
 
 // ---- C ABI -------------------------------------------------------------------
 
+extern "C" int bounds_from_table(tdwp_plan_t p, const double* v);
+
 extern "C" {
 
 int tdwp_plan(const tdwp_config* cfg, tdwp_plan_t* out) {
@@ -892,7 +1003,16 @@ int tdwp_set_potential(tdwp_plan_t p, int mode, const double* v, size_t n_values
   if (n_values != (size_t)p->npair * plane) return TDWP_EINVAL;
   HIP_TRY(hipMemcpyAsync(p->d_V, v, n_values * sizeof(double), hipMemcpyHostToDevice, p->stream));
   HIP_TRY(hipStreamSynchronize(p->stream));
-  if (!p->bounds_given) {
+  if (!p->bounds_given) TRY(bounds_from_table(p, v));
+  p->pot_mode = TDWP_POT_TABLE;
+  p->have_potential = true;
+  reset_propagation(p);
+  return TDWP_OK;
+}
+
+int bounds_from_table(tdwp_plan_t p, const double* v) {
+  const size_t plane = (size_t)p->ng * p->nR * p->nr;
+  {
     // Gershgorin range of the per-point diabatic matrix
     const int ne = p->ne;
     double lo = INFINITY, hi = -INFINITY;
@@ -928,8 +1048,6 @@ int tdwp_set_potential(tdwp_plan_t p, int mode, const double* v, size_t n_values
     p->E0 = 0.5 * (p->e_max + p->e_min);
     p->dE = 0.5 * (p->e_max - p->e_min);
   }
-  p->have_potential = true;
-  reset_propagation(p);
   return TDWP_OK;
 }
 
@@ -1133,6 +1251,200 @@ int tdwp_time_kernels(tdwp_plan_t p, long n_steps, int n_max, double* avg_us, ch
     names[names_len - 1] = 0;
   }
   return 5;
+}
+
+int tdwp_mlp_n_params(tdwp_plan_t p) {
+  if (!p) return TDWP_EINVAL;
+  return mlp_param_count(p->npair);
+}
+
+int tdwp_set_potential_mlp(tdwp_plan_t p, const double* v, size_t n_values,
+                           const tdwp_mlp_options* o, double* report) {
+  if (!p || !v || !o) return TDWP_EINVAL;
+  const size_t plane = (size_t)p->ng * p->nR * p->nr;
+  if (n_values != (size_t)p->npair * plane) return TDWP_EINVAL;
+  if (o->n_samples < 1 || !o->sample_idx || !o->init_params || !o->order) return TDWP_EINVAL;
+  if (o->batch < 1 || o->batch > 4096 || o->batch > o->n_samples || o->epochs < 0) return TDWP_EINVAL;
+  if (!(o->lr > 0)) return TDWP_EINVAL;
+  if (!p->fast || (p->nR / 2 + 15) / 16 > 4 * kMlpMaxMT || p->ne > kMlpMaxElec) return TDWP_EINVAL;
+  for (int i = 0; i < o->n_samples; ++i) {
+    if (o->sample_idx[i] < 0 || (size_t)o->sample_idx[i] >= plane) return TDWP_EINVAL;
+    if (o->order[i] < 0 || o->order[i] >= o->n_samples) return TDWP_EINVAL;
+  }
+  {
+    const int prec = p->cfg.precision;
+    const size_t eb = elem_bytes(prec) * planes_of(prec);
+    const int kpR = round_up(p->nR / 2, (int)ks_of(prec));
+    const size_t sd = ((size_t)2 * 16 * ld_of(prec, kpR) * eb + 15) / 16 * 16;
+    p->lds_radR_mlp = (size_t)p->ne * p->nR * 16 * sizeof(double) + sd +
+                      4 * ((size_t)16 * kMlpLd * 2 + 16 * 16 * 4);
+    if (p->lds_radR_mlp > kLdsMax) return TDWP_EINVAL;
+  }
+  HIP_TRY(hipMemcpyAsync(p->d_V, v, n_values * sizeof(double), hipMemcpyHostToDevice, p->stream));
+  const int npar = mlp_param_count(p->npair);
+  p->mlp_nparams = npar;
+  if (!p->d_mlp_theta) {
+    TRY(dev_alloc(p, (void**)&p->d_mlp_theta, (size_t)npar * sizeof(float)));
+    const size_t nw = (size_t)kMlpH * 32 + 2 * kMlpH * kMlpH + 16 * kMlpH;
+    TRY(dev_alloc(p, &p->d_mlp_w, nw * sizeof(__bf16)));
+    TRY(dev_alloc(p, (void**)&p->d_mlp_b, (size_t)(3 * kMlpH + 16) * sizeof(float)));
+  }
+  Scratch S;
+  float *g = nullptr, *m1 = nullptr, *m2 = nullptr;
+  long* d_idx = nullptr;
+  int* d_ord = nullptr;
+  TRY(S.get((void**)&g, (size_t)npar * sizeof(float)));
+  TRY(S.get((void**)&m1, (size_t)npar * sizeof(float)));
+  TRY(S.get((void**)&m2, (size_t)npar * sizeof(float)));
+  TRY(S.get((void**)&d_idx, (size_t)o->n_samples * sizeof(long)));
+  TRY(S.get((void**)&d_ord, (size_t)o->n_samples * sizeof(int)));
+  HIP_TRY(hipMemcpyAsync(p->d_mlp_theta, o->init_params, (size_t)npar * sizeof(float), hipMemcpyHostToDevice, p->stream));
+  HIP_TRY(hipMemcpyAsync(d_idx, o->sample_idx, (size_t)o->n_samples * sizeof(long), hipMemcpyHostToDevice, p->stream));
+  HIP_TRY(hipMemcpyAsync(d_ord, o->order, (size_t)o->n_samples * sizeof(int), hipMemcpyHostToDevice, p->stream));
+  HIP_TRY(hipMemsetAsync(m1, 0, (size_t)npar * sizeof(float), p->stream));
+  HIP_TRY(hipMemsetAsync(m2, 0, (size_t)npar * sizeof(float), p->stream));
+  MlpPass q;
+  const int B = o->batch;
+  TRY(mlp_alloc_pass(S, p, B, &q));
+  const double mbc = p->cfg.mass_B + p->cfg.mass_C;
+  const double cB = p->cfg.mass_C / mbc, cC = p->cfg.mass_B / mbc;
+  const int nb = o->n_samples / B;
+  long step = 0;
+  const double b1 = 0.9, b2 = 0.999;
+  for (int e = 0; e < o->epochs; ++e)
+    for (int b = 0; b < nb; ++b) {
+      const long e0 = (long)e * o->n_samples + (long)b * B;
+      hipLaunchKernelGGL(k_mlp_batch, dim3((B + 255) / 256), dim3(256), 0, p->stream, d_idx, d_ord,
+                         o->n_samples, e0, B, p->d_V, p->npair, plane, p->d_rg, p->d_Rg, p->d_xg,
+                         p->nR, p->nr, cB, cC, q.X, q.T);
+      TRY(mlp_fwd_bwd(p, p->d_mlp_theta, g, B, q));
+      ++step;
+      const float c1 = (float)(1.0 - std::pow(b1, (double)step));
+      const float c2 = (float)(1.0 - std::pow(b2, (double)step));
+      hipLaunchKernelGGL(k_adam, dim3((npar + 255) / 256), dim3(256), 0, p->stream, p->d_mlp_theta, g,
+                         m1, m2, npar, (float)o->lr, (float)b1, (float)b2, 1e-8f, c1, c2);
+      HIP_TRY(hipGetLastError());
+    }
+  // final training loss over every sample (forward only; the gradient is discarded)
+  double loss_sum = 0.0;
+  {
+    const int nparts = (B * p->npair + 255) / 256;
+    std::vector<float> part(nparts);
+    for (int b = 0; b < nb; ++b) {
+      hipLaunchKernelGGL(k_mlp_batch, dim3((B + 255) / 256), dim3(256), 0, p->stream, d_idx, d_ord,
+                         o->n_samples, (long)b * B, B, p->d_V, p->npair, plane, p->d_rg, p->d_Rg,
+                         p->d_xg, p->nR, p->nr, cB, cC, q.X, q.T);
+      TRY(mlp_fwd_bwd(p, p->d_mlp_theta, g, B, q));
+      HIP_TRY(hipMemcpyAsync(part.data(), q.part, nparts * sizeof(float), hipMemcpyDeviceToHost, p->stream));
+      HIP_TRY(hipStreamSynchronize(p->stream));
+      for (float x : part) loss_sum += x;
+    }
+    loss_sum /= (double)nb * B * p->npair;
+  }
+  hipLaunchKernelGGL(k_mlp_pack, dim3((kMlpH * kMlpH + 255) / 256), dim3(256), 0, p->stream,
+                     p->d_mlp_theta, p->npair, (__bf16*)p->d_mlp_w,
+                     (__bf16*)p->d_mlp_w + kMlpH * 32,
+                     (__bf16*)p->d_mlp_w + kMlpH * 32 + kMlpH * kMlpH,
+                     (__bf16*)p->d_mlp_w + kMlpH * 32 + 2 * kMlpH * kMlpH, p->d_mlp_b);
+  HIP_TRY(hipGetLastError());
+  // the network on the whole grid: error against the table, and spectral bounds
+  double* d_vm = nullptr;
+  TRY(S.get((void**)&d_vm, (size_t)p->npair * plane * sizeof(double)));
+  const long n_pts = (long)plane;
+  hipLaunchKernelGGL(k_mlp_grid, dim3((unsigned)((n_pts + 63) / 64)), dim3(256), 0, p->stream,
+                     mlp_net(p), p->d_rg, p->d_Rg, p->d_xg, p->ng, p->nR, p->nr, cB, cC, d_vm);
+  HIP_TRY(hipGetLastError());
+  std::vector<double> vm((size_t)p->npair * plane);
+  HIP_TRY(hipMemcpyAsync(vm.data(), d_vm, vm.size() * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  double se = 0.0, mx = 0.0;
+  for (size_t q2 = 0; q2 < vm.size(); ++q2) {
+    const double d = vm[q2] - v[q2];
+    se += d * d;
+    mx = std::max(mx, std::fabs(d));
+  }
+  if (!p->bounds_given) TRY(bounds_from_table(p, vm.data()));
+  if (report) {
+    report[0] = loss_sum;
+    report[1] = std::sqrt(se / (double)vm.size());
+    report[2] = mx;
+  }
+  p->pot_mode = TDWP_POT_MLP;
+  p->have_potential = true;
+  reset_propagation(p);
+  return TDWP_OK;
+}
+
+int tdwp_mlp_params(tdwp_plan_t p, float* params) {
+  if (!p || !params) return TDWP_EINVAL;
+  if (!p->d_mlp_theta) return TDWP_ESTATE;
+  HIP_TRY(hipMemcpyAsync(params, p->d_mlp_theta, (size_t)p->mlp_nparams * sizeof(float),
+                         hipMemcpyDeviceToHost, p->stream));
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  return TDWP_OK;
+}
+
+int tdwp_mlp_gradient(tdwp_plan_t p, const float* params, int n_pts, const double* dist,
+                      const double* v, double* loss, float* grad) {
+  if (!p || !params || !dist || !v || n_pts < 1 || n_pts > 65536) return TDWP_EINVAL;
+  const int npar = mlp_param_count(p->npair);
+  Scratch S;
+  float *th = nullptr, *g = nullptr;
+  double *dd = nullptr, *dv = nullptr;
+  TRY(S.get((void**)&th, (size_t)npar * sizeof(float)));
+  TRY(S.get((void**)&g, (size_t)npar * sizeof(float)));
+  TRY(S.get((void**)&dd, (size_t)n_pts * 3 * sizeof(double)));
+  TRY(S.get((void**)&dv, (size_t)n_pts * p->npair * sizeof(double)));
+  MlpPass q;
+  TRY(mlp_alloc_pass(S, p, n_pts, &q));
+  HIP_TRY(hipMemcpyAsync(th, params, (size_t)npar * sizeof(float), hipMemcpyHostToDevice, p->stream));
+  HIP_TRY(hipMemcpyAsync(dd, dist, (size_t)n_pts * 3 * sizeof(double), hipMemcpyHostToDevice, p->stream));
+  HIP_TRY(hipMemcpyAsync(dv, v, (size_t)n_pts * p->npair * sizeof(double), hipMemcpyHostToDevice, p->stream));
+  hipLaunchKernelGGL(k_mlp_feats, dim3((n_pts + 255) / 256), dim3(256), 0, p->stream, dd, dv, n_pts,
+                     p->npair, q.X, q.T);
+  TRY(mlp_fwd_bwd(p, th, g, n_pts, q));
+  const int nparts = (n_pts * p->npair + 255) / 256;
+  std::vector<float> part(nparts);
+  HIP_TRY(hipMemcpyAsync(part.data(), q.part, nparts * sizeof(float), hipMemcpyDeviceToHost, p->stream));
+  if (grad) HIP_TRY(hipMemcpyAsync(grad, g, (size_t)npar * sizeof(float), hipMemcpyDeviceToHost, p->stream));
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  double s = 0.0;
+  for (float x : part) s += x;
+  if (loss) *loss = s / ((double)n_pts * p->npair);
+  return TDWP_OK;
+}
+
+int tdwp_mlp_eval(tdwp_plan_t p, int n_pts, const double* dist, double* v_out) {
+  if (!p || !dist || !v_out || n_pts < 1) return TDWP_EINVAL;
+  if (!p->d_mlp_theta || p->pot_mode != TDWP_POT_MLP) return TDWP_ESTATE;
+  Scratch S;
+  double *dd = nullptr, *dv = nullptr;
+  TRY(S.get((void**)&dd, (size_t)n_pts * 3 * sizeof(double)));
+  TRY(S.get((void**)&dv, (size_t)n_pts * p->npair * sizeof(double)));
+  HIP_TRY(hipMemcpyAsync(dd, dist, (size_t)n_pts * 3 * sizeof(double), hipMemcpyHostToDevice, p->stream));
+  hipLaunchKernelGGL(k_mlp_eval, dim3((n_pts + 63) / 64), dim3(256), 0, p->stream, mlp_net(p), dd,
+                     n_pts, dv);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(v_out, dv, (size_t)n_pts * p->npair * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  return TDWP_OK;
+}
+
+int tdwp_mlp_grid(tdwp_plan_t p, double* v_out) {
+  if (!p || !v_out) return TDWP_EINVAL;
+  if (!p->d_mlp_theta || p->pot_mode != TDWP_POT_MLP) return TDWP_ESTATE;
+  const size_t plane = (size_t)p->ng * p->nR * p->nr;
+  Scratch S;
+  double* dv = nullptr;
+  TRY(S.get((void**)&dv, (size_t)p->npair * plane * sizeof(double)));
+  const double mbc = p->cfg.mass_B + p->cfg.mass_C;
+  hipLaunchKernelGGL(k_mlp_grid, dim3((unsigned)((plane + 63) / 64)), dim3(256), 0, p->stream,
+                     mlp_net(p), p->d_rg, p->d_Rg, p->d_xg, p->ng, p->nR, p->nr,
+                     p->cfg.mass_C / mbc, p->cfg.mass_B / mbc, dv);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(v_out, dv, (size_t)p->npair * plane * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  return TDWP_OK;
 }
 
 void tdwp_destroy(tdwp_plan_t p) { free_plan(p); }

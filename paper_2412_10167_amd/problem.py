@@ -14,15 +14,21 @@ def potential_table(plan, spec):
     return diabatic_matrix(spec, r[None, None, :], R[None, :, None], x[:, None, None])
 
 
-def build(spec, precision="fp64", bounds=None, stream="current", vtable=None):
+def build(spec, precision="fp64", bounds=None, stream="current", vtable=None, mlp=None):
     """Plan + potential + every initial packet.  Returns (plan, info) where info
-    holds the grid, E_v0j0 per packet and the initial channel functions."""
+    holds the grid, E_v0j0 per packet and the initial channel functions.
+    mlp: None (tabulated potential) or a dict of set_potential_mlp arguments
+    (sample_idx, init_params, order, batch, epochs, lr); the table is then the
+    training data and info["mlp_report"] the training report."""
     plan = Plan(spec, precision=precision, bounds=bounds, stream=stream)
     r, R, x, w = plan.grid()
     if vtable is None:
         vtable = potential_table(plan, spec)
-    plan.set_potential(vtable)
     info = dict(r=r, R=R, x=x, w=w, e0={}, chi0={})
+    if mlp is None:
+        plan.set_potential(vtable)
+    else:
+        info["mlp_report"] = plan.set_potential_mlp(vtable, **mlp)
     for pk in spec["packets"]:
         va = asymptotic_potential(spec, r, pk["elec0"])
         e, chi = plan.diatomic_states(va, pk["j0"], pk["v0"] + 1)

@@ -15,7 +15,8 @@ EXPORTED_SYMBOLS = (
     "tdwp_plan", "tdwp_grid", "tdwp_diatomic_states", "tdwp_set_potential",
     "tdwp_spectral_bounds", "tdwp_set_initial_packet", "tdwp_propagate", "tdwp_step_index",
     "tdwp_get_packet", "tdwp_state_to_state", "tdwp_time_kernels", "tdwp_destroy",
-    "tdwp_strerror",
+    "tdwp_strerror", "tdwp_mlp_n_params", "tdwp_set_potential_mlp", "tdwp_mlp_params",
+    "tdwp_mlp_gradient", "tdwp_mlp_eval", "tdwp_mlp_grid",
 )
 
 
@@ -56,6 +57,12 @@ class Packet(ctypes.Structure):
                 ("ecol_mean", ctypes.c_double), ("k_min_elastic", ctypes.c_long)]
 
 
+class MlpOptions(ctypes.Structure):
+    _fields_ = [("n_samples", ctypes.c_int), ("sample_idx", ctypes.POINTER(ctypes.c_long)),
+                ("init_params", ctypes.POINTER(ctypes.c_float)), ("order", ctypes.POINTER(ctypes.c_int)),
+                ("batch", ctypes.c_int), ("epochs", ctypes.c_int), ("lr", ctypes.c_double)]
+
+
 class Channel(ctypes.Structure):
     _fields_ = [("elec", ctypes.c_int), ("v", ctypes.c_int), ("j", ctypes.c_int),
                 ("omega", ctypes.c_int), ("energy", ctypes.c_double)]
@@ -93,6 +100,13 @@ def load_library():
                                         ctypes.POINTER(Channel), dp, dp, dp]
     lib.tdwp_time_kernels.argtypes = [P, ctypes.c_long, ctypes.c_int, dp, ctypes.c_char_p,
                                       ctypes.c_size_t]
+    fp = ctypes.POINTER(ctypes.c_float)
+    lib.tdwp_mlp_n_params.argtypes = [P]
+    lib.tdwp_set_potential_mlp.argtypes = [P, dp, ctypes.c_size_t, ctypes.POINTER(MlpOptions), dp]
+    lib.tdwp_mlp_params.argtypes = [P, fp]
+    lib.tdwp_mlp_gradient.argtypes = [P, fp, ctypes.c_int, dp, dp, dp, fp]
+    lib.tdwp_mlp_eval.argtypes = [P, ctypes.c_int, dp, dp]
+    lib.tdwp_mlp_grid.argtypes = [P, dp]
     lib.tdwp_destroy.argtypes = [P]
     lib.tdwp_destroy.restype = None
     lib.tdwp_strerror.argtypes = [ctypes.c_int]
@@ -239,6 +253,59 @@ class Plan:
                                             _ptr(p_reac) if reactive else None),
                "tdwp_state_to_state")
         return p_inel, (p_reac if reactive else None)
+
+    # -- learned potential ---------------------------------------------------
+    def mlp_n_params(self):
+        return _check(self.lib.tdwp_mlp_n_params(self.handle), "tdwp_mlp_n_params")
+
+    def set_potential_mlp(self, vtable, sample_idx, init_params, order, batch=1024, epochs=10,
+                          lr=1e-3):
+        """Trains the surrogate on the device; returns (final loss, rms error, max error)."""
+        v = _f64(vtable)
+        idx = np.ascontiguousarray(sample_idx, dtype=np.int64)
+        th = np.ascontiguousarray(init_params, dtype=np.float32)
+        od = np.ascontiguousarray(order, dtype=np.int32)
+        self._mlp_keep = (idx, th, od)
+        o = MlpOptions(n_samples=idx.size,
+                       sample_idx=idx.ctypes.data_as(ctypes.POINTER(ctypes.c_long)),
+                       init_params=th.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                       order=od.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                       batch=batch, epochs=epochs, lr=lr)
+        rep = np.zeros(3)
+        _check(self.lib.tdwp_set_potential_mlp(self.handle, _ptr(v), v.size, ctypes.byref(o), _ptr(rep)),
+               "tdwp_set_potential_mlp")
+        return tuple(rep)
+
+    def mlp_params(self):
+        out = np.empty(self.mlp_n_params(), dtype=np.float32)
+        _check(self.lib.tdwp_mlp_params(self.handle, out.ctypes.data_as(ctypes.POINTER(ctypes.c_float))),
+               "tdwp_mlp_params")
+        return out
+
+    def mlp_gradient(self, params, dist, v):
+        th = np.ascontiguousarray(params, dtype=np.float32)
+        d = _f64(dist)
+        vv = _f64(v)
+        g = np.empty(th.size, dtype=np.float32)
+        loss = ctypes.c_double()
+        _check(self.lib.tdwp_mlp_gradient(self.handle, th.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                          d.shape[0], _ptr(d), _ptr(vv), ctypes.byref(loss),
+                                          g.ctypes.data_as(ctypes.POINTER(ctypes.c_float))),
+               "tdwp_mlp_gradient")
+        return loss.value, g
+
+    def mlp_eval(self, dist):
+        d = _f64(dist)
+        out = np.empty((d.shape[0], self.spec["n_elec"] * (self.spec["n_elec"] + 1) // 2))
+        _check(self.lib.tdwp_mlp_eval(self.handle, d.shape[0], _ptr(d), _ptr(out)), "tdwp_mlp_eval")
+        return out
+
+    def mlp_grid(self):
+        s = self.spec
+        npair = s["n_elec"] * (s["n_elec"] + 1) // 2
+        out = np.empty((npair, s["n_gamma"], s["n_R"], s["n_r"]))
+        _check(self.lib.tdwp_mlp_grid(self.handle, _ptr(out)), "tdwp_mlp_grid")
+        return out
 
     def time_kernels(self, n_steps, n_max=8):
         avg = np.zeros(n_max)

@@ -1,0 +1,112 @@
+"""Learned potential on the GPU: gradients and inference against the FP64
+oracle, training, and the step with the network evaluated on the fly."""
+import numpy as np
+import pytest
+
+from oracle import mlp_oracle as MO
+from oracle import tdwp_oracle as O
+from workloads import asymptotic_potential, small_variant
+from workloads import pes as PES
+from workloads.mlp_inputs import batch_order, init_params, sample_indices
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+
+
+def _spec():
+    s = small_variant(5, n_R=24, n_r=20, n_gamma=12)
+    s["packets"][0]["k_min_elastic"] = 60
+    return s
+
+
+def _distances(spec, n, seed=7):
+    rng = np.random.default_rng(seed)
+    r = rng.uniform(0.5, 8.0, n)
+    R = rng.uniform(0.5, 12.0, n)
+    x = rng.uniform(-1.0, 1.0, n)
+    rab, rbc, rac = PES.atom_distances(r, R, x, spec["mass_A"], spec["mass_B"], spec["mass_C"])
+    d = np.stack([rab, rbc, rac], axis=1)
+    v = PES.diabatic_matrix(spec, r, R, x).T
+    return d, v
+
+
+def test_mlp_gradient_matches_oracle():
+    from paper_2412_10167_amd.tdwp import Plan
+    print("\n[case] MLP loss gradient, 256 points, 3 states", flush=True)
+    spec = _spec()
+    plan = Plan(spec)
+    th = init_params(6)
+    d, v = _distances(spec, 256)
+    loss_g, g_gpu = plan.mlp_gradient(th, d, v)
+    loss_o, g_o = MO.loss_and_grad(th.astype(np.float64), d, v, 6)
+    rel = np.max(np.abs(g_gpu - g_o)) / np.max(np.abs(g_o))
+    print(f"[result] loss gpu {loss_g:.6e} oracle {loss_o:.6e}; grad max rel {rel:.2e}", flush=True)
+    plan.close()
+    assert abs(loss_g - loss_o) < 1e-5 * abs(loss_o)
+    assert rel < 2e-4
+
+
+def test_mlp_inference_matches_oracle_at_initial_parameters():
+    from paper_2412_10167_amd import problem
+    print("\n[case] MLP inference (bf16 weights) vs FP64 oracle", flush=True)
+    spec = _spec()
+    th = init_params(6)
+    plan, _ = problem.build(spec, mlp=dict(sample_idx=np.arange(64), init_params=th,
+                                            order=np.arange(64), batch=64, epochs=0, lr=1e-3))
+    d, _ = _distances(spec, 300)
+    v_gpu = plan.mlp_eval(d)
+    v_o = MO.potential(th.astype(np.float64), d, 6)
+    err = np.max(np.abs(v_gpu - v_o))
+    scale = np.max(np.abs(v_o))
+    print(f"[result] max abs {err:.3e} hartree (output scale {scale:.3e})", flush=True)
+    plan.close()
+    assert err < 0.02 * scale
+
+
+def test_mlp_training_and_on_the_fly_step():
+    """Training lowers the loss; a step with the network evaluated inside the
+    propagation equals a tabulated run whose table holds the network's own grid
+    values; the difference from the true table is reported."""
+    from paper_2412_10167_amd import problem
+    print("\n[case] MLP training + on-the-fly propagation (24x20x12, J=4, 3 states)", flush=True)
+    spec = _spec()
+    plan_t, _ = problem.build(spec)
+    vtab = problem.potential_table(plan_t, spec)
+    n_pts = vtab[0].size
+    idx = sample_indices(n_pts, n_samples=4096)
+    th = init_params(6)
+    mlp = dict(sample_idx=idx, init_params=th, order=batch_order(idx.size), batch=256, epochs=60, lr=2e-3)
+    r, R, x, _ = plan_t.grid()
+    flat = np.unravel_index(idx, vtab[0].shape)
+    rab, rbc, rac = PES.atom_distances(r[flat[2]], R[flat[1]], x[flat[0]], spec["mass_A"],
+                                       spec["mass_B"], spec["mass_C"])
+    d = np.stack([rab, rbc, rac], axis=1)
+    loss0, _ = MO.loss_and_grad(th.astype(np.float64), d, vtab.reshape(6, -1)[:, idx].T, 6)
+    plan_m, info = problem.build(spec, mlp=mlp)
+    rep = info["mlp_report"]
+    print(f"[result] loss init {loss0:.4e} -> trained {rep[0]:.4e}; grid rms {rep[1] * 27211.386:.1f} meV, "
+          f"max {rep[2] * 27211.386:.1f} meV", flush=True)
+    assert rep[0] < 0.2 * loss0
+    vnet = plan_m.mlp_grid()
+    lo, hi = plan_m.spectral_bounds()
+    plan_n, _ = problem.build(spec, vtable=vnet, bounds=(lo, hi))
+    K = 80
+    plan_m.propagate(K)
+    plan_n.propagate(K)
+    um, un = plan_m.get_packet(0, 0, 0), plan_n.get_packet(0, 0, 0)
+    rel = np.max(np.abs(um - un)) / np.max(np.abs(un))
+    plan_t.propagate(K)
+    ut = plan_t.get_packet(0, 0, 0)
+    reltab = np.max(np.abs(um - ut)) / np.max(np.abs(ut))
+    print(f"[result] on-the-fly vs table-of-network packet rel {rel:.2e}; vs true table {reltab:.2e}",
+          flush=True)
+    for p in (plan_m, plan_n, plan_t):
+        p.close()
+    assert rel < 1e-12
