@@ -104,6 +104,8 @@ def main():
                     help="skip timing the plain FP64 form beside a mixed form")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-steps", type=int, default=50)
+    ap.add_argument("--autotune", type=int, default=3,
+                    help="steps per tile variant timed by the library's autotuner (0: off)")
     ap.add_argument("--workload", type=int, default=2,
                     help="workload number 1..5 (default 2: J=0 256x192x80)")
     ap.add_argument("--copy-calibration", type=int, default=0,
@@ -121,13 +123,20 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    # a dedicated (non-default, default-priority) stream: the library enqueues on it,
+    # the timing events are recorded on it, and HIP graphs can be captured on it
+    bench_stream = torch.cuda.Stream()
+    torch.cuda.set_stream(bench_stream)
+    tune_reports = {}
     spec = config(args.workload)
     values = sum(
         (u["omega_max"] - (0 if u["parity"] * (-1) ** u["J"] == 1 else 1) + 1) * u["n_packets"]
         for u in spec["units"]) * spec["n_elec"] * spec["n_R"] * spec["n_r"] * spec["n_gamma"]
 
     def timed(precision, steps, warmup):
-        plan, _ = problem.build(spec, precision=precision)
+        plan, info = problem.build(spec, precision=precision, autotune=args.autotune)
+        if info.get("autotune"):
+            tune_reports[precision] = info["autotune"]
         plan.propagate(warmup, norms=False)
         stream = torch.cuda.current_stream()
         torch.cuda.synchronize()
@@ -186,6 +195,7 @@ def main():
                    "grid_pt_steps_per_s": round(steps_per_s * values, 1),
                    "fp64_steps_per_s": round(fp64_rate, 2) if fp64_rate else None,
                    "speedup_vs_fp64": round(steps_per_s / fp64_rate, 3) if fp64_rate else None,
+                   "autotune": tune_reports or None,
                    "wall_s": round(wall, 3)},
         "roofline": roofline,
         "cpu_baseline": cpu,

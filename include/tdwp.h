@@ -228,6 +228,30 @@ int tdwp_get_packet(tdwp_plan_t p, int unit, int slot, int which, double* out);
 int tdwp_state_to_state(tdwp_plan_t p, int unit, int slot, int n_ch, const tdwp_channel* ch,
                         const double* chi, double* p_inel, double* p_reac);
 
+/* Chooses tile shapes of the step kernels by timing each feasible variant for
+ * `steps` steps on this plan's shapes, and keeps the fastest.  Call after the
+ * potential and before any initial packet (the packet buffers are used as
+ * scratch).  With TDWP_TUNE_CACHE naming a file, the choice is appended to it
+ * and later plans of the same shapes start from it.  report (may be NULL)
+ * receives "kernel_variant:time;...;chosen=..." text.  Errors: ESTATE. */
+int tdwp_autotune(tdwp_plan_t p, int steps, char* report, size_t report_len);
+
+enum tdwp_option {
+  TDWP_OPT_GRAPHS = 0,     /* 1 (default): replay captured HIP graphs of steady-state steps */
+  TDWP_OPT_ANG_TILE = 1    /* angular-kernel tile: 1, 2 or 4 sixteen-column tiles          */
+};
+enum tdwp_stat {
+  TDWP_STAT_GRAPH_STEPS = 0,        /* steps taken so far by graph replay      */
+  TDWP_STAT_ANG_TILE = 1,           /* current angular-kernel tile (0: general kernels) */
+  TDWP_STAT_MATRIX_CORE_PATH = 2    /* 1 when the matrix-core kernels are in use */
+};
+
+/* Sets a plan option; EINVAL for an unknown option or value. */
+int tdwp_set_option(tdwp_plan_t p, int option, long value);
+
+/* Reads a plan statistic. */
+int tdwp_get_stat(tdwp_plan_t p, int stat, long* value);
+
 /* Per-kernel average device time (microseconds) over n_steps further steps,
  * each kernel bracketed by HIP events on the plan's stream.  names receives
  * up to n_max kernel-kind names joined by ';' (buffer of names_len bytes).

@@ -76,7 +76,10 @@ struct SliceArgs {
   const double* d_s;
   const double* d_d;
   double inv_sqrt_dR;
-  double* ring_row;
+  double* ring_base;               // ring row = ring_base + counters[0] * ring_stride
+  size_t ring_stride;
+  const int* counters;             // device step counters: [0] ring row, [1] norm row
+  int ring_len;                    // rows of the ring (a counter outside 0..ring_len-1 records nothing)
 };
 
 template <int P>
@@ -98,6 +101,9 @@ __global__ __launch_bounds__(256) void k_radr(const double* __restrict__ u,
   E* S = reinterpret_cast<E*>(lds);
   E* Dd = S + F::PLANES * ps;
   const long line0 = (long)blockIdx.x * kRadrLines;
+  const int crow = sa.record ? sa.counters[0] : -1;
+  const bool rec_ok = crow >= 0 && crow < sa.ring_len;
+  double* ring_row = rec_ok ? sa.ring_base + (size_t)crow * sa.ring_stride : nullptr;
   // wave w loads lines w, w+4, ...; lanes run along the half line
   for (int li = threadIdx.x >> 6; li < kRadrLines; li += 4) {
     const long gl = line0 + li;
@@ -105,7 +111,7 @@ __global__ __launch_bounds__(256) void k_radr(const double* __restrict__ u,
     int pkx = 0;
     long local = 0;
     bool rinf = false;
-    if (sa.record && gl < nlines) {
+    if (rec_ok && gl < nlines) {
       int lo = 0, hi = sa.n_pk - 1;
       while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
@@ -120,14 +126,14 @@ __global__ __launch_bounds__(256) void k_radr(const double* __restrict__ u,
     double* wline = nullptr;
     if (rinf) {
       const long nsv = sa.line_start[pkx + 1] - sa.line_start[pkx];
-      wline = sa.ring_row + sa.slice_off[pkx] + 2 * nsv + (local / sa.nR) * nr;
+      wline = ring_row + sa.slice_off[pkx] + 2 * nsv + (local / sa.nR) * nr;
     }
     for (int k = threadIdx.x & 63; k < kp; k += 64) {
       double a = 0.0, b = 0.0;
       if (gl < nlines && k < nh) {
         a = p[k];
         b = p[nr - 1 - k];
-        if (sa.record) {
+        if (rec_ok) {
           sv += sa.a_s[k] * (a + b) + sa.a_d[k] * (a - b);
           sd += sa.d_s[k] * (a + b) + sa.d_d[k] * (a - b);
           if (rinf) {
@@ -139,14 +145,14 @@ __global__ __launch_bounds__(256) void k_radr(const double* __restrict__ u,
       F::put(S, ps, li * ld + k, a + b);
       F::put(Dd, ps, li * ld + k, a - b);
     }
-    if (sa.record && gl < nlines) {
+    if (rec_ok && gl < nlines) {
       for (int off = 32; off > 0; off >>= 1) {
         sv += __shfl_down(sv, off, 64);
         sd += __shfl_down(sd, off, 64);
       }
       if ((threadIdx.x & 63) == 0) {
         const long nsv = sa.line_start[pkx + 1] - sa.line_start[pkx];
-        double* out = sa.ring_row + sa.slice_off[pkx];
+        double* out = ring_row + sa.slice_off[pkx];
         out[local] = sv;
         out[nsv + local] = sd;
       }
@@ -412,13 +418,17 @@ __global__ __launch_bounds__(256) void k_radR_epi(
     const int* __restrict__ blk_start, int n_pk, const typename Fmt<P>::E* __restrict__ Ts,
     const typename Fmt<P>::E* __restrict__ Td, int ldt, int pst, const double* __restrict__ V,
     const double* __restrict__ D, int ne, int ng, int nR, int nr, double E0, double inv_dE,
-    int first, double* __restrict__ normpart_row) {
+    int first, double* __restrict__ normpart, size_t n_wg_total, const int* __restrict__ counters,
+    int norm_rows) {
   using M = Mma<P>;
   using F = Fmt<P>;
   using E = typename F::E;
   constexpr int CH = Chunk<P>::CH;
   constexpr int RT = 16;
   extern __shared__ __align__(16) double lds[];
+  const int nrow_ix = counters[1];
+  double* __restrict__ normpart_row =
+      (nrow_ix >= 0 && nrow_ix < norm_rows) ? normpart + (size_t)nrow_ix * n_wg_total : nullptr;
   __shared__ double red[4];
   const int pk = find_packet(blk_start, n_pk, blockIdx.x);
   const int local = blockIdx.x - blk_start[pk];
@@ -516,7 +526,7 @@ __global__ __launch_bounds__(256) void k_radR_epi(
   for (int off = 32; off > 0; off >>= 1) nsum += __shfl_down(nsum, off, 64);
   if (l == 0) red[w] = nsum;
   __syncthreads();
-  if (threadIdx.x == 0) normpart_row[dsc.wg_off + local] = red[0] + red[1] + red[2] + red[3];
+  if (threadIdx.x == 0 && normpart_row) normpart_row[dsc.wg_off + local] = red[0] + red[1] + red[2] + red[3];
 }
 
 // Converts an FP64 operator table to compute format (planes ps elements apart).
@@ -593,4 +603,22 @@ __global__ __launch_bounds__(256) void k_accum_mfma(double* __restrict__ acc_all
   }
 }
 
+}  // namespace tdwp
+
+namespace tdwp {
+// Advances the device step counters after a step: ring row if slices were recorded,
+// norm-partial row always.
+__global__ void k_advance(int* counters, int recorded, int stepped) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    counters[0] += recorded;
+    counters[1] += stepped;
+  }
+}
+
+__global__ void k_set_counters(int* counters, int ring_row, int norm_row) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    counters[0] = ring_row;
+    counters[1] = norm_row;
+  }
+}
 }  // namespace tdwp

@@ -313,7 +313,11 @@ __global__ __launch_bounds__(256) void k_radR_epi_mlp(
     const typename Fmt<P>::E* __restrict__ Td, int ldt, int pst, MlpNet net,
     const double* __restrict__ rg, const double* __restrict__ Rg, const double* __restrict__ xg,
     double cB, double cC, const double* __restrict__ D, int ne, int ng, int nR, int nr,
-    double E0, double inv_dE, int first, double* __restrict__ normpart_row) {
+    double E0, double inv_dE, int first, double* __restrict__ normpart, size_t n_wg_total,
+    const int* __restrict__ counters, int norm_rows) {
+  const int nrow_ix = counters[1];
+  double* __restrict__ normpart_row =
+      (nrow_ix >= 0 && nrow_ix < norm_rows) ? normpart + (size_t)nrow_ix * n_wg_total : nullptr;
   using M = Mma<P>;
   using F = Fmt<P>;
   using E = typename F::E;
@@ -444,7 +448,7 @@ __global__ __launch_bounds__(256) void k_radR_epi_mlp(
   for (int off = 32; off > 0; off >>= 1) nsum += __shfl_down(nsum, off, 64);
   if (l == 0) red[w] = nsum;
   __syncthreads();
-  if (threadIdx.x == 0) normpart_row[dsc.wg_off + local] = red[0] + red[1] + red[2] + red[3];
+  if (threadIdx.x == 0 && normpart_row) normpart_row[dsc.wg_off + local] = red[0] + red[1] + red[2] + red[3];
 }
 
 }  // namespace tdwp

@@ -149,6 +149,13 @@ struct tdwp_plan_s {
   double* d_Rg = nullptr;
   double* d_xg = nullptr;
   size_t lds_radR_mlp = 0;
+  // device step counters ([0] ring row, [1] norm-partial row) and captured steps
+  int* d_counters = nullptr;
+  int norm_row = 0;
+  bool use_graphs = true;
+  hipGraphExec_t graph_exec[2] = {nullptr, nullptr};   // two steps, starting from cur = 0 / 1
+  hipGraph_t graph[2] = {nullptr, nullptr};
+  long graph_steps = 0;        // steps taken by graph replay (diagnostics)
   std::vector<void*> allocations;
 };
 

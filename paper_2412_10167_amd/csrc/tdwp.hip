@@ -63,9 +63,19 @@ int alloc_copy(Plan* P, T** dptr, const std::vector<T>& h) {
   return TDWP_OK;
 }
 
+void drop_graphs(Plan* P) {
+  for (int c = 0; c < 2; ++c) {
+    if (P->graph_exec[c]) (void)hipGraphExecDestroy(P->graph_exec[c]);
+    if (P->graph[c]) (void)hipGraphDestroy(P->graph[c]);
+    P->graph_exec[c] = nullptr;
+    P->graph[c] = nullptr;
+  }
+}
+
 void free_plan(Plan* P) {
   if (!P) return;
   if (P->stream) (void)hipStreamSynchronize(P->stream);
+  drop_graphs(P);
   for (void* a : P->allocations) (void)hipFree(a);
   if (P->own_stream && P->stream) (void)hipStreamDestroy(P->stream);
   delete P;
@@ -469,6 +479,9 @@ int layout_and_allocate(Plan* P) {
   TRY(alloc_copy(P, &dad, ad));
   P->d_accdesc = dad;
   TRY(dev_alloc(P, (void**)&P->d_E, P->packets.size() * sizeof(double)));
+  TRY(dev_alloc(P, (void**)&P->d_counters, 4 * sizeof(int)));
+  hipLaunchKernelGGL(k_set_counters, dim3(1), dim3(64), 0, P->stream, P->d_counters, 0, 0);
+  HIP_TRY(hipGetLastError());
   if (P->fast) {
     std::vector<PkDesc> pd;
     std::vector<int> ba(1, 0), br(1, 0);
@@ -523,6 +536,68 @@ int ensure_staging(Plan* P, double** buf, size_t* cap, size_t need) {
   return TDWP_OK;
 }
 
+// Angular-kernel tile width (16 nt columns): block prefix sums and LDS size.
+int set_ang_tiles(Plan* P, int nt) {
+  HIP_TRY(hipStreamSynchronize(P->stream));
+  const int prec = P->cfg.precision;
+  const size_t eb = elem_bytes(prec) * planes_of(prec);
+  const int kpa = round_up(P->ng / 2, (int)ks_of(prec));
+  int max_om = 0;
+  size_t ang_tab = 0;
+  for (auto& U : P->units) {
+    max_om = std::max(max_om, U.n_om);
+    ang_tab = std::max(ang_tab, (U.ang_U.size() + U.ang_ell.size()) * sizeof(double));
+  }
+  const int mt_per = (kpa + 15) / 16;
+  const int per_wave = (max_om * 2 * mt_per + 3) / 4;
+  const size_t lds = ((size_t)max_om * 2 * 16 * nt * ld_of(prec, kpa) * eb + 15) / 16 * 16 + ang_tab;
+  if (per_wave * nt > kAngMaxAcc || lds > kLdsMax) return TDWP_EINVAL;
+  std::vector<int> ba(1, 0);
+  const int nrt_a = (P->nr + 16 * nt - 1) / (16 * nt);
+  for (auto& pk : P->packets) {
+    (void)pk;
+    ba.push_back(ba.back() + nrt_a * P->nR * P->ne);
+  }
+  HIP_TRY(hipMemcpy(P->d_blk_ang, ba.data(), ba.size() * sizeof(int), hipMemcpyHostToDevice));
+  P->blocks_ang = ba.back();
+  P->nta = nt;
+  P->lds_ang = P->lds_ang_max = lds;
+  return TDWP_OK;
+}
+
+std::string tune_key(Plan* P) {
+  int max_om = 0;
+  for (auto& U : P->units) max_om = std::max(max_om, U.n_om);
+  char buf[160];
+  std::snprintf(buf, sizeof buf, "ang p%d r%d R%d g%d e%d om%d", P->cfg.precision, P->nr, P->nR,
+                P->ng, P->ne, max_om);
+  return buf;
+}
+
+// Cached tile choice from the file named by TDWP_TUNE_CACHE (lines "key=value").
+int cached_tile(Plan* P) {
+  const char* path = std::getenv("TDWP_TUNE_CACHE");
+  if (!path) return 0;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return 0;
+  const std::string key = tune_key(P) + "=";
+  char line[256];
+  int val = 0;
+  while (std::fgets(line, sizeof line, f))
+    if (std::strncmp(line, key.c_str(), key.size()) == 0) val = std::atoi(line + key.size());
+  std::fclose(f);
+  return val;
+}
+
+void store_tile(Plan* P, int nt) {
+  const char* path = std::getenv("TDWP_TUNE_CACHE");
+  if (!path) return;
+  FILE* f = std::fopen(path, "a");
+  if (!f) return;
+  std::fprintf(f, "%s=%d\n", tune_key(P).c_str(), nt);
+  std::fclose(f);
+}
+
 // ---- propagation -----------------------------------------------------------
 
 struct Timing {
@@ -558,6 +633,14 @@ int record_slices(Plan* P, int row) {
   return TDWP_OK;
 }
 
+// Mirrors the host's ring row and norm row into the device counters.
+int sync_counters(Plan* P) {
+  hipLaunchKernelGGL(k_set_counters, dim3(1), dim3(64), 0, P->stream, P->d_counters,
+                     P->ring_count, P->norm_row);
+  HIP_TRY(hipGetLastError());
+  return TDWP_OK;
+}
+
 int flush_ring(Plan* P) {
   if (P->ring_count == 0) return TDWP_OK;
   const tdwp_config& c = P->cfg;
@@ -585,7 +668,7 @@ int flush_ring(Plan* P) {
   HIP_TRY(hipGetLastError());
   P->ring_k0 += P->ring_count;
   P->ring_count = 0;
-  return TDWP_OK;
+  return sync_counters(P);
 }
 
 int take_snapshots(Plan* P) {
@@ -692,37 +775,32 @@ int prepare_record(Plan* P, Timing* T) {
   return TDWP_OK;
 }
 
+// Launches the kernels of one step of the matrix-core path (no host state change):
+// u_k in d_u[cur], u_{k-1} in d_u[1 - cur]; rec: record the slices of u_k.
 template <int PR>
-int fast_step(Plan* P, int chunk_row, Timing* T) {
+int enqueue_step(Plan* P, int cur, int first, int rec, Timing* T) {
   using HT = typename HType<PR>::T;
   using E = typename Fmt<PR>::E;
-  const int first = (P->k == 0) ? 1 : 0;
-  const double* uk = P->d_u[P->cur];
-  double* uo = P->d_u[1 - P->cur];
+  const double* uk = P->d_u[cur];
+  double* uo = P->d_u[1 - cur];
   HT* h = reinterpret_cast<HT*>(P->d_h);
   const int nr = P->nr, nR = P->nR, ng = P->ng, ne = P->ne;
   const int np = (int)P->packets.size();
   const PkDesc* pkd = (const PkDesc*)P->d_pkdesc;
-  const bool rec = P->rec_k < P->k;
-  if (rec) TRY(prepare_record(P, T));
   TRY(timed_begin(P, T));
   {
     const long nlines = (long)(P->n_total / nr);
     const int h2 = nr / 2;
-    SliceArgs sa{rec ? 1 : 0, 0, P->d_line_start, P->d_slice_off, np, nR, P->m_inf,
+    SliceArgs sa{rec, 0, P->d_line_start, P->d_slice_off, np, nR, P->m_inf,
                  P->d_flux_split, P->d_flux_split + h2, P->d_flux_split + 2 * h2,
-                 P->d_flux_split + 3 * h2, 1.0 / std::sqrt(P->dR),
-                 P->d_ring + (size_t)P->ring_count * P->slice_total};
+                 P->d_flux_split + 3 * h2, 1.0 / std::sqrt(P->dR), P->d_ring, P->slice_total,
+                 P->d_counters, P->ring_len};
     hipLaunchKernelGGL(k_radr<PR>, dim3((unsigned)((nlines + kRadrLines - 1) / kRadrLines)),
                        dim3(256), P->lds_radr, P->stream, uk, h, (const E*)P->d_TrsF,
                        (const E*)P->d_TrdF, P->nrhk, P->nrhk * P->nrhk, nr, nlines, sa);
   }
   HIP_TRY(hipGetLastError());
   TRY(timed_end(P, T, 4));
-  if (rec) {
-    P->ring_count += 1;
-    P->rec_k = P->k;
-  }
   TRY(timed_begin(P, T));
   {
     const int psp = (int)P->Pc.size();
@@ -746,22 +824,67 @@ int fast_step(Plan* P, int chunk_row, Timing* T) {
   HIP_TRY(hipGetLastError());
   TRY(timed_end(P, T, 0));
   TRY(timed_begin(P, T));
-  double* nrow = P->d_normpart + (size_t)chunk_row * P->n_wg_total;
   if (P->pot_mode == TDWP_POT_MLP) {
     const double mbc = P->cfg.mass_B + P->cfg.mass_C;
     hipLaunchKernelGGL(k_radR_epi_mlp<PR>, dim3(P->blocks_radR), dim3(256), P->lds_radR_mlp,
                        P->stream, uk, uo, h, pkd, P->d_blk_radR, np, (const E*)P->d_TRsF,
                        (const E*)P->d_TRdF, P->nRhk, P->nRhk * P->nRhk, mlp_net(P), P->d_rg,
                        P->d_Rg, P->d_xg, P->cfg.mass_C / mbc, P->cfg.mass_B / mbc, P->d_D, ne, ng,
-                       nR, nr, P->E0, 1.0 / P->dE, first, nrow);
+                       nR, nr, P->E0, 1.0 / P->dE, first, P->d_normpart, P->n_wg_total,
+                       (const int*)P->d_counters, kNormChunk);
   } else {
     hipLaunchKernelGGL(k_radR_epi<PR>, dim3(P->blocks_radR), dim3(256), P->lds_radR, P->stream,
                        uk, uo, h, pkd, P->d_blk_radR, np, (const E*)P->d_TRsF,
                        (const E*)P->d_TRdF, P->nRhk, P->nRhk * P->nRhk, P->d_V, P->d_D, ne, ng,
-                       nR, nr, P->E0, 1.0 / P->dE, first, nrow);
+                       nR, nr, P->E0, 1.0 / P->dE, first, P->d_normpart, P->n_wg_total,
+                       (const int*)P->d_counters, kNormChunk);
   }
+  hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, P->stream, P->d_counters, rec, 1);
   HIP_TRY(hipGetLastError());
   TRY(timed_end(P, T, 1));
+  return TDWP_OK;
+}
+
+template <int PR>
+int fast_step(Plan* P, int chunk_row, Timing* T) {
+  (void)chunk_row;
+  const int first = (P->k == 0) ? 1 : 0;
+  const bool rec = P->rec_k < P->k;
+  if (rec) TRY(prepare_record(P, T));
+  TRY(enqueue_step<PR>(P, P->cur, first, rec ? 1 : 0, T));
+  if (rec) {
+    P->ring_count += 1;
+    P->rec_k = P->k;
+  }
+  P->norm_row += 1;
+  return TDWP_OK;
+}
+
+// Two steady-state steps (slices recorded, not the first step) captured once per
+// buffer parity and replayed; every per-step argument lives in the device counters.
+template <int PR>
+int graph_two_steps(Plan* P) {
+  const int c = P->cur;
+  if (!P->graph_exec[c]) {
+    HIP_TRY(hipStreamBeginCapture(P->stream, hipStreamCaptureModeThreadLocal));
+    int st = enqueue_step<PR>(P, c, 0, 1, nullptr);
+    if (st == TDWP_OK) st = enqueue_step<PR>(P, 1 - c, 0, 1, nullptr);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(P->stream, &g);
+    if (st != TDWP_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return st;
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture", __LINE__);
+    P->graph[c] = g;
+    HIP_TRY(hipGraphInstantiate(&P->graph_exec[c], g, nullptr, nullptr, 0));
+  }
+  HIP_TRY(hipGraphLaunch(P->graph_exec[c], P->stream));
+  P->ring_count += 2;
+  P->rec_k = P->k + 1;
+  P->k += 2;
+  P->norm_row += 2;
+  P->graph_steps += 2;
   return TDWP_OK;
 }
 
@@ -831,12 +954,13 @@ int record_via_radr(Plan* P) {
   const long nlines = (long)(P->n_total / nr);
   SliceArgs sa{1, 1, P->d_line_start, P->d_slice_off, (int)P->packets.size(), P->nR, P->m_inf,
                P->d_flux_split, P->d_flux_split + h2, P->d_flux_split + 2 * h2,
-               P->d_flux_split + 3 * h2, 1.0 / std::sqrt(P->dR),
-               P->d_ring + (size_t)P->ring_count * P->slice_total};
+               P->d_flux_split + 3 * h2, 1.0 / std::sqrt(P->dR), P->d_ring, P->slice_total,
+               P->d_counters, P->ring_len};
   hipLaunchKernelGGL(k_radr<PR>, dim3((unsigned)((nlines + kRadrLines - 1) / kRadrLines)),
                      dim3(256), P->lds_radr, P->stream, P->d_u[P->cur],
                      reinterpret_cast<typename HType<PR>::T*>(P->d_h), (const E*)P->d_TrsF,
                      (const E*)P->d_TrdF, P->nrhk, P->nrhk * P->nrhk, nr, nlines, sa);
+  hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, P->stream, P->d_counters, 1, 0);
   HIP_TRY(hipGetLastError());
   return TDWP_OK;
 }
@@ -862,6 +986,16 @@ int finish_slices(Plan* P, Timing* T) {
   return TDWP_OK;
 }
 
+// Whether the next two steps are steady state: matrix-core path, not the first
+// step, slices recorded in both, no ring flush or elastic snapshot in between.
+bool graph_ready(Plan* P, int left, Timing* T) {
+  if (!P->use_graphs || !P->fast || T || left < 2 || P->k < 1) return false;
+  if (P->rec_k >= P->k || P->ring_count + 2 > P->ring_len) return false;
+  for (auto& pk : P->packets)
+    if (!pk.snap_taken && (pk.pk.k_min_elastic == P->k || pk.pk.k_min_elastic == P->k + 1)) return false;
+  return true;
+}
+
 int run_steps(Plan* P, long n_steps, double* norms_out, Timing* T) {
   if (!P->have_potential) return TDWP_ESTATE;
   for (auto& pk : P->packets)
@@ -871,7 +1005,22 @@ int run_steps(Plan* P, long n_steps, double* norms_out, Timing* T) {
   long done = 0;
   while (done < n_steps) {
     const int chunk = (int)std::min<long>(kNormChunk, n_steps - done);
-    for (int s = 0; s < chunk; ++s) TRY(one_step(P, s, T));
+    P->norm_row = 0;
+    if (P->fast) TRY(sync_counters(P));
+    for (int s = 0; s < chunk;) {
+      if (graph_ready(P, chunk - s, T)) {
+        switch (P->cfg.precision) {
+          case TDWP_FP64: TRY(graph_two_steps<kP64>(P)); break;
+          case TDWP_FP32: TRY(graph_two_steps<kP32>(P)); break;
+          case TDWP_BF16X3: TRY(graph_two_steps<kPBF>(P)); break;
+          default: TRY(graph_two_steps<kPF16>(P)); break;
+        }
+        s += 2;
+      } else {
+        TRY(one_step(P, s, T));
+        s += 1;
+      }
+    }
     const int nq = np * chunk;
     hipLaunchKernelGGL(k_norm_reduce, dim3((nq + 255) / 256), dim3(256), 0, P->stream,
                        P->d_norms, P->d_normpart, P->n_wg_total, P->d_wg_off, P->d_n_wg,
@@ -897,6 +1046,7 @@ int run_steps(Plan* P, long n_steps, double* norms_out, Timing* T) {
 void reset_propagation(Plan* P) {
   P->k = 0;
   P->rec_k = -1;
+  P->norm_row = 0;
   P->cur = 0;
   P->ring_count = 0;
   P->ring_k0 = 0;
@@ -930,6 +1080,7 @@ int tdwp_plan(const tdwp_config* cfg, tdwp_plan_t* out) {
   P->units_in.assign(cfg->units, cfg->units + cfg->n_units);
   P->cfg.units = nullptr;
   P->bounds_given = !(cfg->e_min == 0 && cfg->e_max == 0);
+  P->use_graphs = std::getenv("TDWP_NO_GRAPHS") == nullptr;
   if (cfg->stream) {
     P->stream = (hipStream_t)cfg->stream;
   } else {
@@ -944,6 +1095,10 @@ int tdwp_plan(const tdwp_config* cfg, tdwp_plan_t* out) {
   if (st != TDWP_OK) {
     free_plan(P);
     return st;
+  }
+  if (P->fast) {
+    const int nt = cached_tile(P);
+    if (nt == 1 || nt == 2 || nt == 4) (void)set_ang_tiles(P, nt);
   }
   if (P->bounds_given) {
     P->e_min = cfg->e_min;
@@ -1004,6 +1159,7 @@ int tdwp_set_potential(tdwp_plan_t p, int mode, const double* v, size_t n_values
   HIP_TRY(hipMemcpyAsync(p->d_V, v, n_values * sizeof(double), hipMemcpyHostToDevice, p->stream));
   HIP_TRY(hipStreamSynchronize(p->stream));
   if (!p->bounds_given) TRY(bounds_from_table(p, v));
+  drop_graphs(p);
   p->pot_mode = TDWP_POT_TABLE;
   p->have_potential = true;
   reset_propagation(p);
@@ -1122,7 +1278,9 @@ int tdwp_set_initial_packet(tdwp_plan_t p, const tdwp_packet* pk, const double* 
   HIP_TRY(hipMemcpyAsync(p->d_E + ip, &pk->E_v0j0, sizeof(double), hipMemcpyHostToDevice, p->stream));
   // k = 0 slices into ring row 0 (packets not yet set are overwritten when they are)
   p->ring_count = 0;
+  p->norm_row = 0;
   if (p->fast) {
+    TRY(sync_counters(p));
     switch (p->cfg.precision) {
       case TDWP_FP64: TRY(record_via_radr<kP64>(p)); break;
       case TDWP_FP32: TRY(record_via_radr<kP32>(p)); break;
@@ -1253,6 +1411,90 @@ int tdwp_time_kernels(tdwp_plan_t p, long n_steps, int n_max, double* avg_us, ch
   return 5;
 }
 
+int tdwp_autotune(tdwp_plan_t p, int steps, char* report, size_t report_len) {
+  if (!p || steps < 1) return TDWP_EINVAL;
+  if (!p->have_potential) return TDWP_ESTATE;
+  for (auto& pk : p->packets)
+    if (pk.set) return TDWP_ESTATE;
+  if (!p->fast) return TDWP_OK;
+  Timing T;
+  HIP_TRY(hipEventCreate(&T.ev[0]));
+  HIP_TRY(hipEventCreate(&T.ev[1]));
+  // the timed steps run on zeroed buffers (no packet is installed yet)
+  HIP_TRY(hipMemsetAsync(p->d_u[0], 0, p->n_total * sizeof(double), p->stream));
+  HIP_TRY(hipMemsetAsync(p->d_u[1], 0, p->n_total * sizeof(double), p->stream));
+  std::string rep;
+  int best = p->nta;
+  double best_us = 1e300;
+  for (int nt : {4, 2, 1}) {
+    if (set_ang_tiles(p, nt) != TDWP_OK) continue;
+    T.ms[0] = 0.0;
+    T.calls[0] = 0;
+    reset_propagation(p);
+    int st = sync_counters(p);
+    for (int s2 = 0; s2 < steps + 1 && st == TDWP_OK; ++s2) {   // the first step warms up
+      if (s2 == 1) {
+        T.ms[0] = 0.0;
+        T.calls[0] = 0;
+      }
+      st = one_step(p, 0, &T);
+    }
+    reset_propagation(p);
+    if (st != TDWP_OK) {
+      (void)hipEventDestroy(T.ev[0]);
+      (void)hipEventDestroy(T.ev[1]);
+      return st;
+    }
+    const double us = 1000.0 * T.ms[0] / std::max<long>(T.calls[0], 1);
+    char buf[64];
+    std::snprintf(buf, sizeof buf, "%sang_nt=%d:%.1fus", rep.empty() ? "" : ";", nt, us);
+    rep += buf;
+    if (us < best_us) {
+      best_us = us;
+      best = nt;
+    }
+  }
+  (void)hipEventDestroy(T.ev[0]);
+  (void)hipEventDestroy(T.ev[1]);
+  TRY(set_ang_tiles(p, best));
+  store_tile(p, best);
+  drop_graphs(p);
+  reset_propagation(p);
+  if (report && report_len) {
+    rep += ";chosen=" + std::to_string(best);
+    std::strncpy(report, rep.c_str(), report_len - 1);
+    report[report_len - 1] = 0;
+  }
+  return TDWP_OK;
+}
+
+int tdwp_set_option(tdwp_plan_t p, int option, long value) {
+  if (!p) return TDWP_EINVAL;
+  switch (option) {
+    case TDWP_OPT_GRAPHS:
+      if (value != 0 && value != 1) return TDWP_EINVAL;
+      p->use_graphs = value != 0;
+      return TDWP_OK;
+    case TDWP_OPT_ANG_TILE:
+      if (!p->fast || (value != 1 && value != 2 && value != 4)) return TDWP_EINVAL;
+      TRY(set_ang_tiles(p, (int)value));
+      drop_graphs(p);
+      return TDWP_OK;
+    default:
+      return TDWP_EINVAL;
+  }
+}
+
+int tdwp_get_stat(tdwp_plan_t p, int stat, long* value) {
+  if (!p || !value) return TDWP_EINVAL;
+  switch (stat) {
+    case TDWP_STAT_GRAPH_STEPS: *value = p->graph_steps; return TDWP_OK;
+    case TDWP_STAT_ANG_TILE: *value = p->fast ? p->nta : 0; return TDWP_OK;
+    case TDWP_STAT_MATRIX_CORE_PATH: *value = p->fast ? 1 : 0; return TDWP_OK;
+    default: return TDWP_EINVAL;
+  }
+}
+
 int tdwp_mlp_n_params(tdwp_plan_t p) {
   if (!p) return TDWP_EINVAL;
   return mlp_param_count(p->npair);
@@ -1369,6 +1611,7 @@ int tdwp_set_potential_mlp(tdwp_plan_t p, const double* v, size_t n_values,
     report[1] = std::sqrt(se / (double)vm.size());
     report[2] = mx;
   }
+  drop_graphs(p);
   p->pot_mode = TDWP_POT_MLP;
   p->have_potential = true;
   reset_propagation(p);

@@ -14,7 +14,8 @@ def potential_table(plan, spec):
     return diabatic_matrix(spec, r[None, None, :], R[None, :, None], x[:, None, None])
 
 
-def build(spec, precision="fp64", bounds=None, stream="current", vtable=None, mlp=None):
+def build(spec, precision="fp64", bounds=None, stream="current", vtable=None, mlp=None,
+          autotune=0):
     """Plan + potential + every initial packet.  Returns (plan, info) where info
     holds the grid, E_v0j0 per packet and the initial channel functions.
     mlp: None (tabulated potential) or a dict of set_potential_mlp arguments
@@ -29,6 +30,8 @@ def build(spec, precision="fp64", bounds=None, stream="current", vtable=None, ml
         plan.set_potential(vtable)
     else:
         info["mlp_report"] = plan.set_potential_mlp(vtable, **mlp)
+    if autotune:
+        info["autotune"] = plan.autotune(autotune)
     for pk in spec["packets"]:
         va = asymptotic_potential(spec, r, pk["elec0"])
         e, chi = plan.diatomic_states(va, pk["j0"], pk["v0"] + 1)

@@ -16,8 +16,11 @@ EXPORTED_SYMBOLS = (
     "tdwp_spectral_bounds", "tdwp_set_initial_packet", "tdwp_propagate", "tdwp_step_index",
     "tdwp_get_packet", "tdwp_state_to_state", "tdwp_time_kernels", "tdwp_destroy",
     "tdwp_strerror", "tdwp_mlp_n_params", "tdwp_set_potential_mlp", "tdwp_mlp_params",
-    "tdwp_mlp_gradient", "tdwp_mlp_eval", "tdwp_mlp_grid",
+    "tdwp_mlp_gradient", "tdwp_mlp_eval", "tdwp_mlp_grid", "tdwp_autotune",
+    "tdwp_set_option", "tdwp_get_stat",
 )
+OPTIONS = {"graphs": 0, "ang_tile": 1}
+STATS = {"graph_steps": 0, "ang_tile": 1, "matrix_core_path": 2}
 
 
 class TdwpError(RuntimeError):
@@ -107,6 +110,9 @@ def load_library():
     lib.tdwp_mlp_gradient.argtypes = [P, fp, ctypes.c_int, dp, dp, dp, fp]
     lib.tdwp_mlp_eval.argtypes = [P, ctypes.c_int, dp, dp]
     lib.tdwp_mlp_grid.argtypes = [P, dp]
+    lib.tdwp_autotune.argtypes = [P, ctypes.c_int, ctypes.c_char_p, ctypes.c_size_t]
+    lib.tdwp_set_option.argtypes = [P, ctypes.c_int, ctypes.c_long]
+    lib.tdwp_get_stat.argtypes = [P, ctypes.c_int, ctypes.POINTER(ctypes.c_long)]
     lib.tdwp_destroy.argtypes = [P]
     lib.tdwp_destroy.restype = None
     lib.tdwp_strerror.argtypes = [ctypes.c_int]
@@ -299,6 +305,21 @@ class Plan:
         out = np.empty((d.shape[0], self.spec["n_elec"] * (self.spec["n_elec"] + 1) // 2))
         _check(self.lib.tdwp_mlp_eval(self.handle, d.shape[0], _ptr(d), _ptr(out)), "tdwp_mlp_eval")
         return out
+
+    def set_option(self, name, value):
+        _check(self.lib.tdwp_set_option(self.handle, OPTIONS[name], int(value)), "tdwp_set_option")
+
+    def stat(self, name):
+        v = ctypes.c_long()
+        _check(self.lib.tdwp_get_stat(self.handle, STATS[name], ctypes.byref(v)), "tdwp_get_stat")
+        return v.value
+
+    def autotune(self, steps=5):
+        """Times the tile variants of the step kernels and keeps the fastest (call
+        before setting packets).  Returns the report text."""
+        buf = ctypes.create_string_buffer(512)
+        _check(self.lib.tdwp_autotune(self.handle, steps, buf, 512), "tdwp_autotune")
+        return buf.value.decode()
 
     def mlp_grid(self):
         s = self.spec

@@ -252,3 +252,56 @@ def test_errors_are_reported():
                                          chi=np.zeros(spec["n_r"]))])
     assert e.value.code == -1
     plan.close()
+
+
+def test_graph_replay_bit_identical_to_direct_launches():
+    banner("HIP graph replay == direct launches (bit-exact), config-1 shape")
+    spec = config(1)
+    spec["steps"] = 700
+    problem = _problem()
+    a, _ = problem.build(spec)
+    b, _ = problem.build(spec)
+    b.set_option("graphs", 0)
+    na = a.propagate(300)
+    na2 = a.propagate(400)
+    nb = b.propagate(700)
+    assert a.stat("graph_steps") > 500 and b.stat("graph_steps") == 0
+    assert np.array_equal(np.concatenate([na, na2], axis=1), nb)
+    assert np.array_equal(a.get_packet(0, 0, 0), b.get_packet(0, 0, 0))
+    chans = problem.channels(a, spec, 0, 4, 1)
+    pa, pb = a.state_to_state(0, 0, chans), b.state_to_state(0, 0, chans)
+    assert np.array_equal(pa[0], pb[0]) and np.array_equal(pa[1], pb[1])
+    a.close()
+    b.close()
+
+
+@pytest.mark.parametrize("nt", [1, 2, 4])
+def test_angular_tile_variants(nt):
+    banner(f"angular tile {nt}: J=0 24x20x10 and J=5 Omega 1..3 2 states")
+    problem = _problem()
+    for spec in (small_variant(1, n_R=24, n_r=20, n_gamma=10), _coriolis_spec(5, 1, 3, 2)):
+        plan, _ = problem.build(spec)
+        try:
+            plan.set_option("ang_tile", nt)
+        except Exception:
+            plan.close()
+            continue    # variant not feasible for this shape
+        K = 40
+        plan.propagate(K)
+        op, ref = oracle_packets(spec, K, keep=(K,))
+        assert rel_err(plan.get_packet(0, 0, 0), ref[(0, 0)][0]["vectors"][K]) < PKT_TOL
+        assert plan.stat("ang_tile") == nt
+        plan.close()
+
+
+def test_autotune_then_parity():
+    banner("autotune before packets, then FP64 parity")
+    spec = _coriolis_spec(4, 1, 4, 3, cfg=5)
+    problem = _problem()
+    plan, info = problem.build(spec, autotune=2)
+    print("[result] autotune", info["autotune"], flush=True)
+    K = 30
+    plan.propagate(K)
+    op, ref = oracle_packets(spec, K, keep=(K,))
+    assert rel_err(plan.get_packet(0, 0, 0), ref[(0, 0)][0]["vectors"][K]) < PKT_TOL
+    plan.close()
