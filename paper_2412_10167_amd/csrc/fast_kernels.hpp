@@ -11,8 +11,8 @@
 // or d (c = 1).  This halves the arithmetic of every dense contraction.
 //
 // Passes per packet and step (Sec. 2.1 items 1-5, Sec. 2.2 Eq. wvp-k):
-//   k_radr<P>      h  = T_r u                       (lines along r)
-//   k_ang<P>       h += angular + Coriolis terms    (per R, r tile, elec)
+//   k_ang<P>       h  = angular + Coriolis terms    (per R, r tile, elec)
+//   k_radr<P>      h += T_r u                       (lines along r)
 //   k_radR_epi<P>  u_{k+1} = D(2 (T_R u + h + V u - E0 u)/dE - D u_{k-1})
 //                  (first step: D (...)/dE), plus one norm partial per workgroup.
 #pragma once
@@ -34,6 +34,8 @@ struct PkDesc {
   const int* ell_off;
   const int* n_om_j;
   int n_U, n_ell;         // sizes of U and ell (staged into LDS by k_ang)
+  const float* Uf;        // FP32 copies (register mixing of the mixed forms)
+  const float* ellf;
 };
 
 // Index p with start[p] <= b < start[p + 1] (start has n + 1 entries).
@@ -57,7 +59,7 @@ template <int P> __host__ __device__ constexpr int tile_ld(int kp) {
   return kp + (P == kPBF || P == kPF16 ? 8 : 1);
 }
 
-// ---- h = T_r u along r --------------------------------------------------------
+// ---- h += T_r u along r (h holds the angular terms already) ----------------------
 // One workgroup per 32 lines (2 M-tiles) of length n_r.  LDS holds the sum and
 // difference halves of the lines in compute format; the half-size operators come
 // from global tables in compute format (symmetric, so their rows are the
@@ -80,6 +82,7 @@ struct SliceArgs {
   size_t ring_stride;
   const int* counters;             // device step counters: [0] ring row, [1] norm row
   int ring_len;                    // rows of the ring (a counter outside 0..ring_len-1 records nothing)
+  const int* blk_pk;               // packet holding the first line of each workgroup
 };
 
 template <int P>
@@ -104,57 +107,82 @@ __global__ __launch_bounds__(256) void k_radr(const double* __restrict__ u,
   const int crow = sa.record ? sa.counters[0] : -1;
   const bool rec_ok = crow >= 0 && crow < sa.ring_len;
   double* ring_row = rec_ok ? sa.ring_base + (size_t)crow * sa.ring_stride : nullptr;
-  // wave w loads lines w, w+4, ...; lanes run along the half line
-  for (int li = threadIdx.x >> 6; li < kRadrLines; li += 4) {
-    const long gl = line0 + li;
-    const double* p = u + gl * nr;
-    int pkx = 0;
-    long local = 0;
-    bool rinf = false;
-    if (rec_ok && gl < nlines) {
-      int lo = 0, hi = sa.n_pk - 1;
-      while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (sa.line_start[mid] <= gl) lo = mid;
-        else hi = mid - 1;
+  // wave w loads lines w, w+4, ...; lanes run along the half line; the loads of
+  // a group of G lines are issued before any of them is used
+  constexpr int LPW = kRadrLines / 4;
+  constexpr int G = 4;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int pk0 = rec_ok ? sa.blk_pk[blockIdx.x] : 0;
+#pragma unroll 1
+  for (int g0 = 0; g0 < LPW; g0 += G) {
+    int pkx[G];
+    int lidx[G];
+    bool rinf[G];
+    double sv[G], sd[G];
+#pragma unroll
+    for (int q = 0; q < G; ++q) {
+      const long gl = line0 + wv + 4 * (g0 + q);
+      pkx[q] = 0;
+      lidx[q] = 0;
+      rinf[q] = false;
+      sv[q] = sd[q] = 0.0;
+      if (rec_ok && gl < nlines) {
+        int pp = pk0;
+        while (pp + 1 < sa.n_pk && sa.line_start[pp + 1] <= gl) ++pp;
+        pkx[q] = pp;
+        lidx[q] = (int)(gl - sa.line_start[pp]);
+        rinf[q] = (lidx[q] % sa.nR) == sa.m_inf;
       }
-      pkx = lo;
-      local = gl - sa.line_start[lo];
-      rinf = (local % sa.nR) == sa.m_inf;
     }
-    double sv = 0.0, sd = 0.0;
-    double* wline = nullptr;
-    if (rinf) {
-      const long nsv = sa.line_start[pkx + 1] - sa.line_start[pkx];
-      wline = ring_row + sa.slice_off[pkx] + 2 * nsv + (local / sa.nR) * nr;
-    }
-    for (int k = threadIdx.x & 63; k < kp; k += 64) {
-      double a = 0.0, b = 0.0;
-      if (gl < nlines && k < nh) {
-        a = p[k];
-        b = p[nr - 1 - k];
-        if (rec_ok) {
-          sv += sa.a_s[k] * (a + b) + sa.a_d[k] * (a - b);
-          sd += sa.d_s[k] * (a + b) + sa.d_d[k] * (a - b);
-          if (rinf) {
+    for (int kc = 0; kc < kp; kc += 64) {
+      const int k = kc + lane;
+      const int kcl = k < nh ? k : nh - 1;   // loads use clamped, in-range addresses
+      double av[G], bv[G];
+#pragma unroll
+      for (int q = 0; q < G; ++q) {
+        long gl = line0 + wv + 4 * (g0 + q);
+        gl = gl < nlines ? gl : nlines - 1;
+        av[q] = u[gl * nr + kcl];
+        bv[q] = u[gl * nr + nr - 1 - kcl];
+      }
+#pragma unroll
+      for (int q = 0; q < G; ++q) {
+        const int li = wv + 4 * (g0 + q);
+        const long gl = line0 + li;
+        const bool ok = gl < nlines && k < nh;
+        const double a = ok ? av[q] : 0.0, b = ok ? bv[q] : 0.0;
+        if (rec_ok && gl < nlines && k < nh) {
+          sv[q] += sa.a_s[k] * (a + b) + sa.a_d[k] * (a - b);
+          sd[q] += sa.d_s[k] * (a + b) + sa.d_d[k] * (a - b);
+          if (rinf[q]) {
+            const long nsv = sa.line_start[pkx[q] + 1] - sa.line_start[pkx[q]];
+            double* wline = ring_row + sa.slice_off[pkx[q]] + 2 * nsv + (lidx[q] / sa.nR) * nr;
             wline[k] = a * sa.inv_sqrt_dR;
             wline[nr - 1 - k] = b * sa.inv_sqrt_dR;
           }
         }
+        if (k < kp) {
+          F::put(S, ps, li * ld + k, a + b);
+          F::put(Dd, ps, li * ld + k, a - b);
+        }
       }
-      F::put(S, ps, li * ld + k, a + b);
-      F::put(Dd, ps, li * ld + k, a - b);
     }
-    if (rec_ok && gl < nlines) {
-      for (int off = 32; off > 0; off >>= 1) {
-        sv += __shfl_down(sv, off, 64);
-        sd += __shfl_down(sd, off, 64);
-      }
-      if ((threadIdx.x & 63) == 0) {
-        const long nsv = sa.line_start[pkx + 1] - sa.line_start[pkx];
-        double* out = ring_row + sa.slice_off[pkx];
-        out[local] = sv;
-        out[nsv + local] = sd;
+    if (rec_ok) {
+#pragma unroll
+      for (int q = 0; q < G; ++q) {
+        const long gl = line0 + wv + 4 * (g0 + q);
+        if (gl >= nlines) continue;
+        double x = sv[q], y = sd[q];
+        for (int off = 32; off > 0; off >>= 1) {
+          x += __shfl_down(x, off, 64);
+          y += __shfl_down(y, off, 64);
+        }
+        if (lane == 0) {
+          const long nsv = sa.line_start[pkx[q] + 1] - sa.line_start[pkx[q]];
+          double* out = ring_row + sa.slice_off[pkx[q]];
+          out[lidx[q]] = x;
+          out[nsv + lidx[q]] = y;
+        }
       }
     }
   }
@@ -166,6 +194,20 @@ __global__ __launch_bounds__(256) void k_radr(const double* __restrict__ u,
   const E* Sw = S + 16 * mt * ld;
   const E* Dw = Dd + 16 * mt * ld;
   for (int nt = (w >> 1); nt < NT; nt += 2) {
+    // the angular pass has written h already: read this lane's 8 values first
+    // (clamped, in-range addresses; outputs outside the range are skipped below)
+    typename HType<P>::T hp[4], hm[4];
+    {
+      int a = nt * 16 + (l & 15);
+      a = a < nh ? a : nh - 1;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        long gl = line0 + 16 * mt + M::row(l, v);
+        gl = gl < nlines ? gl : nlines - 1;
+        hp[v] = h[gl * nr + a];
+        hm[v] = h[gl * nr + nr - 1 - a];
+      }
+    }
     typename M::acc_t cs = M::zero(), cd = M::zero();
     const E* Bs = Ts + (size_t)nt * 16 * ldt;
     const E* Bd = Td + (size_t)nt * 16 * ldt;
@@ -191,14 +233,127 @@ __global__ __launch_bounds__(256) void k_radr(const double* __restrict__ u,
       if (gl < nlines && a < nh) {
         const double ys = (double)cs[v] * M::kUnscale;
         const double yd = (double)cd[v] * M::kUnscale;
-        h[gl * nr + a] = (typename HType<P>::T)(ys + yd);
-        h[gl * nr + nr - 1 - a] = (typename HType<P>::T)(ys - yd);
+        h[gl * nr + a] = (typename HType<P>::T)((double)hp[v] + ys + yd);
+        h[gl * nr + nr - 1 - a] = (typename HType<P>::T)((double)hm[v] + ys - yd);
       }
     }
   }
 }
 
-// ---- h += angular + Coriolis terms -----------------------------------------------
+// Loads the sums / differences of mirrored Gauss-Legendre nodes of every helicity of
+// one (R index m, r tile, elec le) column block: X[o][class][t][k] in compute format.
+// (Helicity, node pair) items of a thread's column are loaded 8 at a time from
+// clamped, in-range addresses.
+template <int P, int RT>
+__device__ __forceinline__ void ang_load(typename Fmt<P>::E* __restrict__ X,
+                                         const double* __restrict__ u, int n_om, int ne, int le,
+                                         int ng, int kpa, int ld, int tile, int ps, int m,
+                                         int i0, int nr, size_t plane) {
+  using F = Fmt<P>;
+  const int ngh = ng >> 1;
+  const int t = threadIdx.x % RT, k_first = threadIdx.x / RT;
+  constexpr int kstep = 256 / RT;
+  constexpr int B = 8;
+  const int i = i0 + t;
+  const bool okc = i < nr;
+  const double* ub = u + (size_t)m * nr + (okc ? i : nr - 1);
+  const int n_items = n_om * kpa;
+  const float inv_kpa = 1.0f / (float)kpa;   // exact quotients: items < 2^13
+  for (int it0 = k_first; it0 < n_items; it0 += kstep * B) {
+    double av[B], bv[B];
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+      int it = it0 + kstep * b;
+      it = it < n_items ? it : n_items - 1;
+      const int o = (int)(((float)it + 0.5f) * inv_kpa);
+      int k = it - o * kpa;
+      k = k < ngh ? k : ngh - 1;
+      const size_t col = (size_t)(o * ne + le) * ng;
+      av[b] = ub[(col + k) * plane];
+      bv[b] = ub[(col + ng - 1 - k) * plane];
+    }
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+      const int it = it0 + kstep * b;
+      if (it < n_items) {
+        const int o = (int)(((float)it + 0.5f) * inv_kpa);
+        const int k = it - o * kpa;
+        const bool ok = okc && k < ngh;
+        const double a = ok ? av[b] : 0.0, bb = ok ? bv[b] : 0.0;
+        F::put(X + (o * 2 + 0) * tile + t * ld, ps, k, a + bb);
+        F::put(X + (o * 2 + 1) * tile + t * ld, ps, k, a - bb);
+      }
+    }
+  }
+}
+
+__device__ __forceinline__ int n_class(int ng, int Om, int c) {
+  const int top = ng - 1 - (Om + c);
+  return top >= 0 ? top / 2 + 1 : 0;
+}
+
+// Back transform FBR -> DVR of one column block and the h stores:
+// H_c[o][n'][t] = sum_jj PcT[Omega][c][n'][jj] C[o][c][t][jj] (C in X's place),
+// h[n'] = H_0 + H_1, h[ng-1-n'] = H_0 - H_1.
+template <int P, int NT>
+__device__ __forceinline__ void ang_back(const typename Fmt<P>::E* __restrict__ X,
+                                         typename HType<P>::T* __restrict__ h,
+                                         const typename Fmt<P>::E* __restrict__ PcT, size_t tab,
+                                         int ngk, int psp, int n_om, int om_lo, int ne, int le,
+                                         int ng, int ld, int tile, int ps, int m, int i0, int nr,
+                                         size_t plane) {
+  using M = Mma<P>;
+  using F = Fmt<P>;
+  using E = typename F::E;
+  constexpr int CH = Chunk<P>::CH;
+  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int ngh = ng >> 1;
+  const int NTh = (ngh + 15) >> 4;
+  for (int it = w; it < n_om * NTh; it += 4) {
+    const int o = it / NTh, mt = it % NTh;
+    const int Om = om_lo + o;
+    const int nj0 = n_class(ng, Om, 0), nj1 = n_class(ng, Om, 1);
+    const int kb = round_up(nj0 > nj1 ? nj0 : nj1, M::KS);
+    typename M::acc_t acc[2][NT];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const E* Ab = PcT + (size_t)(Om * 2 + c) * tab + (size_t)mt * 16 * ngk;
+      const E* Bb = X + (o * 2 + c) * tile;
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) acc[c][nt] = M::zero();
+      for (int k0 = 0; k0 < kb; k0 += CH * M::KS) {
+        typename M::frag_t fa[CH];
+#pragma unroll
+        for (int q = 0; q < CH; ++q)
+          if (k0 + q * M::KS < kb) fa[q] = F::frag(Ab, ngk, psp, l, k0 + q * M::KS);
+#pragma unroll
+        for (int q = 0; q < CH; ++q)
+          if (k0 + q * M::KS < kb) {
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt)
+              M::mma(acc[c][nt], fa[q], F::frag(Bb + nt * 16 * ld, ld, ps, l, k0 + q * M::KS));
+          }
+      }
+    }
+    const size_t col = (size_t)(o * ne + le) * ng;
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+      const int i = i0 + nt * 16 + (l & 15);
+      if (i >= nr) continue;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int n = mt * 16 + M::row(l, v);
+        if (n >= ngh) continue;
+        const double h0 = (double)acc[0][nt][v] * M::kUnscale;
+        const double h1 = (double)acc[1][nt][v] * M::kUnscale;
+        h[(col + n) * plane + (size_t)m * nr + i] = (typename HType<P>::T)(h0 + h1);
+        h[(col + ng - 1 - n) * plane + (size_t)m * nr + i] = (typename HType<P>::T)(h0 - h1);
+      }
+    }
+  }
+}
+
+// ---- h = angular + Coriolis terms (the first pass of a step) ---------------------
 // One workgroup per (r tile of 16 NT columns, R index m, elec l) of one packet,
 // all helicities.  Pc / PcT: [omega][class][jj][n'] and [omega][class][n'][jj]
 // with P^omega[omega + class + 2 jj][n'] (n' < ng/2), compute format, zero padded
@@ -206,11 +361,6 @@ __global__ __launch_bounds__(256) void k_radr(const double* __restrict__ u,
 // nodes) are replaced by the FBR coefficients C[o][class][t][jj] once every wave
 // has finished reading them (forward results are held in registers meanwhile).
 constexpr int kAngMaxAcc = 12;   // 16x16 accumulators per wave held across the barrier
-
-__device__ __forceinline__ int n_class(int ng, int Om, int c) {
-  const int top = ng - 1 - (Om + c);
-  return top >= 0 ? top / 2 + 1 : 0;
-}
 
 template <int P, int NT, int MAXOM>
 __global__ __launch_bounds__(256) void k_ang(const double* __restrict__ u_all,
@@ -252,26 +402,7 @@ __global__ __launch_bounds__(256) void k_ang(const double* __restrict__ u_all,
   double* elll = Ul + d.n_U;
   for (int q = threadIdx.x; q < d.n_U; q += blockDim.x) Ul[q] = d.U[q];
   for (int q = threadIdx.x; q < d.n_ell; q += blockDim.x) elll[q] = d.ell[q];
-  {
-    const int t = threadIdx.x % RT, k_first = threadIdx.x / RT;
-    constexpr int kstep = 256 / RT;
-    const int i = i0 + t;
-    const double* ub = u + (size_t)m * nr + i;
-    for (int o = 0; o < n_om; ++o) {
-      const size_t col = (size_t)(o * ne + le) * ng;
-      E* x0 = X + (o * 2 + 0) * tile + t * ld;
-      E* x1 = X + (o * 2 + 1) * tile + t * ld;
-      for (int k = k_first; k < kpa; k += kstep) {
-        double a = 0.0, b = 0.0;
-        if (k < ngh && i < nr) {
-          a = ub[(col + k) * plane];
-          b = ub[(col + ng - 1 - k) * plane];
-        }
-        F::put(x0, ps, k, a + b);
-        F::put(x1, ps, k, a - b);
-      }
-    }
-  }
+  ang_load<P, RT>(X, u, n_om, ne, le, ng, kpa, ld, tile, ps, m, i0, nr, plane);
   __syncthreads();
   const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int mt_per = (kpa + 15) >> 4;   // forward M-tiles per (omega, class): rows up to kpa
@@ -357,72 +488,194 @@ __global__ __launch_bounds__(256) void k_ang(const double* __restrict__ u_all,
     }
   }
   __syncthreads();
-  // back: H_c[o][n'][t] = sum_jj PcT[Omega][c][n'][jj] C[o][c][t][jj]
-  const int NTh = (ngh + 15) >> 4;
-  for (int it = w; it < n_om * NTh; it += 4) {
-    const int o = it / NTh, mt = it % NTh;
-    const int Om = om_lo + o;
-    const int nj0 = n_class(ng, Om, 0), nj1 = n_class(ng, Om, 1);
-    const int kb = round_up(nj0 > nj1 ? nj0 : nj1, M::KS);
-    typename M::acc_t acc[2][NT];
+  ang_back<P, NT>(X, h, PcT, tab, ngk, psp, n_om, om_lo, ne, le, ng, ld, tile, ps, m, i0, nr,
+                  plane);
+}
+
+// ---- h = angular + Coriolis terms, helicity mixing in registers -----------------
+// Same column blocks as k_ang.  The forward transform is indexed by the absolute
+// FBR index j: C[o][j][t] = sum_n' Pf[Omega][0][j][n'] s[o][n'][t]
+//                         + sum_n' Pf[Omega][1][j][n'] d[o][n'][t],
+// where Pf[Omega][c] keeps the rows of P^Omega whose (j + Omega) mod 2 is c and is
+// zero elsewhere (rows j < Omega or j >= ng are zero too).  A wave computes one
+// (j tile, t tile) for every helicity, so a lane holds C[.][j][t] for all Omega of
+// its rows j and the mixing U diag(min(B_r j(j+1) + B_R ell_a, rot_cut)) U^T runs in
+// registers (U and ell read through the cache).  The mixed coefficients go to
+// C[o][class][t][jj] in X's place for the back transform of ang_back.  TPW tiles
+// per wave times MAXOM helicities bound the accumulators held across the barrier.
+template <int P, int NT, int MAXOM>
+__global__ __launch_bounds__(256) void k_angr(const double* __restrict__ u_all,
+                                              typename HType<P>::T* __restrict__ h_all,
+                                              const PkDesc* __restrict__ pks,
+                                              const int* __restrict__ blk_start, int n_pk, int ne,
+                                              int ng, int nR, int nr,
+                                              const typename Fmt<P>::E* __restrict__ Pf, int ngr,
+                                              int psf,
+                                              const typename Fmt<P>::E* __restrict__ PcT,
+                                              int ngk, int psp,
+                                              const double* __restrict__ Br,
+                                              const double* __restrict__ BR, double rot_cut) {
+  using M = Mma<P>;
+  using F = Fmt<P>;
+  using E = typename F::E;
+  constexpr int CH = Chunk<P>::CH;
+  constexpr int RT = 16 * NT;
+  constexpr int TPW = 16 / MAXOM;
+  extern __shared__ __align__(16) double lds[];
+  const int pk = find_packet(blk_start, n_pk, blockIdx.x);
+  const int local = blockIdx.x - blk_start[pk];
+  const PkDesc d = pks[pk];
+  const double* __restrict__ u = u_all + d.off;
+  typename HType<P>::T* __restrict__ h = h_all + d.off;
+  const int n_om = d.n_om, om_lo = d.om_lo;
+  const int nrt = (nr + RT - 1) / RT;
+  const int ngh = ng >> 1;
+  const int kpa = round_up(ngh, M::KS);
+  const int ld = tile_ld<P>(kpa);
+  const int tile = RT * ld;
+  const int ps = n_om * 2 * tile;
+  const int i0 = (local % nrt) * RT;
+  const int m = (local / nrt) % nR;
+  const int le = local / (nrt * nR);
+  const size_t plane = (size_t)nR * nr;
+  E* X = reinterpret_cast<E*>(lds);
+  ang_load<P, RT>(X, u, n_om, ne, le, ng, kpa, ld, tile, ps, m, i0, nr, plane);
+  __syncthreads();
+  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int MTj = (ng + 15) >> 4;
+  const int n_tiles = MTj * NT;
+  typename M::acc_t acc[TPW][MAXOM];
 #pragma unroll
-    for (int c = 0; c < 2; ++c) {
-      const E* Ab = PcT + (size_t)(Om * 2 + c) * tab + (size_t)mt * 16 * ngk;
-      const E* Bb = X + (o * 2 + c) * tile;
+  for (int tp = 0; tp < TPW; ++tp) {
+    const int tix = w + 4 * tp;
+    if (tix >= n_tiles) break;
+    const int mt = tix % MTj, nt = tix / MTj;
 #pragma unroll
-      for (int nt = 0; nt < NT; ++nt) acc[c][nt] = M::zero();
-      for (int k0 = 0; k0 < kb; k0 += CH * M::KS) {
-        typename M::frag_t fa[CH];
+    for (int o = 0; o < MAXOM; ++o) {
+      acc[tp][o] = M::zero();
+      if (o >= n_om) continue;
+      const int Om = om_lo + o;
+      const E* Ae = Pf + ((size_t)(Om * 2 + 0) * ngr + mt * 16) * ngk;
+      const E* Ao = Pf + ((size_t)(Om * 2 + 1) * ngr + mt * 16) * ngk;
+      const E* Bs = X + (o * 2 + 0) * tile + nt * 16 * ld;
+      const E* Bd = X + (o * 2 + 1) * tile + nt * 16 * ld;
+      typename M::acc_t c = M::zero();
+      for (int k0 = 0; k0 < kpa; k0 += CH * M::KS) {
+        typename M::frag_t fe[CH], fo[CH];
 #pragma unroll
         for (int q = 0; q < CH; ++q)
-          if (k0 + q * M::KS < kb) fa[q] = F::frag(Ab, ngk, psp, l, k0 + q * M::KS);
+          if (k0 + q * M::KS < kpa) {
+            fe[q] = F::frag(Ae, ngk, psf, l, k0 + q * M::KS);
+            fo[q] = F::frag(Ao, ngk, psf, l, k0 + q * M::KS);
+          }
 #pragma unroll
         for (int q = 0; q < CH; ++q)
-          if (k0 + q * M::KS < kb) {
-#pragma unroll
-            for (int nt = 0; nt < NT; ++nt)
-              M::mma(acc[c][nt], fa[q], F::frag(Bb + nt * 16 * ld, ld, ps, l, k0 + q * M::KS));
+          if (k0 + q * M::KS < kpa) {
+            M::mma(c, fe[q], F::frag(Bs, ld, ps, l, k0 + q * M::KS));
+            M::mma(c, fo[q], F::frag(Bd, ld, ps, l, k0 + q * M::KS));
           }
       }
-    }
-    const size_t col = (size_t)(o * ne + le) * ng;
-#pragma unroll
-    for (int nt = 0; nt < NT; ++nt) {
-      const int i = i0 + nt * 16 + (l & 15);
-      if (i >= nr) continue;
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int n = mt * 16 + M::row(l, v);
-        if (n >= ngh) continue;
-        const double h0 = (double)acc[0][nt][v] * M::kUnscale;
-        const double h1 = (double)acc[1][nt][v] * M::kUnscale;
-        const size_t ia = (col + n) * plane + (size_t)m * nr + i;
-        const size_t ib = (col + ng - 1 - n) * plane + (size_t)m * nr + i;
-        h[ia] = (typename HType<P>::T)((double)h[ia] + h0 + h1);
-        h[ib] = (typename HType<P>::T)((double)h[ib] + h0 - h1);
-      }
+      acc[tp][o] = c;
     }
   }
+  __syncthreads();   // X is read by every wave before the coefficients replace it
+  using MX = typename HType<P>::T;
+  const MX* __restrict__ mixU;
+  const MX* __restrict__ mixl;
+  if constexpr (P == kP64) {
+    mixU = d.U;
+    mixl = d.ell;
+  } else {
+    mixU = d.Uf;
+    mixl = d.ellf;
+  }
+  const MX bRm = (MX)BR[m];
+  const MX cap = (MX)rot_cut;
+  const int om_hi = om_lo + n_om - 1;
+#pragma unroll
+  for (int tp = 0; tp < TPW; ++tp) {
+    const int tix = w + 4 * tp;
+    if (tix >= n_tiles) break;
+    const int mt = tix % MTj, nt = tix / MTj;
+    const int t = nt * 16 + (l & 15);
+    const int i = i0 + t;
+    const double br = Br[i < nr ? i : nr - 1];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int j = mt * 16 + M::row(l, v);
+      const int nj = (j < ng) ? (j < om_hi ? j : om_hi) - om_lo + 1 : 0;
+      if (nj <= 0) continue;
+      // mixing in the accumulation precision (FP64 form: FP64; mixed forms: FP32)
+      MX cv[MAXOM];
+#pragma unroll
+      for (int o = 0; o < MAXOM; ++o)
+        cv[o] = (o < nj) ? (MX)((double)acc[tp][o][v] * M::kUnscale) : (MX)0;
+      const MX rot = (MX)(br * (double)j * (double)(j + 1));
+      const MX* __restrict__ Uj = mixU + d.ang_off[j];
+      const MX* __restrict__ lj = mixl + d.ell_off[j];
+      if (MAXOM == 1 || nj == 1) {
+        MX e = rot + bRm * lj[0];
+        if (rot_cut > 0.0) e = e < cap ? e : cap;
+        cv[0] *= e;
+      } else {
+        // one eigenvector column per iteration: project, scale, scatter back
+        MX outv[MAXOM];
+#pragma unroll
+        for (int a = 0; a < MAXOM; ++a) outv[a] = (MX)0;
+        for (int b = 0; b < nj; ++b) {
+          MX uc[MAXOM];
+#pragma unroll
+          for (int a = 0; a < MAXOM; ++a) uc[a] = Uj[(a < nj ? a : nj - 1) * nj + b];
+          MX sacc = (MX)0;
+#pragma unroll
+          for (int a = 0; a < MAXOM; ++a)
+            if (a < nj) sacc += uc[a] * cv[a];
+          MX e = rot + bRm * lj[b];
+          if (rot_cut > 0.0) e = e < cap ? e : cap;
+          const MX tb = sacc * e;
+#pragma unroll
+          for (int a = 0; a < MAXOM; ++a)
+            if (a < nj) outv[a] += uc[a] * tb;
+        }
+#pragma unroll
+        for (int a = 0; a < MAXOM; ++a) cv[a] = outv[a];
+      }
+#pragma unroll
+      for (int o = 0; o < MAXOM; ++o)
+        if (o < nj) {
+          const int Om = om_lo + o, c = (j + Om) & 1;
+          F::put(X, ps, (o * 2 + c) * tile + t * ld + ((j - Om - c) >> 1), (double)cv[o]);
+        }
+    }
+  }
+  __syncthreads();
+  ang_back<P, NT>(X, h, PcT, (size_t)ngk * ngk, ngk, psp, n_om, om_lo, ne, le, ng, ld, tile, ps,
+                  m, i0, nr, plane);
 }
 
 // ---- T_R along R, potential, scaling, recursion, damping, norm partial ---------------
 // One workgroup per (r tile of 16 columns, slab (omega, gamma)) of one packet, all
-// elec.  The raw FP64 tile X[elec][R][t] stays in LDS for the epilogue; per elec
-// the sum/difference operand (rows t, contraction over R) is built in compute
-// format, and each M-tile work item finishes rows a and n_R-1-a from its
-// accumulators.
-template <int P>
+// NE electronic states.  The raw FP64 tile X[elec][R][t] stays in LDS for the
+// epilogue; per elec the sum/difference operand (rows t, contraction over R) is
+// built in compute format, and each M-tile work item finishes rows a and n_R-1-a
+// from its accumulators.  Global loads are issued in independent batches (the
+// tile in groups of kLoadBatch rows; the epilogue operands of an M-tile before its
+// contraction) so that one memory latency is paid per batch, not per element.
+constexpr int kLoadBatch = 8;
+
+template <int P, int NE>
 __global__ __launch_bounds__(256) void k_radR_epi(
     const double* __restrict__ uk_all, double* __restrict__ uprev_all,
     const typename HType<P>::T* __restrict__ h_all, const PkDesc* __restrict__ pks,
     const int* __restrict__ blk_start, int n_pk, const typename Fmt<P>::E* __restrict__ Ts,
     const typename Fmt<P>::E* __restrict__ Td, int ldt, int pst, const double* __restrict__ V,
-    const double* __restrict__ D, int ne, int ng, int nR, int nr, double E0, double inv_dE,
+    const double* __restrict__ D, int ng, int nR, int nr, double E0, double inv_dE,
     int first, double* __restrict__ normpart, size_t n_wg_total, const int* __restrict__ counters,
     int norm_rows) {
   using M = Mma<P>;
   using F = Fmt<P>;
   using E = typename F::E;
+  using HT = typename HType<P>::T;
   constexpr int CH = Chunk<P>::CH;
   constexpr int RT = 16;
   extern __shared__ __align__(16) double lds[];
@@ -435,7 +688,7 @@ __global__ __launch_bounds__(256) void k_radR_epi(
   const PkDesc dsc = pks[pk];
   const double* __restrict__ uk = uk_all + dsc.off;
   double* __restrict__ uprev = uprev_all + dsc.off;
-  const typename HType<P>::T* __restrict__ h = h_all + dsc.off;
+  const HT* __restrict__ h = h_all + dsc.off;
   const int nrt = (nr + RT - 1) / RT;
   const int nh = nR >> 1;
   const int kp = round_up(nh, M::KS);
@@ -446,14 +699,29 @@ __global__ __launch_bounds__(256) void k_radR_epi(
   const int o = slab / ng, n = slab % ng;
   const size_t plane = (size_t)nR * nr;
   double* X = lds;                                             // [le][nR][RT]
-  E* SD = reinterpret_cast<E*>(lds + (size_t)ne * nR * RT);    // S^T [t][k], then D^T
+  E* SD = reinterpret_cast<E*>(lds + (size_t)NE * nR * RT);    // S^T [t][k], then D^T
   {
     const int tt = threadIdx.x & 15, r0 = threadIdx.x >> 4;
     const int ii = i0 + tt;
-    for (int le = 0; le < ne; ++le) {
-      const double* src = uk + ((size_t)(o * ne + le) * ng + n) * plane + ii;
+    const bool okc = ii < nr;
+    const int iic = okc ? ii : nr - 1;   // loads use clamped, in-range addresses
+#pragma unroll
+    for (int le = 0; le < NE; ++le) {
+      const double* src = uk + ((size_t)(o * NE + le) * ng + n) * plane + iic;
       double* dst = X + (size_t)le * nR * RT + tt;
-      for (int mm = r0; mm < nR; mm += 16) dst[mm * RT] = (ii < nr) ? src[(size_t)mm * nr] : 0.0;
+      for (int m0 = r0; m0 < nR; m0 += 16 * kLoadBatch) {
+        double vb[kLoadBatch];
+#pragma unroll
+        for (int b = 0; b < kLoadBatch; ++b) {
+          const int mm = m0 + 16 * b;
+          vb[b] = src[(size_t)(mm < nR ? mm : nR - 1) * nr];
+        }
+#pragma unroll
+        for (int b = 0; b < kLoadBatch; ++b) {
+          const int mm = m0 + 16 * b;
+          if (mm < nR) dst[mm * RT] = okc ? vb[b] : 0.0;
+        }
+      }
     }
   }
   const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -461,7 +729,8 @@ __global__ __launch_bounds__(256) void k_radR_epi(
   const int t = l & 15;
   const int i = i0 + t;
   double nsum = 0.0;
-  for (int le = 0; le < ne; ++le) {
+#pragma unroll 1
+  for (int le = 0; le < NE; ++le) {
     __syncthreads();
     const double* Xl = X + (size_t)le * nR * RT;
     {
@@ -478,6 +747,32 @@ __global__ __launch_bounds__(256) void k_radR_epi(
     }
     __syncthreads();
     for (int mt = w; mt < MT; mt += 4) {
+      // epilogue operands of this lane's 8 outputs (rows a and n_R-1-a), loaded
+      // before the contraction so their latency overlaps it
+      // (addresses clamped into range; outputs outside it are skipped below)
+      HT hv[8];
+      double dv[8], pv[8], vv[8][NE];
+      const int ic = i < nr ? i : nr - 1;
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int side = 0; side < 2; ++side) {
+          const int q = 2 * v + side;
+          const int a0r = mt * 16 + M::row(l, v);
+          const int a = a0r < nh ? a0r : nh - 1;
+          const int mm = side ? nR - 1 - a : a;
+          const size_t pt = (size_t)n * plane + (size_t)mm * nr + ic;
+          const size_t idx = (size_t)(o * NE + le) * ng * plane + pt;
+          hv[q] = h[idx];
+          dv[q] = D[(size_t)mm * nr + ic];
+          pv[q] = first ? 0.0 : uprev[idx];
+#pragma unroll
+          for (int l2 = 0; l2 < NE; ++l2) {
+            const int a0 = le < l2 ? le : l2, a1 = le < l2 ? l2 : le;
+            const int pi = a0 * NE - a0 * (a0 - 1) / 2 + (a1 - a0);
+            vv[q][l2] = V[(size_t)pi * ng * plane + pt];
+          }
+        }
       const E* As = Ts + (size_t)mt * 16 * ldt;
       const E* Ad = Td + (size_t)mt * 16 * ldt;
       typename M::acc_t cs = M::zero(), cd = M::zero();
@@ -504,19 +799,16 @@ __global__ __launch_bounds__(256) void k_radR_epi(
         const double ys = (double)cs[v] * M::kUnscale, yd = (double)cd[v] * M::kUnscale;
 #pragma unroll
         for (int side = 0; side < 2; ++side) {
+          const int q = 2 * v + side;
           const int mm = side ? nR - 1 - a : a;
-          const size_t pt = (size_t)n * plane + (size_t)mm * nr + i;
-          const size_t idx = (size_t)(o * ne + le) * ng * plane + pt;
+          const size_t idx = (size_t)(o * NE + le) * ng * plane + (size_t)n * plane + (size_t)mm * nr + i;
           const double ukv = Xl[mm * RT + t];
-          double sacc = (side ? ys - yd : ys + yd) + (double)h[idx];
-          for (int l2 = 0; l2 < ne; ++l2) {
-            const int a0 = le < l2 ? le : l2, a1 = le < l2 ? l2 : le;
-            const int pi = a0 * ne - a0 * (a0 - 1) / 2 + (a1 - a0);
-            sacc += V[(size_t)pi * ng * plane + pt] * X[((size_t)l2 * nR + mm) * RT + t];
-          }
+          double sacc = (side ? ys - yd : ys + yd) + (double)hv[q];
+#pragma unroll
+          for (int l2 = 0; l2 < NE; ++l2) sacc += vv[q][l2] * X[((size_t)l2 * nR + mm) * RT + t];
           const double wv = (sacc - E0 * ukv) * inv_dE;
-          const double dmp = D[(size_t)mm * nr + i];
-          const double un = first ? dmp * wv : dmp * (2.0 * wv - dmp * uprev[idx]);
+          const double dmp = dv[q];
+          const double un = first ? dmp * wv : dmp * (2.0 * wv - dmp * pv[q]);
           uprev[idx] = un;
           nsum += un * un;
         }

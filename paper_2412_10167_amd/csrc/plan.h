@@ -25,6 +25,8 @@ struct UnitInfo {
   std::vector<double> ang_U, ang_ell;
   double* d_U = nullptr;
   double* d_ell = nullptr;
+  float* d_Uf = nullptr;     // FP32 copies for the register mixing of the mixed forms
+  float* d_ellf = nullptr;
   int* d_ang_off = nullptr;
   int* d_ell_off = nullptr;
   int* d_n_om_j = nullptr;
@@ -76,8 +78,9 @@ struct tdwp_plan_s {
   bool fast = false;
   bool fast_accum = false;
   int ntr = 1;               // 16-column tiles per k_radR_epi workgroup
-  int nta = 1;               // 16-column tiles per k_ang workgroup
-  int nrhk = 0, nRhk = 0, ngk = 0;
+  int nta = 1;               // 16-column tiles per angular workgroup
+  int ang_regs = 0;          // angular kernel: 0 k_ang, else k_angr with this many helicities
+  int nrhk = 0, nRhk = 0, ngk = 0, ngr = 0;
   size_t lds_radr = 0, lds_ang = 0, lds_radR = 0;
   std::vector<double> Trs, Trd, TRs, TRd, Pc;
   double* d_Trs = nullptr;
@@ -86,6 +89,7 @@ struct tdwp_plan_s {
   double* d_TRd = nullptr;
   double* d_Pc = nullptr;
   std::vector<double> PcT;
+  std::vector<double> Pf;    // [omega][parity][j < ngr][n' < ngk], rows of one parity of j + omega
   // operator tables in the compute format of the plan's precision
   void* d_TrsF = nullptr;
   void* d_TrdF = nullptr;
@@ -93,6 +97,7 @@ struct tdwp_plan_s {
   void* d_TRdF = nullptr;
   void* d_PcF = nullptr;
   void* d_PcTF = nullptr;
+  void* d_PfF = nullptr;
   // propagation state
   long k = 0;
   int cur = 0;               // u_k lives in d_u[cur], u_{k-1} in d_u[1 - cur]
@@ -133,6 +138,7 @@ struct tdwp_plan_s {
   void* d_accdesc = nullptr;      // AccDesc[n_packets]
   int* d_blk_acc = nullptr;       // block prefix sums per packet, k_accum_mfma
   long* d_line_start = nullptr;   // first r-line of each packet (n_packets + 1)
+  int* d_radr_pk = nullptr;       // packet of the first line of each k_radr workgroup
   unsigned long* d_slice_off = nullptr;
   double* d_E = nullptr;          // E_v0j0 per packet
   int blocks_ang = 0, blocks_radR = 0, blocks_acc = 0;

@@ -237,6 +237,17 @@ int build_tables(Plan* P) {
       for (int x = 0; x < ngk; ++x)
         for (int y = 0; y < ngk; ++y)
           P->PcT[(b * ngk + y) * ngk + x] = P->Pc[(b * ngk + x) * ngk + y];
+    // forward rows by absolute j, split by the parity of j + omega
+    P->ngr = round_up(P->ng, 16);
+    const int ngr = P->ngr;
+    P->Pf.assign((size_t)(P->max_om + 1) * 2 * ngr * ngk, 0.0);
+    for (int om = 0; om <= P->max_om; ++om)
+      for (int j = om; j < P->ng; ++j) {
+        const int c = (j + om) & 1;
+        for (int n = 0; n < ngh; ++n)
+          P->Pf[(((size_t)om * 2 + c) * ngr + j) * ngk + n] =
+              P->Ptab[((size_t)om * P->ng + j) * P->ng + n];
+      }
   }
   return TDWP_OK;
 }
@@ -248,6 +259,34 @@ size_t elem_bytes(int prec) {
 }
 int planes_of(int prec) { return (prec == TDWP_BF16X3 || prec == TDWP_FP16X3) ? 2 : 1; }
 int ld_of(int prec, int kp) { return kp + ((prec == TDWP_BF16X3 || prec == TDWP_FP16X3) ? 8 : 1); }
+
+// Angular kernel for a tile width of 16 nt columns: k_angr (helicity mixing in
+// registers) when its accumulators fit, else k_ang.  Returns false if neither fits.
+bool ang_config(Plan* P, int nt, int* regs, size_t* lds) {
+  const int prec = P->cfg.precision;
+  const size_t eb = elem_bytes(prec) * planes_of(prec);
+  const int kpa = round_up(P->ng / 2, (int)ks_of(prec));
+  int max_om = 0;
+  size_t ang_tab = 0;
+  for (auto& U : P->units) {
+    max_om = std::max(max_om, U.n_om);
+    ang_tab = std::max(ang_tab, (U.ang_U.size() + U.ang_ell.size()) * sizeof(double));
+  }
+  const size_t tiles = ((size_t)max_om * 2 * 16 * nt * ld_of(prec, kpa) * eb + 15) / 16 * 16;
+  const int mom = max_om <= 1 ? 1 : (max_om <= 8 ? 8 : 16);
+  const int tpw = ((P->ng + 15) / 16 * nt + 3) / 4;
+  if (max_om <= kMaxOmega && tpw <= 16 / mom && tiles <= kLdsMax) {
+    *regs = mom;
+    *lds = tiles;
+    return true;
+  }
+  const int mt_per = (kpa + 15) / 16;
+  const int per_wave = (max_om * 2 * mt_per + 3) / 4;
+  if (per_wave * nt > kAngMaxAcc || tiles + ang_tab > kLdsMax) return false;
+  *regs = 0;
+  *lds = tiles + ang_tab;
+  return true;
+}
 
 // Decides whether the matrix-core kernels apply and sizes their tiles and LDS.
 void choose_fast_path(Plan* P) {
@@ -262,16 +301,16 @@ void choose_fast_path(Plan* P) {
   int max_om = 0;
   for (auto& U : P->units) max_om = std::max(max_om, U.n_om);
   P->lds_radr = (size_t)2 * kRadrLines * ld_of(prec, kpr) * eb;
-  const int mt_per = (kpa + 15) / 16;
-  const int per_wave = (max_om * 2 * mt_per + 3) / 4;
-  size_t ang_tab = 0;
-  for (auto& U : P->units) ang_tab = std::max(ang_tab, (U.ang_U.size() + U.ang_ell.size()) * sizeof(double));
+  (void)kpa;
+  (void)max_om;
   P->nta = 0;
   for (int nt : {4, 2, 1}) {
-    const size_t lds = ((size_t)max_om * 2 * 16 * nt * ld_of(prec, kpa) * eb + 15) / 16 * 16 + ang_tab;
-    if (per_wave * nt > kAngMaxAcc) continue;
-    if (lds <= soft || (nt == 1 && lds <= kLdsMax)) {
+    int regs = 0;
+    size_t lds = 0;
+    if (!ang_config(P, nt, &regs, &lds)) continue;
+    if (lds <= soft || nt == 1) {
       P->nta = nt;
+      P->ang_regs = regs;
       P->lds_ang = lds;
       break;
     }
@@ -304,6 +343,7 @@ int upload_tables(Plan* P) {
   TRY(upload_formatted<PR>(P, &P->d_TRdF, P->TRd));
   TRY(upload_formatted<PR>(P, &P->d_PcF, P->Pc));
   TRY(upload_formatted<PR>(P, &P->d_PcTF, P->PcT));
+  TRY(upload_formatted<PR>(P, &P->d_PfF, P->Pf));
   return TDWP_OK;
 }
 
@@ -313,10 +353,16 @@ int upload_tables(Plan* P) {
 template <int PR>
 void set_lds_limits() {
   if (kLdsMax <= 64 * 1024) return;
-  const void* fns[8] = {(const void*)k_radr<PR>, (const void*)k_ang<PR, 1, 1>,
-                        (const void*)k_ang<PR, 2, 1>, (const void*)k_ang<PR, 4, 1>,
-                        (const void*)k_ang<PR, 1, kMaxOmega>, (const void*)k_ang<PR, 2, kMaxOmega>,
-                        (const void*)k_ang<PR, 4, kMaxOmega>, (const void*)k_radR_epi<PR>};
+  const void* fns[20] = {(const void*)k_radr<PR>, (const void*)k_ang<PR, 1, 1>,
+                         (const void*)k_ang<PR, 2, 1>, (const void*)k_ang<PR, 4, 1>,
+                         (const void*)k_ang<PR, 1, kMaxOmega>, (const void*)k_ang<PR, 2, kMaxOmega>,
+                         (const void*)k_ang<PR, 4, kMaxOmega>, (const void*)k_radR_epi<PR, 1>,
+                         (const void*)k_radR_epi<PR, 2>, (const void*)k_radR_epi<PR, 3>,
+                         (const void*)k_radR_epi<PR, 4>, (const void*)k_angr<PR, 1, 1>,
+                         (const void*)k_angr<PR, 2, 1>, (const void*)k_angr<PR, 4, 1>,
+                         (const void*)k_angr<PR, 1, 8>, (const void*)k_angr<PR, 2, 8>,
+                         (const void*)k_angr<PR, 4, 8>, (const void*)k_angr<PR, 1, 16>,
+                         (const void*)k_angr<PR, 2, 16>, (const void*)k_angr<PR, 4, 16>};
   for (const void* f : fns) {
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsMax);
     if (e != hipSuccess) {
@@ -417,6 +463,8 @@ int layout_and_allocate(Plan* P) {
     std::vector<double> lv = U.ang_ell.empty() ? std::vector<double>{0.0} : U.ang_ell;
     TRY(alloc_copy(P, &U.d_U, Uv));
     TRY(alloc_copy(P, &U.d_ell, lv));
+    TRY(alloc_copy(P, &U.d_Uf, std::vector<float>(Uv.begin(), Uv.end())));
+    TRY(alloc_copy(P, &U.d_ellf, std::vector<float>(lv.begin(), lv.end())));
     TRY(alloc_copy(P, &U.d_ang_off, U.ang_off));
     TRY(alloc_copy(P, &U.d_ell_off, U.ell_off));
     TRY(alloc_copy(P, &U.d_n_om_j, U.n_om_j));
@@ -473,6 +521,17 @@ int layout_and_allocate(Plan* P) {
   }
   P->blocks_acc = blk_acc.back();
   TRY(alloc_copy(P, &P->d_line_start, line_start));
+  {
+    const long nlines = (long)(P->n_total / nr);
+    const long nblk = (nlines + kRadrLines - 1) / kRadrLines;
+    std::vector<int> bp((size_t)std::max<long>(nblk, 1), 0);
+    int q = 0;
+    for (long b = 0; b < nblk; ++b) {
+      while (q + 1 < (int)P->packets.size() && line_start[q + 1] <= b * kRadrLines) ++q;
+      bp[b] = q;
+    }
+    TRY(alloc_copy(P, &P->d_radr_pk, bp));
+  }
   TRY(alloc_copy(P, &P->d_slice_off, slice_off));
   TRY(alloc_copy(P, &P->d_blk_acc, blk_acc));
   AccDesc* dad = nullptr;
@@ -491,7 +550,8 @@ int layout_and_allocate(Plan* P) {
     for (auto& pk : P->packets) {
       const UnitInfo& U = P->units[pk.unit];
       pd.push_back(PkDesc{pk.off, pk.wg_off, U.n_om, U.om_lo, U.d_U, U.d_ell, U.d_ang_off,
-                          U.d_ell_off, U.d_n_om_j, (int)U.ang_U.size(), (int)U.ang_ell.size()});
+                          U.d_ell_off, U.d_n_om_j, (int)U.ang_U.size(), (int)U.ang_ell.size(),
+                          U.d_Uf, U.d_ellf});
       ba.push_back(ba.back() + nrt_a * nR * ne);
       br.push_back(br.back() + nrt_r * U.n_om * ng);
     }
@@ -539,19 +599,9 @@ int ensure_staging(Plan* P, double** buf, size_t* cap, size_t need) {
 // Angular-kernel tile width (16 nt columns): block prefix sums and LDS size.
 int set_ang_tiles(Plan* P, int nt) {
   HIP_TRY(hipStreamSynchronize(P->stream));
-  const int prec = P->cfg.precision;
-  const size_t eb = elem_bytes(prec) * planes_of(prec);
-  const int kpa = round_up(P->ng / 2, (int)ks_of(prec));
-  int max_om = 0;
-  size_t ang_tab = 0;
-  for (auto& U : P->units) {
-    max_om = std::max(max_om, U.n_om);
-    ang_tab = std::max(ang_tab, (U.ang_U.size() + U.ang_ell.size()) * sizeof(double));
-  }
-  const int mt_per = (kpa + 15) / 16;
-  const int per_wave = (max_om * 2 * mt_per + 3) / 4;
-  const size_t lds = ((size_t)max_om * 2 * 16 * nt * ld_of(prec, kpa) * eb + 15) / 16 * 16 + ang_tab;
-  if (per_wave * nt > kAngMaxAcc || lds > kLdsMax) return TDWP_EINVAL;
+  int regs = 0;
+  size_t lds = 0;
+  if (!ang_config(P, nt, &regs, &lds)) return TDWP_EINVAL;
   std::vector<int> ba(1, 0);
   const int nrt_a = (P->nr + 16 * nt - 1) / (16 * nt);
   for (auto& pk : P->packets) {
@@ -561,6 +611,7 @@ int set_ang_tiles(Plan* P, int nt) {
   HIP_TRY(hipMemcpy(P->d_blk_ang, ba.data(), ba.size() * sizeof(int), hipMemcpyHostToDevice));
   P->blocks_ang = ba.back();
   P->nta = nt;
+  P->ang_regs = regs;
   P->lds_ang = P->lds_ang_max = lds;
   return TDWP_OK;
 }
@@ -789,29 +840,33 @@ int enqueue_step(Plan* P, int cur, int first, int rec, Timing* T) {
   const PkDesc* pkd = (const PkDesc*)P->d_pkdesc;
   TRY(timed_begin(P, T));
   {
-    const long nlines = (long)(P->n_total / nr);
-    const int h2 = nr / 2;
-    SliceArgs sa{rec, 0, P->d_line_start, P->d_slice_off, np, nR, P->m_inf,
-                 P->d_flux_split, P->d_flux_split + h2, P->d_flux_split + 2 * h2,
-                 P->d_flux_split + 3 * h2, 1.0 / std::sqrt(P->dR), P->d_ring, P->slice_total,
-                 P->d_counters, P->ring_len};
-    hipLaunchKernelGGL(k_radr<PR>, dim3((unsigned)((nlines + kRadrLines - 1) / kRadrLines)),
-                       dim3(256), P->lds_radr, P->stream, uk, h, (const E*)P->d_TrsF,
-                       (const E*)P->d_TrdF, P->nrhk, P->nrhk * P->nrhk, nr, nlines, sa);
-  }
-  HIP_TRY(hipGetLastError());
-  TRY(timed_end(P, T, 4));
-  TRY(timed_begin(P, T));
-  {
     const int psp = (int)P->Pc.size();
     auto launch = [&](auto kern) {
       hipLaunchKernelGGL(kern, dim3(P->blocks_ang), dim3(256), P->lds_ang_max, P->stream, uk, h,
                          pkd, P->d_blk_ang, np, ne, ng, nR, nr, (const E*)P->d_PcF,
                          (const E*)P->d_PcTF, P->ngk, psp, P->d_Br, P->d_BR, P->cfg.rot_cut);
     };
+    auto launch_r = [&](auto kern) {
+      hipLaunchKernelGGL(kern, dim3(P->blocks_ang), dim3(256), P->lds_ang_max, P->stream, uk, h,
+                         pkd, P->d_blk_ang, np, ne, ng, nR, nr, (const E*)P->d_PfF, P->ngr,
+                         (int)P->Pf.size(), (const E*)P->d_PcTF, P->ngk, psp, P->d_Br, P->d_BR,
+                         P->cfg.rot_cut);
+    };
     int max_om = 0;
     for (auto& U : P->units) max_om = std::max(max_om, U.n_om);
-    if (max_om == 1) {
+    if (P->ang_regs == 1) {
+      if (P->nta == 4) launch_r(k_angr<PR, 4, 1>);
+      else if (P->nta == 2) launch_r(k_angr<PR, 2, 1>);
+      else launch_r(k_angr<PR, 1, 1>);
+    } else if (P->ang_regs == 8) {
+      if (P->nta == 4) launch_r(k_angr<PR, 4, 8>);
+      else if (P->nta == 2) launch_r(k_angr<PR, 2, 8>);
+      else launch_r(k_angr<PR, 1, 8>);
+    } else if (P->ang_regs == 16) {
+      if (P->nta == 4) launch_r(k_angr<PR, 4, 16>);
+      else if (P->nta == 2) launch_r(k_angr<PR, 2, 16>);
+      else launch_r(k_angr<PR, 1, 16>);
+    } else if (max_om == 1) {
       if (P->nta == 4) launch(k_ang<PR, 4, 1>);
       else if (P->nta == 2) launch(k_ang<PR, 2, 1>);
       else launch(k_ang<PR, 1, 1>);
@@ -824,6 +879,20 @@ int enqueue_step(Plan* P, int cur, int first, int rec, Timing* T) {
   HIP_TRY(hipGetLastError());
   TRY(timed_end(P, T, 0));
   TRY(timed_begin(P, T));
+  {
+    const long nlines = (long)(P->n_total / nr);
+    const int h2 = nr / 2;
+    SliceArgs sa{rec, 0, P->d_line_start, P->d_slice_off, np, nR, P->m_inf,
+                 P->d_flux_split, P->d_flux_split + h2, P->d_flux_split + 2 * h2,
+                 P->d_flux_split + 3 * h2, 1.0 / std::sqrt(P->dR), P->d_ring, P->slice_total,
+                 P->d_counters, P->ring_len, P->d_radr_pk};
+    hipLaunchKernelGGL(k_radr<PR>, dim3((unsigned)((nlines + kRadrLines - 1) / kRadrLines)),
+                       dim3(256), P->lds_radr, P->stream, uk, h, (const E*)P->d_TrsF,
+                       (const E*)P->d_TrdF, P->nrhk, P->nrhk * P->nrhk, nr, nlines, sa);
+  }
+  HIP_TRY(hipGetLastError());
+  TRY(timed_end(P, T, 4));
+  TRY(timed_begin(P, T));
   if (P->pot_mode == TDWP_POT_MLP) {
     const double mbc = P->cfg.mass_B + P->cfg.mass_C;
     hipLaunchKernelGGL(k_radR_epi_mlp<PR>, dim3(P->blocks_radR), dim3(256), P->lds_radR_mlp,
@@ -833,11 +902,19 @@ int enqueue_step(Plan* P, int cur, int first, int rec, Timing* T) {
                        nR, nr, P->E0, 1.0 / P->dE, first, P->d_normpart, P->n_wg_total,
                        (const int*)P->d_counters, kNormChunk);
   } else {
-    hipLaunchKernelGGL(k_radR_epi<PR>, dim3(P->blocks_radR), dim3(256), P->lds_radR, P->stream,
-                       uk, uo, h, pkd, P->d_blk_radR, np, (const E*)P->d_TRsF,
-                       (const E*)P->d_TRdF, P->nRhk, P->nRhk * P->nRhk, P->d_V, P->d_D, ne, ng,
-                       nR, nr, P->E0, 1.0 / P->dE, first, P->d_normpart, P->n_wg_total,
-                       (const int*)P->d_counters, kNormChunk);
+    auto launch = [&](auto kern) {
+      hipLaunchKernelGGL(kern, dim3(P->blocks_radR), dim3(256), P->lds_radR, P->stream, uk, uo,
+                         h, pkd, P->d_blk_radR, np, (const E*)P->d_TRsF, (const E*)P->d_TRdF,
+                         P->nRhk, P->nRhk * P->nRhk, P->d_V, P->d_D, ng, nR, nr, P->E0,
+                         1.0 / P->dE, first, P->d_normpart, P->n_wg_total,
+                         (const int*)P->d_counters, kNormChunk);
+    };
+    switch (ne) {
+      case 1: launch(k_radR_epi<PR, 1>); break;
+      case 2: launch(k_radR_epi<PR, 2>); break;
+      case 3: launch(k_radR_epi<PR, 3>); break;
+      default: launch(k_radR_epi<PR, 4>); break;
+    }
   }
   hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, P->stream, P->d_counters, rec, 1);
   HIP_TRY(hipGetLastError());
@@ -955,7 +1032,7 @@ int record_via_radr(Plan* P) {
   SliceArgs sa{1, 1, P->d_line_start, P->d_slice_off, (int)P->packets.size(), P->nR, P->m_inf,
                P->d_flux_split, P->d_flux_split + h2, P->d_flux_split + 2 * h2,
                P->d_flux_split + 3 * h2, 1.0 / std::sqrt(P->dR), P->d_ring, P->slice_total,
-               P->d_counters, P->ring_len};
+               P->d_counters, P->ring_len, P->d_radr_pk};
   hipLaunchKernelGGL(k_radr<PR>, dim3((unsigned)((nlines + kRadrLines - 1) / kRadrLines)),
                      dim3(256), P->lds_radr, P->stream, P->d_u[P->cur],
                      reinterpret_cast<typename HType<PR>::T*>(P->d_h), (const E*)P->d_TrsF,
