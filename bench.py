@@ -108,6 +108,8 @@ def main():
                     help="steps per tile variant timed by the library's autotuner (0: off)")
     ap.add_argument("--workload", type=int, default=2,
                     help="workload number 1..5 (default 2: J=0 256x192x80)")
+    ap.add_argument("--radial-grid", type=int, default=0,
+                    help="workgroups of the radial passes (0: one per block)")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="also run one device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -135,6 +137,8 @@ def main():
 
     def timed(precision, steps, warmup):
         plan, info = problem.build(spec, precision=precision, autotune=args.autotune)
+        if args.radial_grid:
+            plan.set_option("radial_grid", args.radial_grid)
         if info.get("autotune"):
             tune_reports[precision] = info["autotune"]
         plan.propagate(warmup, norms=False)

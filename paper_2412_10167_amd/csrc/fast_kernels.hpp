@@ -103,16 +103,20 @@ __global__ __launch_bounds__(256) void k_radr(const double* __restrict__ u,
   const int ps = kRadrLines * ld;
   E* S = reinterpret_cast<E*>(lds);
   E* Dd = S + F::PLANES * ps;
-  const long line0 = (long)blockIdx.x * kRadrLines;
   const int crow = sa.record ? sa.counters[0] : -1;
   const bool rec_ok = crow >= 0 && crow < sa.ring_len;
   double* ring_row = rec_ok ? sa.ring_base + (size_t)crow * sa.ring_stride : nullptr;
+  const long nblk = (nlines + kRadrLines - 1) / kRadrLines;
+  // a workgroup takes blocks blockIdx.x, blockIdx.x + gridDim.x, ...
+  for (long blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+  __syncthreads();   // the previous block's operands have been read
+  const long line0 = blk * kRadrLines;
   // wave w loads lines w, w+4, ...; lanes run along the half line; the loads of
   // a group of G lines are issued before any of them is used
   constexpr int LPW = kRadrLines / 4;
   constexpr int G = 4;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int pk0 = rec_ok ? sa.blk_pk[blockIdx.x] : 0;
+  const int pk0 = rec_ok ? sa.blk_pk[blk] : 0;
 #pragma unroll 1
   for (int g0 = 0; g0 < LPW; g0 += G) {
     int pkx[G];
@@ -186,7 +190,7 @@ __global__ __launch_bounds__(256) void k_radr(const double* __restrict__ u,
       }
     }
   }
-  if (sa.slices_only) return;
+  if (sa.slices_only) continue;
   __syncthreads();
   const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int NT = (nh + 15) >> 4;
@@ -237,6 +241,7 @@ __global__ __launch_bounds__(256) void k_radr(const double* __restrict__ u,
         h[gl * nr + nr - 1 - a] = (typename HType<P>::T)((double)hm[v] + ys - yd);
       }
     }
+  }
   }
 }
 
@@ -683,8 +688,12 @@ __global__ __launch_bounds__(256) void k_radR_epi(
   double* __restrict__ normpart_row =
       (nrow_ix >= 0 && nrow_ix < norm_rows) ? normpart + (size_t)nrow_ix * n_wg_total : nullptr;
   __shared__ double red[4];
-  const int pk = find_packet(blk_start, n_pk, blockIdx.x);
-  const int local = blockIdx.x - blk_start[pk];
+  const int nblk = blk_start[n_pk];
+  // a workgroup takes blocks blockIdx.x, blockIdx.x + gridDim.x, ...
+  for (int blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+  __syncthreads();   // the previous block's tile and partials have been read
+  const int pk = find_packet(blk_start, n_pk, blk);
+  const int local = blk - blk_start[pk];
   const PkDesc dsc = pks[pk];
   const double* __restrict__ uk = uk_all + dsc.off;
   double* __restrict__ uprev = uprev_all + dsc.off;
@@ -819,6 +828,7 @@ __global__ __launch_bounds__(256) void k_radR_epi(
   if (l == 0) red[w] = nsum;
   __syncthreads();
   if (threadIdx.x == 0 && normpart_row) normpart_row[dsc.wg_off + local] = red[0] + red[1] + red[2] + red[3];
+  }
 }
 
 // Converts an FP64 operator table to compute format (planes ps elements apart).

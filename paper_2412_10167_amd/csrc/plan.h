@@ -80,6 +80,8 @@ struct tdwp_plan_s {
   int ntr = 1;               // 16-column tiles per k_radR_epi workgroup
   int nta = 1;               // 16-column tiles per angular workgroup
   int ang_regs = 0;          // angular kernel: 0 k_ang, else k_angr with this many helicities
+  long radial_grid = 0;      // workgroups of the two radial passes (0: one per block)
+  int ang_pref = 0;          // angular kernel: 0 automatic, 1 k_ang, 2 k_angr
   int nrhk = 0, nRhk = 0, ngk = 0, ngr = 0;
   size_t lds_radr = 0, lds_ang = 0, lds_radR = 0;
   std::vector<double> Trs, Trd, TRs, TRd, Pc;

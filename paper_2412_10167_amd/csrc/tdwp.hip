@@ -275,11 +275,12 @@ bool ang_config(Plan* P, int nt, int* regs, size_t* lds) {
   const size_t tiles = ((size_t)max_om * 2 * 16 * nt * ld_of(prec, kpa) * eb + 15) / 16 * 16;
   const int mom = max_om <= 1 ? 1 : (max_om <= 8 ? 8 : 16);
   const int tpw = ((P->ng + 15) / 16 * nt + 3) / 4;
-  if (max_om <= kMaxOmega && tpw <= 16 / mom && tiles <= kLdsMax) {
+  if (P->ang_pref != 1 && max_om <= kMaxOmega && tpw <= 16 / mom && tiles <= kLdsMax) {
     *regs = mom;
     *lds = tiles;
     return true;
   }
+  if (P->ang_pref == 2) return false;
   const int mt_per = (kpa + 15) / 16;
   const int per_wave = (max_om * 2 * mt_per + 3) / 4;
   if (per_wave * nt > kAngMaxAcc || tiles + ang_tab > kLdsMax) return false;
@@ -826,6 +827,11 @@ int prepare_record(Plan* P, Timing* T) {
   return TDWP_OK;
 }
 
+// Workgroups of a radial pass over n blocks (each workgroup loops over its blocks).
+unsigned radial_blocks(const Plan* P, long n) {
+  return (unsigned)((P->radial_grid > 0 && P->radial_grid < n) ? P->radial_grid : n);
+}
+
 // Launches the kernels of one step of the matrix-core path (no host state change):
 // u_k in d_u[cur], u_{k-1} in d_u[1 - cur]; rec: record the slices of u_k.
 template <int PR>
@@ -886,7 +892,7 @@ int enqueue_step(Plan* P, int cur, int first, int rec, Timing* T) {
                  P->d_flux_split, P->d_flux_split + h2, P->d_flux_split + 2 * h2,
                  P->d_flux_split + 3 * h2, 1.0 / std::sqrt(P->dR), P->d_ring, P->slice_total,
                  P->d_counters, P->ring_len, P->d_radr_pk};
-    hipLaunchKernelGGL(k_radr<PR>, dim3((unsigned)((nlines + kRadrLines - 1) / kRadrLines)),
+    hipLaunchKernelGGL(k_radr<PR>, dim3(radial_blocks(P, (nlines + kRadrLines - 1) / kRadrLines)),
                        dim3(256), P->lds_radr, P->stream, uk, h, (const E*)P->d_TrsF,
                        (const E*)P->d_TrdF, P->nrhk, P->nrhk * P->nrhk, nr, nlines, sa);
   }
@@ -903,7 +909,8 @@ int enqueue_step(Plan* P, int cur, int first, int rec, Timing* T) {
                        (const int*)P->d_counters, kNormChunk);
   } else {
     auto launch = [&](auto kern) {
-      hipLaunchKernelGGL(kern, dim3(P->blocks_radR), dim3(256), P->lds_radR, P->stream, uk, uo,
+      hipLaunchKernelGGL(kern, dim3(radial_blocks(P, P->blocks_radR)), dim3(256), P->lds_radR,
+                         P->stream, uk, uo,
                          h, pkd, P->d_blk_radR, np, (const E*)P->d_TRsF, (const E*)P->d_TRdF,
                          P->nRhk, P->nRhk * P->nRhk, P->d_V, P->d_D, ng, nR, nr, P->E0,
                          1.0 / P->dE, first, P->d_normpart, P->n_wg_total,
@@ -1033,7 +1040,7 @@ int record_via_radr(Plan* P) {
                P->d_flux_split, P->d_flux_split + h2, P->d_flux_split + 2 * h2,
                P->d_flux_split + 3 * h2, 1.0 / std::sqrt(P->dR), P->d_ring, P->slice_total,
                P->d_counters, P->ring_len, P->d_radr_pk};
-  hipLaunchKernelGGL(k_radr<PR>, dim3((unsigned)((nlines + kRadrLines - 1) / kRadrLines)),
+  hipLaunchKernelGGL(k_radr<PR>, dim3(radial_blocks(P, (nlines + kRadrLines - 1) / kRadrLines)),
                      dim3(256), P->lds_radr, P->stream, P->d_u[P->cur],
                      reinterpret_cast<typename HType<PR>::T*>(P->d_h), (const E*)P->d_TrsF,
                      (const E*)P->d_TrdF, P->nrhk, P->nrhk * P->nrhk, nr, nlines, sa);
@@ -1353,23 +1360,20 @@ int tdwp_set_initial_packet(tdwp_plan_t p, const tdwp_packet* pk, const double* 
   HIP_TRY(hipMemsetAsync(p->d_snap + P.snap_off, 0, (size_t)2 * p->cfg.n_energy * P.n_w * sizeof(double), p->stream));
   P.snap_taken = (pk->k_min_elastic == 0);
   HIP_TRY(hipMemcpyAsync(p->d_E + ip, &pk->E_v0j0, sizeof(double), hipMemcpyHostToDevice, p->stream));
-  // k = 0 slices into ring row 0 (packets not yet set are overwritten when they are)
+  // k = 0 slices: the matrix-core path records them inside the first step (or in
+  // finish_slices), once for all packets; the general path records them here into
+  // ring row 0 (packets not yet set are overwritten when they are)
   p->ring_count = 0;
   p->norm_row = 0;
+  p->ring_k0 = 0;
   if (p->fast) {
     TRY(sync_counters(p));
-    switch (p->cfg.precision) {
-      case TDWP_FP64: TRY(record_via_radr<kP64>(p)); break;
-      case TDWP_FP32: TRY(record_via_radr<kP32>(p)); break;
-      case TDWP_BF16X3: TRY(record_via_radr<kPBF>(p)); break;
-      default: TRY(record_via_radr<kPF16>(p)); break;
-    }
+    p->rec_k = -1;
   } else {
     TRY(record_slices(p, 0));
+    p->ring_count = 1;
+    p->rec_k = 0;
   }
-  p->ring_k0 = 0;
-  p->ring_count = 1;
-  p->rec_k = 0;
   P.set = true;
   HIP_TRY(hipStreamSynchronize(p->stream));
   return TDWP_OK;
@@ -1557,6 +1561,25 @@ int tdwp_set_option(tdwp_plan_t p, int option, long value) {
       TRY(set_ang_tiles(p, (int)value));
       drop_graphs(p);
       return TDWP_OK;
+    case TDWP_OPT_ANG_KERNEL: {
+      if (!p->fast || value < 0 || value > 2) return TDWP_EINVAL;
+      const int keep = p->ang_pref;
+      p->ang_pref = (int)value;
+      int regs = 0;
+      size_t lds = 0;
+      if (!ang_config(p, p->nta, &regs, &lds)) {
+        p->ang_pref = keep;
+        return TDWP_EINVAL;
+      }
+      TRY(set_ang_tiles(p, p->nta));
+      drop_graphs(p);
+      return TDWP_OK;
+    }
+    case TDWP_OPT_RADIAL_GRID:
+      if (value < 0 || value > (1L << 30)) return TDWP_EINVAL;
+      p->radial_grid = value;
+      drop_graphs(p);
+      return TDWP_OK;
     default:
       return TDWP_EINVAL;
   }
@@ -1567,6 +1590,7 @@ int tdwp_get_stat(tdwp_plan_t p, int stat, long* value) {
   switch (stat) {
     case TDWP_STAT_GRAPH_STEPS: *value = p->graph_steps; return TDWP_OK;
     case TDWP_STAT_ANG_TILE: *value = p->fast ? p->nta : 0; return TDWP_OK;
+    case TDWP_STAT_ANG_KERNEL: *value = p->fast ? (p->ang_regs ? 2 : 1) : 0; return TDWP_OK;
     case TDWP_STAT_MATRIX_CORE_PATH: *value = p->fast ? 1 : 0; return TDWP_OK;
     default: return TDWP_EINVAL;
   }

@@ -294,6 +294,40 @@ def test_angular_tile_variants(nt):
         plan.close()
 
 
+@pytest.mark.parametrize("kernel", [1, 2])
+def test_angular_kernels(kernel):
+    banner(f"angular kernel {kernel}: J=0, J=5 Omega 1..3 2 states, J=20 Omega 0..8 2 states")
+    problem = _problem()
+    for spec in (small_variant(1, n_R=24, n_r=20, n_gamma=10), _coriolis_spec(5, 1, 3, 2),
+                 _coriolis_spec(20, 1, 8, 2)):
+        plan, _ = problem.build(spec)
+        plan.set_option("ang_kernel", kernel)
+        assert plan.stat("ang_kernel") == kernel
+        K = 40
+        plan.propagate(K)
+        op, ref = oracle_packets(spec, K, keep=(K,))
+        assert rel_err(plan.get_packet(0, 0, 0), ref[(0, 0)][0]["vectors"][K]) < PKT_TOL
+        plan.close()
+
+
+@pytest.mark.parametrize("grid", [1, 7])
+def test_radial_grid_is_bit_identical(grid):
+    banner(f"radial passes on {grid} looping workgroups == one workgroup per block")
+    spec = _coriolis_spec(5, 1, 3, 2)
+    problem = _problem()
+    a, _ = problem.build(spec)
+    b, _ = problem.build(spec)
+    b.set_option("radial_grid", grid)
+    na, nb = a.propagate(45), b.propagate(45)
+    assert np.array_equal(na, nb)
+    assert np.array_equal(a.get_packet(0, 0, 0), b.get_packet(0, 0, 0))
+    chans = problem.channels(a, spec, 0, 3, 1)
+    pa, pb = a.state_to_state(0, 0, chans), b.state_to_state(0, 0, chans)
+    assert np.array_equal(pa[0], pb[0]) and np.array_equal(pa[1], pb[1])
+    a.close()
+    b.close()
+
+
 def test_autotune_then_parity():
     banner("autotune before packets, then FP64 parity")
     spec = _coriolis_spec(4, 1, 4, 3, cfg=5)

@@ -22,6 +22,15 @@ def test_header_and_binding_agree():
     assert header_symbols() == set(EXPORTED_SYMBOLS)
 
 
+def test_option_and_statistic_codes_agree_with_the_header():
+    from paper_2412_10167_amd.tdwp import OPTIONS, STATS
+    text = open(os.path.join(ROOT, "include", "tdwp.h")).read()
+    for prefix, table in (("TDWP_OPT_", OPTIONS), ("TDWP_STAT_", STATS)):
+        declared = {m.group(1).lower(): int(m.group(2))
+                    for m in re.finditer(prefix + r"(\w+)\s*=\s*(\d+)", text)}
+        assert declared == table, prefix
+
+
 def test_library_exports_every_declared_symbol():
     lib = load_library()
     for name in header_symbols():
