@@ -49,19 +49,54 @@ def kernel_model(spec, name, precision):
     hb = 8 if precision == "fp64" else 4
     fp64 = precision == "fp64"
     if name == "radial_R_epilogue":
-        # T_R split: nR flops per value; bytes: u_k, h, u_{k-1}, V, u_{k+1}
+        # T_R split: nR flops per value; bytes: u_k, h, u_{k-1}, V (shared by the
+        # helicity blocks of a point), u_{k+1}
         flops, byts = values * nR, values * (8 + hb + 8 + 8 * ne * (ne + 1) / 2 / (n_blk * ne) + 8)
     elif name == "radial_r":
-        flops, byts = values * nr, values * (8 + hb)
+        # T_r split: nr flops per value; bytes: u_k, h read and written
+        flops, byts = values * nr, values * (8 + 2 * hb)
     elif name == "angular":
-        flops, byts = values * 2 * ng, values * (8 + 2 * hb)
-    elif name == "slices":
-        flops, byts = values * 4, values * 8
+        # forward by absolute j (2 ng flops per value), back by parity class (ng);
+        # bytes: u_k, h written
+        flops, byts = values * 3 * ng, values * (8 + hb)
     else:
         return None
     if fp64 and flops / byts > PEAKS["fp64"][0] * 1e3 / PEAKS["hbm"][0]:
         return "mfma", flops / 1e12, "TFLOP/s", PEAKS["fp64"][0], byts
     return "hbm", byts / 1e9, "GB/s", PEAKS["hbm"][0], byts
+
+
+KERNEL_SOURCES = ("paper_2412_10167_amd/csrc/fast_kernels.hpp", "paper_2412_10167_amd/csrc/mfma.hpp",
+                  "paper_2412_10167_amd/csrc/tdwp.hip")
+
+
+def kernel_source_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, workload, precision):
+    """HBM bytes per launch of `kernel` from the committed PMC summary of this
+    workload and precision (FETCH_SIZE and WRITE_SIZE scaled by a device copy of
+    known size), or None when there is none or the kernel sources have changed
+    since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"step_kernels_w{workload}_{precision}_hbm_traffic.md")
+    if not os.path.exists(path):
+        return None
+    digest, table = None, {}
+    for line in open(path):
+        if line.startswith("kernel sources sha256/16:"):
+            digest = line.split(":", 1)[1].strip()
+        elif line.startswith("traffic_bytes "):
+            _, name, val = line.split()
+            table[name] = float(val)
+    if digest != kernel_source_digest():
+        return None
+    return table.get(kernel)
 
 
 def cpu_baseline(spec, budget_s=15.0):
@@ -98,7 +133,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=400)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--precision", default="fp32",
+    ap.add_argument("--precision", default="fp16x3",
                     help="contraction precision of the timed form: fp64, fp32, bf16x3, fp16x3")
     ap.add_argument("--no-fp64-reference", action="store_true",
                     help="skip timing the plain FP64 form beside a mixed form")
@@ -157,10 +192,11 @@ def main():
     kt = plan.time_kernels(args.kernel_steps)
     per_step = {k: v for k, v in kt.items()}
     dom = max((k for k in per_step if kernel_model(spec, k, args.precision)), key=lambda k: per_step[k])
+    traffic = measured_traffic(dom, args.workload, args.precision)
     bound, amount, unit, peak, _ = kernel_model(spec, dom, args.precision)
     achieved = amount / (per_step[dom] * 1e-6)
     roofline = dict(bound=bound, achieved=round(achieved, 3), peak=peak, unit=unit,
-                    frac=round(achieved / peak, 4), traffic=None, kernel=dom,
+                    frac=round(achieved / peak, 4), traffic=traffic, kernel=dom,
                     kernel_avg_us=round(per_step[dom], 2),
                     kernels_avg_us={k: round(v, 2) for k, v in per_step.items()})
     plan.close()
