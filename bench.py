@@ -99,6 +99,28 @@ def measured_traffic(kernel, workload, precision):
     return table.get(kernel)
 
 
+def pe_difference(problem, spec, precision, steps, jmax=10, vmax=2):
+    """Largest |P(E)| difference between the timed form and the FP64 form after the
+    same number of steps: reactive probability per state and every reactant-channel
+    probability (v <= vmax, j <= jmax, all helicities) of every packet, on all
+    collision energies."""
+    import numpy as np
+    res = {}
+    for prec in (precision, "fp64"):
+        plan, _ = problem.build(spec, precision=prec, autotune=0)
+        plan.propagate(steps, norms=False)
+        parts = []
+        for pk in spec["packets"]:
+            chans = problem.channels(plan, spec, pk["unit"], min(jmax, spec["n_gamma"] - 1), vmax)
+            p_inel, p_reac = plan.state_to_state(pk["unit"], pk["slot"], chans)
+            parts += [p_inel.ravel(), p_reac.ravel()]
+        res[prec] = np.concatenate(parts)
+        plan.close()
+    d = np.abs(res[precision] - res["fp64"])
+    return dict(steps=steps, probabilities=int(d.size), max_abs_diff=float(d.max()),
+                max_probability=float(np.max(np.abs(res["fp64"]))))
+
+
 def cpu_baseline(spec, budget_s=15.0):
     """The oracle, untuned, on a bounded sample: as many full-size Chebyshev steps
     as fit in about budget_s seconds after one warm-up step."""
@@ -145,6 +167,9 @@ def main():
                     help="workload number 1..5 (default 2: J=0 256x192x80)")
     ap.add_argument("--radial-grid", type=int, default=0,
                     help="workgroups of the radial passes (0: one per block)")
+    ap.add_argument("--pe-steps", type=int, default=None,
+                    help="steps of the P(E) comparison of the timed form with the FP64 form "
+                         "(default: the workload's full step count on workload 2, else 0 = off)")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="also run one device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -213,6 +238,11 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
 
+    pe_steps = args.pe_steps if args.pe_steps is not None else (spec["steps"] if args.workload == 2 else 0)
+    pe = None
+    if pe_steps > 0 and args.precision != "fp64":
+        pe = pe_difference(problem, spec, args.precision, pe_steps)
+
     cpu = None
     if not args.no_cpu_baseline and args.workload == 2:
         cpu = cpu_baseline(spec)
@@ -236,6 +266,7 @@ def main():
                    "fp64_steps_per_s": round(fp64_rate, 2) if fp64_rate else None,
                    "speedup_vs_fp64": round(steps_per_s / fp64_rate, 3) if fp64_rate else None,
                    "autotune": tune_reports or None,
+                   "pe_vs_fp64": pe,
                    "wall_s": round(wall, 3)},
         "roofline": roofline,
         "cpu_baseline": cpu,
