@@ -115,8 +115,22 @@ __global__ __launch_bounds__(256) void k_radr(const double* __restrict__ u,
   // a group of G lines are issued before any of them is used
   constexpr int LPW = kRadrLines / 4;
   constexpr int G = 4;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int pk0 = rec_ok ? sa.blk_pk[blk] : 0;
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
+  // packet of the block's first line and its bounds (block-uniform loads); a
+  // line past the packet's end (a block straddling two packets) looks up its own
+  int pk0 = 0;
+  long ls0 = 0, ls1 = 0;
+  unsigned long so0 = 0;
+  if (rec_ok) {
+    pk0 = sa.blk_pk[blk];
+    ls0 = sa.line_start[pk0];
+    ls1 = sa.line_start[pk0 + 1];
+    so0 = sa.slice_off[pk0];
+  }
+  // slice values per packet and the packet's offset in the ring row
+  auto nsv_of = [&](int pp) { return pp == pk0 ? ls1 - ls0 : sa.line_start[pp + 1] - sa.line_start[pp]; };
+  auto soff_of = [&](int pp) { return pp == pk0 ? so0 : sa.slice_off[pp]; };
 #pragma unroll 1
   for (int g0 = 0; g0 < LPW; g0 += G) {
     int pkx[G];
@@ -132,9 +146,13 @@ __global__ __launch_bounds__(256) void k_radr(const double* __restrict__ u,
       sv[q] = sd[q] = 0.0;
       if (rec_ok && gl < nlines) {
         int pp = pk0;
-        while (pp + 1 < sa.n_pk && sa.line_start[pp + 1] <= gl) ++pp;
+        long base = ls0;
+        if (gl >= ls1) {
+          while (pp + 1 < sa.n_pk && sa.line_start[pp + 1] <= gl) ++pp;
+          base = sa.line_start[pp];
+        }
         pkx[q] = pp;
-        lidx[q] = (int)(gl - sa.line_start[pp]);
+        lidx[q] = (int)(gl - base);
         rinf[q] = (lidx[q] % sa.nR) == sa.m_inf;
       }
     }
@@ -159,8 +177,8 @@ __global__ __launch_bounds__(256) void k_radr(const double* __restrict__ u,
           sv[q] += sa.a_s[k] * (a + b) + sa.a_d[k] * (a - b);
           sd[q] += sa.d_s[k] * (a + b) + sa.d_d[k] * (a - b);
           if (rinf[q]) {
-            const long nsv = sa.line_start[pkx[q] + 1] - sa.line_start[pkx[q]];
-            double* wline = ring_row + sa.slice_off[pkx[q]] + 2 * nsv + (lidx[q] / sa.nR) * nr;
+            const long nsv = nsv_of(pkx[q]);
+            double* wline = ring_row + soff_of(pkx[q]) + 2 * nsv + (lidx[q] / sa.nR) * nr;
             wline[k] = a * sa.inv_sqrt_dR;
             wline[nr - 1 - k] = b * sa.inv_sqrt_dR;
           }
@@ -182,8 +200,8 @@ __global__ __launch_bounds__(256) void k_radr(const double* __restrict__ u,
           y += __shfl_down(y, off, 64);
         }
         if (lane == 0) {
-          const long nsv = sa.line_start[pkx[q] + 1] - sa.line_start[pkx[q]];
-          double* out = ring_row + sa.slice_off[pkx[q]];
+          const long nsv = nsv_of(pkx[q]);
+          double* out = ring_row + soff_of(pkx[q]);
           out[lidx[q]] = x;
           out[nsv + lidx[q]] = y;
         }
@@ -192,7 +210,7 @@ __global__ __launch_bounds__(256) void k_radr(const double* __restrict__ u,
   }
   if (sa.slices_only) continue;
   __syncthreads();
-  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int l = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int NT = (nh + 15) >> 4;
   const int mt = w & 1;
   const E* Sw = S + 16 * mt * ld;
@@ -311,7 +329,7 @@ __device__ __forceinline__ void ang_back(const typename Fmt<P>::E* __restrict__ 
   using F = Fmt<P>;
   using E = typename F::E;
   constexpr int CH = Chunk<P>::CH;
-  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int l = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int ngh = ng >> 1;
   const int NTh = (ngh + 15) >> 4;
   for (int it = w; it < n_om * NTh; it += 4) {
@@ -409,7 +427,7 @@ __global__ __launch_bounds__(256) void k_ang(const double* __restrict__ u_all,
   for (int q = threadIdx.x; q < d.n_ell; q += blockDim.x) elll[q] = d.ell[q];
   ang_load<P, RT>(X, u, n_om, ne, le, ng, kpa, ld, tile, ps, m, i0, nr, plane);
   __syncthreads();
-  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int l = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int mt_per = (kpa + 15) >> 4;   // forward M-tiles per (omega, class): rows up to kpa
   const size_t tab = (size_t)ngk * ngk;
   typename M::acc_t res[RES][NT];
@@ -546,7 +564,7 @@ __global__ __launch_bounds__(256) void k_angr(const double* __restrict__ u_all,
   E* X = reinterpret_cast<E*>(lds);
   ang_load<P, RT>(X, u, n_om, ne, le, ng, kpa, ld, tile, ps, m, i0, nr, plane);
   __syncthreads();
-  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int l = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int MTj = (ng + 15) >> 4;
   const int n_tiles = MTj * NT;
   typename M::acc_t acc[TPW][MAXOM];
@@ -733,7 +751,7 @@ __global__ __launch_bounds__(256) void k_radR_epi(
       }
     }
   }
-  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int l = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int MT = (nh + 15) >> 4;
   const int t = l & 15;
   const int i = i0 + t;
@@ -857,7 +875,7 @@ __global__ __launch_bounds__(256) void k_accum_mfma(double* __restrict__ acc_all
                                                     const int* __restrict__ blk_start, int n_pk,
                                                     int rows, int count) {
   using M = Mma<kP64>;
-  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int l = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int pk = find_packet(blk_start, n_pk, blockIdx.x);
   const AccDesc ad = ads[pk];
   double* __restrict__ acc = acc_all + ad.acc_off;

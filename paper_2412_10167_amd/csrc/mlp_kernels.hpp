@@ -253,7 +253,7 @@ __global__ __launch_bounds__(256) void k_mlp_eval(MlpNet N, const double* __rest
                                                   int n_pts, double* __restrict__ out) {
   __shared__ __align__(16) __bf16 hs[4][16 * kMlpLd];
   __shared__ float vs[4][16 * 16];
-  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int l = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int p0 = (blockIdx.x * 4 + w) * 16;
   if (p0 >= n_pts) return;
   const int p = p0 + (l & 15);
@@ -272,7 +272,7 @@ __global__ __launch_bounds__(256) void k_mlp_grid(MlpNet N, const double* __rest
                                                   double* __restrict__ out) {
   __shared__ __align__(16) __bf16 hs[4][16 * kMlpLd];
   __shared__ float vs[4][16 * 16];
-  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int l = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const long n_pts = (long)ng * nR * nr;
   const long p0 = ((long)blockIdx.x * 4 + w) * 16;
   if (p0 >= n_pts) return;
@@ -344,7 +344,7 @@ __global__ __launch_bounds__(256) void k_radR_epi_mlp(
   E* SD = reinterpret_cast<E*>(lds + (size_t)ne * nR * RT);    // S^T, D^T of one elec
   const size_t sd_bytes = ((size_t)F::PLANES * ps * sizeof(E) + 15) / 16 * 16;
   char* scratch = reinterpret_cast<char*>(SD) + sd_bytes;
-  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int l = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   __bf16* Hs = reinterpret_cast<__bf16*>(scratch + (size_t)w * (16 * kMlpLd * 2 + 16 * 16 * 4));
   float* Vs = reinterpret_cast<float*>(reinterpret_cast<char*>(Hs) + 16 * kMlpLd * 2);
   {
