@@ -121,6 +121,72 @@ def pe_difference(problem, spec, precision, steps, jmax=10, vmax=2):
                 max_probability=float(np.max(np.abs(res["fp64"]))))
 
 
+def mlp_bench(args, torch, problem, config):
+    """Learned potential: device training from the tabulated surface (timed apart),
+    grid error of the network, and the step with the network evaluated on the fly
+    against the tabulated step of the same plan shape.  Prints one JSON line."""
+    import numpy as np
+    from workloads.mlp_inputs import batch_order, init_params, sample_indices
+    wl = args.workload if args.workload != 2 else 5
+    spec = config(wl)
+    torch.cuda.set_device(0)
+    torch.cuda.set_stream(torch.cuda.Stream())
+    stream = torch.cuda.current_stream()
+    plan_t, _ = problem.build(spec, precision=args.precision, autotune=args.autotune)
+    vtab = problem.potential_table(plan_t, spec)
+    n_pair = vtab.shape[0]
+    n_pts = vtab[0].size
+    idx = sample_indices(n_pts, n_samples=args.mlp_samples)
+    mlp = dict(sample_idx=idx, init_params=init_params(n_pair), order=batch_order(idx.size),
+               batch=args.mlp_batch, epochs=args.mlp_epochs, lr=args.mlp_lr,
+               lr_final=args.mlp_lr_final)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan_m, info = problem.build(spec, precision=args.precision, vtable=vtab, mlp=mlp,
+                                 autotune=args.autotune)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    loss, rms, mx = info["mlp_report"]
+
+    def rate(plan):
+        plan.propagate(args.warmup, norms=False)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        plan.propagate(args.steps, norms=False)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return args.steps / (e0.elapsed_time(e1) / 1e3)
+
+    r_table, r_mlp = rate(plan_t), rate(plan_m)
+    kt = plan_m.time_kernels(args.kernel_steps)
+    plan_t.close()
+    plan_m.close()
+    eh_mev = 27211.386245988
+    values = n_pts * sum((u["omega_max"] - (0 if u["parity"] * (-1) ** u["J"] == 1 else 1) + 1)
+                         * u["n_packets"] for u in spec["units"]) * spec["n_elec"]
+    out = {
+        "metric": "Chebyshev steps/s with the learned potential evaluated on the fly",
+        "value": round(r_mlp, 2), "unit": "Chebyshev steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "higher_is_better": True,
+        "dtype": {"fp64": "f64", "fp32": "f32+f64", "bf16x3": "bf16x3+f64",
+                  "fp16x3": "f16x3+f64"}[args.precision] + ", network bf16/f32",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD_NAMES.get(wl, spec["name"]), "grid_values": values,
+                   "table_steps_per_s": round(r_table, 2),
+                   "table_bytes_per_step": int(vtab.size * 8),
+                   "network_flops_per_step": int(n_pts * 2 * (3 * 128 + 2 * 128 * 128 + 128 * n_pair)),
+                   "training": {"samples": int(idx.size), "epochs": args.mlp_epochs,
+                                "batch": args.mlp_batch, "lr": args.mlp_lr,
+                                "lr_final": args.mlp_lr_final,
+                                "seconds": round(train_s, 2), "final_loss": loss,
+                                "grid_rms_meV": round(rms * eh_mev, 3),
+                                "grid_max_meV": round(mx * eh_mev, 3)},
+                   "kernels_avg_us": {k: round(v, 2) for k, v in kt.items()}},
+    }
+    print(json.dumps(out))
+
+
 def cpu_baseline(spec, budget_s=15.0):
     """The oracle, untuned, on a bounded sample: as many full-size Chebyshev steps
     as fit in about budget_s seconds after one warm-up step."""
@@ -170,6 +236,15 @@ def main():
     ap.add_argument("--pe-steps", type=int, default=None,
                     help="steps of the P(E) comparison of the timed form with the FP64 form "
                          "(default: the workload's full step count on workload 2, else 0 = off)")
+    ap.add_argument("--mlp", action="store_true",
+                    help="learned-potential run: train the network on the device from the "
+                         "tabulated surface, then time the step with the network evaluated on "
+                         "the fly beside the tabulated step (default workload 5)")
+    ap.add_argument("--mlp-samples", type=int, default=200000)
+    ap.add_argument("--mlp-epochs", type=int, default=40)
+    ap.add_argument("--mlp-batch", type=int, default=1024)
+    ap.add_argument("--mlp-lr", type=float, default=2e-3)
+    ap.add_argument("--mlp-lr-final", type=float, default=2e-5)
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="also run one device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -182,6 +257,9 @@ def main():
     import torch
     from paper_2412_10167_amd import problem
     from workloads import config
+
+    if args.mlp:
+        return mlp_bench(args, torch, problem, config)
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)

@@ -157,7 +157,9 @@ typedef struct {
                               /* takes order[(e*n_samples + b*batch + j) % n_samples]   */
   int batch;                  /* minibatch size, 1..4096                               */
   int epochs;
-  double lr;                  /* Adam step size                                        */
+  double lr;                  /* Adam step size (at the first minibatch)               */
+  double lr_final;            /* step size at the last minibatch, reached by a cosine  */
+                              /* decay over all minibatches; 0: constant lr            */
 } tdwp_mlp_options;
 
 /* Number of parameters of the learned potential for this plan's n_elec. */

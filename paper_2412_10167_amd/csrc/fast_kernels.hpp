@@ -677,6 +677,8 @@ __global__ __launch_bounds__(256) void k_angr(const double* __restrict__ u_all,
 }
 
 // ---- T_R along R, potential, scaling, recursion, damping, norm partial ---------------
+// (SPLIT: only y = T_R u + h is formed and stored in h's place; the learned-potential
+// pass k_mlp_epi adds the potential and finishes the step.)
 // One workgroup per (r tile of 16 columns, slab (omega, gamma)) of one packet, all
 // NE electronic states.  The raw FP64 tile X[elec][R][t] stays in LDS for the
 // epilogue; per elec the sum/difference operand (rows t, contraction over R) is
@@ -686,10 +688,10 @@ __global__ __launch_bounds__(256) void k_angr(const double* __restrict__ u_all,
 // contraction) so that one memory latency is paid per batch, not per element.
 constexpr int kLoadBatch = 8;
 
-template <int P, int NE>
+template <int P, int NE, bool SPLIT = false>
 __global__ __launch_bounds__(256) void k_radR_epi(
     const double* __restrict__ uk_all, double* __restrict__ uprev_all,
-    const typename HType<P>::T* __restrict__ h_all, const PkDesc* __restrict__ pks,
+    typename HType<P>::T* __restrict__ h_all, const PkDesc* __restrict__ pks,
     const int* __restrict__ blk_start, int n_pk, const typename Fmt<P>::E* __restrict__ Ts,
     const typename Fmt<P>::E* __restrict__ Td, int ldt, int pst, const double* __restrict__ V,
     const double* __restrict__ D, int ng, int nR, int nr, double E0, double inv_dE,
@@ -715,7 +717,7 @@ __global__ __launch_bounds__(256) void k_radR_epi(
   const PkDesc dsc = pks[pk];
   const double* __restrict__ uk = uk_all + dsc.off;
   double* __restrict__ uprev = uprev_all + dsc.off;
-  const HT* __restrict__ h = h_all + dsc.off;
+  HT* __restrict__ h = h_all + dsc.off;
   const int nrt = (nr + RT - 1) / RT;
   const int nh = nR >> 1;
   const int kp = round_up(nh, M::KS);
@@ -791,13 +793,15 @@ __global__ __launch_bounds__(256) void k_radR_epi(
           const size_t pt = (size_t)n * plane + (size_t)mm * nr + ic;
           const size_t idx = (size_t)(o * NE + le) * ng * plane + pt;
           hv[q] = h[idx];
-          dv[q] = D[(size_t)mm * nr + ic];
-          pv[q] = first ? 0.0 : uprev[idx];
+          if constexpr (!SPLIT) {
+            dv[q] = D[(size_t)mm * nr + ic];
+            pv[q] = first ? 0.0 : uprev[idx];
 #pragma unroll
-          for (int l2 = 0; l2 < NE; ++l2) {
-            const int a0 = le < l2 ? le : l2, a1 = le < l2 ? l2 : le;
-            const int pi = a0 * NE - a0 * (a0 - 1) / 2 + (a1 - a0);
-            vv[q][l2] = V[(size_t)pi * ng * plane + pt];
+            for (int l2 = 0; l2 < NE; ++l2) {
+              const int a0 = le < l2 ? le : l2, a1 = le < l2 ? l2 : le;
+              const int pi = a0 * NE - a0 * (a0 - 1) / 2 + (a1 - a0);
+              vv[q][l2] = V[(size_t)pi * ng * plane + pt];
+            }
           }
         }
       const E* As = Ts + (size_t)mt * 16 * ldt;
@@ -829,8 +833,12 @@ __global__ __launch_bounds__(256) void k_radR_epi(
           const int q = 2 * v + side;
           const int mm = side ? nR - 1 - a : a;
           const size_t idx = (size_t)(o * NE + le) * ng * plane + (size_t)n * plane + (size_t)mm * nr + i;
-          const double ukv = Xl[mm * RT + t];
           double sacc = (side ? ys - yd : ys + yd) + (double)hv[q];
+          if constexpr (SPLIT) {   // T_R u + h only; the potential and the recursion follow
+            h[idx] = (HT)sacc;
+            continue;
+          }
+          const double ukv = Xl[mm * RT + t];
 #pragma unroll
           for (int l2 = 0; l2 < NE; ++l2) sacc += vv[q][l2] * X[((size_t)l2 * nR + mm) * RT + t];
           const double wv = (sacc - E0 * ukv) * inv_dE;
@@ -842,10 +850,12 @@ __global__ __launch_bounds__(256) void k_radR_epi(
       }
     }
   }
-  for (int off = 32; off > 0; off >>= 1) nsum += __shfl_down(nsum, off, 64);
-  if (l == 0) red[w] = nsum;
-  __syncthreads();
-  if (threadIdx.x == 0 && normpart_row) normpart_row[dsc.wg_off + local] = red[0] + red[1] + red[2] + red[3];
+  if constexpr (!SPLIT) {
+    for (int off = 32; off > 0; off >>= 1) nsum += __shfl_down(nsum, off, 64);
+    if (l == 0) red[w] = nsum;
+    __syncthreads();
+    if (threadIdx.x == 0 && normpart_row) normpart_row[dsc.wg_off + local] = red[0] + red[1] + red[2] + red[3];
+  }
   }
 }
 

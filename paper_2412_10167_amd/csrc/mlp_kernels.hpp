@@ -148,6 +148,8 @@ struct MlpNet {
   const float* b3;
   const float* b4;     // [16]
   int npair;
+  int s1 = 32;         // row strides (elements) of w1t and of w2t, w3t, w4t
+  int s2 = kMlpH;
 };
 
 // Packs FP32 master parameters into the inference layout.
@@ -186,22 +188,29 @@ __global__ void k_mlp_pack(const float* __restrict__ th, int npair, __bf16* __re
 
 __device__ __forceinline__ v8bf ld8(const __bf16* p) { return *reinterpret_cast<const v8bf*>(p); }
 
-// One wavefront evaluates the network on 16 points.  Lane l supplies the
-// features of point l % 16 (feat, already normalised).  Hs: per-wave LDS tile
-// [16][kMlpLd] bf16; Vs: per-wave LDS [16][16] float receiving V (hartree).
-__device__ __forceinline__ void mlp_wave16(const MlpNet& N, const float* feat, __bf16* Hs,
-                                           float* Vs, int l) {
+// One wavefront evaluates the network on 16 MTP points (MTP tiles of 16).  Lane l
+// supplies the features of point 16 mt + l % 16 of each tile (feat[mt], already
+// normalised).  Hs: per-wave LDS tile [16 MTP][kMlpLd] bf16; Vs: per-wave LDS
+// [16 MTP][16] float receiving V (hartree).  Every weight fragment is read once
+// and applied to all MTP tiles; per point the arithmetic does not depend on MTP.
+template <int MTP>
+__device__ __forceinline__ void mlp_wave(const MlpNet& N, const float (&feat)[MTP][3], __bf16* Hs,
+                                         float* Vs, int l) {
   const int row = l & 15, kq = 8 * (l >> 4);
-  v4f acc[8];
+  v4f acc[MTP][8];
   // layer 1: K = 3 (padded to 32)
   {
-    v8bf a;
+    v8bf a[MTP];
 #pragma unroll
-    for (int t = 0; t < 8; ++t) a[t] = (__bf16)((kq + t) < 3 ? feat[kq + t] : 0.0f);
+    for (int mt = 0; mt < MTP; ++mt)
+#pragma unroll
+      for (int t = 0; t < 8; ++t) a[mt][t] = (__bf16)((kq + t) < 3 ? feat[mt][kq + t] : 0.0f);
 #pragma unroll
     for (int nt = 0; nt < 8; ++nt) {
-      acc[nt] = v4f{0, 0, 0, 0};
-      acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, ld8(N.w1t + (nt * 16 + row) * 32 + kq), acc[nt], 0, 0, 0);
+      const v8bf b = ld8(N.w1t + (nt * 16 + row) * N.s1 + kq);
+#pragma unroll
+      for (int mt = 0; mt < MTP; ++mt)
+        acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt], b, v4f{0, 0, 0, 0}, 0, 0, 0);
     }
   }
 #pragma unroll
@@ -210,42 +219,64 @@ __device__ __forceinline__ void mlp_wave16(const MlpNet& N, const float* feat, _
     const __bf16* wl = layer == 0 ? N.w2t : N.w3t;
     // bias + SiLU, store as the next A operand (row = point, k = unit)
 #pragma unroll
-    for (int nt = 0; nt < 8; ++nt)
+    for (int mt = 0; mt < MTP; ++mt)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int pr = 4 * (l >> 4) + v, col = nt * 16 + row;
-        Hs[pr * kMlpLd + col] = (__bf16)silu_f(acc[nt][v] + bl[col]);
-      }
+      for (int nt = 0; nt < 8; ++nt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int pr = 16 * mt + 4 * (l >> 4) + v, col = nt * 16 + row;
+          Hs[pr * kMlpLd + col] = (__bf16)silu_f(acc[mt][nt][v] + bl[col]);
+        }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
-    v8bf a[4];
+    v8bf a[MTP][4];
 #pragma unroll
-    for (int ks = 0; ks < 4; ++ks) a[ks] = ld8(Hs + row * kMlpLd + ks * 32 + kq);
+    for (int mt = 0; mt < MTP; ++mt)
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks) a[mt][ks] = ld8(Hs + (16 * mt + row) * kMlpLd + ks * 32 + kq);
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
     if (layer < 2) {
 #pragma unroll
       for (int nt = 0; nt < 8; ++nt) {
-        acc[nt] = v4f{0, 0, 0, 0};
 #pragma unroll
-        for (int ks = 0; ks < 4; ++ks)
-          acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-              a[ks], ld8(wl + (nt * 16 + row) * kMlpH + ks * 32 + kq), acc[nt], 0, 0, 0);
+        for (int mt = 0; mt < MTP; ++mt) acc[mt][nt] = v4f{0, 0, 0, 0};
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+          const v8bf b = ld8(wl + (nt * 16 + row) * N.s2 + ks * 32 + kq);
+#pragma unroll
+          for (int mt = 0; mt < MTP; ++mt)
+            acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt][ks], b, acc[mt][nt], 0, 0, 0);
+        }
       }
     } else {
-      v4f o = v4f{0, 0, 0, 0};
+      v4f o[MTP];
 #pragma unroll
-      for (int ks = 0; ks < 4; ++ks)
-        o = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[ks], ld8(N.w4t + row * kMlpH + ks * 32 + kq), o, 0, 0, 0);
+      for (int mt = 0; mt < MTP; ++mt) o[mt] = v4f{0, 0, 0, 0};
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int pr = 4 * (l >> 4) + v;
-        Vs[pr * 16 + row] = (float)kOutScale * (o[v] + N.b4[row]);
+      for (int ks = 0; ks < 4; ++ks) {
+        const v8bf b = ld8(N.w4t + row * N.s2 + ks * 32 + kq);
+#pragma unroll
+        for (int mt = 0; mt < MTP; ++mt)
+          o[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt][ks], b, o[mt], 0, 0, 0);
       }
+#pragma unroll
+      for (int mt = 0; mt < MTP; ++mt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int pr = 16 * mt + 4 * (l >> 4) + v;
+          Vs[pr * 16 + row] = (float)kOutScale * (o[mt][v] + N.b4[row]);
+        }
     }
   }
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   __builtin_amdgcn_wave_barrier();
+}
+
+__device__ __forceinline__ void mlp_wave16(const MlpNet& N, const float* feat, __bf16* Hs,
+                                           float* Vs, int l) {
+  const float f[1][3] = {{feat[0], feat[1], feat[2]}};
+  mlp_wave<1>(N, f, Hs, Vs, l);
 }
 
 // Inference on arbitrary points (tests, bounds): one wave per 16 points.
@@ -288,167 +319,145 @@ __global__ __launch_bounds__(256) void k_mlp_grid(MlpNet N, const double* __rest
     for (int q = 0; q < N.npair; ++q) out[(size_t)q * n_pts + p] = (double)vs[w][l * 16 + q];
 }
 
-// Row selector of the accumulator layout: the item v of lane l that holds tile row rr, or -1.
-template <int P> __device__ __forceinline__ int vsel(int l, int rr) {
-  if (P == kP64) return ((l >> 4) == (rr & 3)) ? (rr >> 2) : -1;
-  return ((l >> 4) == (rr >> 2)) ? (rr & 3) : -1;
+// ---- the step with the potential evaluated by the network --------------------------
+// Runs after k_radR_epi<P, NE, true>, which leaves y = T_R u + h in h's place.
+// Resident workgroups (the weights staged in LDS once each) take blocks of 256
+// grid points (gamma, R, r); a wave evaluates the network on 32 points at a time,
+// once per point for every packet and helicity, then finishes the step there:
+//   u_{k+1} = D (2 (y + sum_l' V_ll' u_l' - E0 u_l)/dE - D u_{k-1})   (first step: D w).
+// Norm partials: one per (workgroup, packet), at normpart_row[packet * gridDim.x + block].
+constexpr int kMlpW1Ld = 40;   // LDS row strides of the staged weights (bf16)
+constexpr int kMlpWLd = 136;
+constexpr size_t kMlpEpiWeights = (size_t)(kMlpH * kMlpW1Ld + 2 * kMlpH * kMlpWLd + 16 * kMlpWLd) * 2 +
+                                  (3 * kMlpH + 16) * 4;
+constexpr size_t kMlpEpiWave = (size_t)32 * kMlpLd * 2 + 32 * 16 * 4;
+
+__host__ __device__ constexpr size_t mlp_epi_lds(int n_pk) {
+  return kMlpEpiWeights + 4 * kMlpEpiWave + (size_t)4 * n_pk * sizeof(double);
 }
 
-template <class A> __device__ __forceinline__ double pick(const A& a, int v) {
-  return (double)(v == 0 ? a[0] : v == 1 ? a[1] : v == 2 ? a[2] : a[3]);
-}
-
-constexpr int kMlpMaxMT = 2;   // R M-tiles per wave (n_R <= 256)
-constexpr int kMlpMaxElec = 4;
-
-// k_radR_epi with the potential evaluated by the network at every point of the
-// tile instead of read from a table.  Phase 1 forms T_R u for every elec (results
-// kept in registers); phase 2 walks the tile rows 16 points at a time: one
-// network evaluation per point serves every elec.
-template <int P>
-__global__ __launch_bounds__(256) void k_radR_epi_mlp(
-    const double* __restrict__ uk_all, double* __restrict__ uprev_all,
-    const typename HType<P>::T* __restrict__ h_all, const PkDesc* __restrict__ pks,
-    const int* __restrict__ blk_start, int n_pk, const typename Fmt<P>::E* __restrict__ Ts,
-    const typename Fmt<P>::E* __restrict__ Td, int ldt, int pst, MlpNet net,
-    const double* __restrict__ rg, const double* __restrict__ Rg, const double* __restrict__ xg,
-    double cB, double cC, const double* __restrict__ D, int ne, int ng, int nR, int nr,
-    double E0, double inv_dE, int first, double* __restrict__ normpart, size_t n_wg_total,
-    const int* __restrict__ counters, int norm_rows) {
+template <int P, int NE>
+__global__ __launch_bounds__(256) void k_mlp_epi(
+    MlpNet gnet, const double* __restrict__ rg, const double* __restrict__ Rg,
+    const double* __restrict__ xg, double cB, double cC, int ng, int nR, int nr,
+    const PkDesc* __restrict__ pks, int n_pk, const double* __restrict__ uk_all,
+    double* __restrict__ uprev_all, const typename HType<P>::T* __restrict__ y_all,
+    const double* __restrict__ D, double E0, double inv_dE, int first,
+    double* __restrict__ normpart, size_t n_wg_total, const int* __restrict__ counters,
+    int norm_rows) {
+  constexpr int NPAIR = NE * (NE + 1) / 2;
+  extern __shared__ __align__(16) double lds[];
+  const int l = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  __bf16* W1 = reinterpret_cast<__bf16*>(lds);
+  __bf16* W2 = W1 + kMlpH * kMlpW1Ld;
+  __bf16* W3 = W2 + kMlpH * kMlpWLd;
+  __bf16* W4 = W3 + kMlpH * kMlpWLd;
+  float* Bs = reinterpret_cast<float*>(W4 + 16 * kMlpWLd);
+  char* wbase = reinterpret_cast<char*>(lds) + kMlpEpiWeights;
+  __bf16* Hs = reinterpret_cast<__bf16*>(wbase + (size_t)w * kMlpEpiWave);
+  float* Vs = reinterpret_cast<float*>(reinterpret_cast<char*>(Hs) + (size_t)32 * kMlpLd * 2);
+  double* red = reinterpret_cast<double*>(wbase + 4 * kMlpEpiWave);   // [4][n_pk]
+  // stage the weights (16-byte chunks) and biases
+  for (int q = threadIdx.x; q < kMlpH * 4; q += 256) {
+    const int r = q >> 2, c = (q & 3) * 8;
+    *reinterpret_cast<uint4*>(W1 + r * kMlpW1Ld + c) = *reinterpret_cast<const uint4*>(gnet.w1t + r * 32 + c);
+  }
+  for (int q = threadIdx.x; q < kMlpH * 16; q += 256) {
+    const int r = q >> 4, c = (q & 15) * 8;
+    *reinterpret_cast<uint4*>(W2 + r * kMlpWLd + c) = *reinterpret_cast<const uint4*>(gnet.w2t + r * kMlpH + c);
+    *reinterpret_cast<uint4*>(W3 + r * kMlpWLd + c) = *reinterpret_cast<const uint4*>(gnet.w3t + r * kMlpH + c);
+  }
+  for (int q = threadIdx.x; q < 16 * 16; q += 256) {
+    const int r = q >> 4, c = (q & 15) * 8;
+    *reinterpret_cast<uint4*>(W4 + r * kMlpWLd + c) = *reinterpret_cast<const uint4*>(gnet.w4t + r * kMlpH + c);
+  }
+  for (int q = threadIdx.x; q < 3 * kMlpH + 16; q += 256)
+    Bs[q] = q < kMlpH ? gnet.b1[q] : (q < 2 * kMlpH ? gnet.b2[q - kMlpH]
+                                                     : (q < 3 * kMlpH ? gnet.b3[q - 2 * kMlpH] : gnet.b4[q - 3 * kMlpH]));
+  for (int q = threadIdx.x; q < 4 * n_pk; q += 256) red[q] = 0.0;
+  MlpNet net;
+  net.w1t = W1;
+  net.w2t = W2;
+  net.w3t = W3;
+  net.w4t = W4;
+  net.b1 = Bs;
+  net.b2 = Bs + kMlpH;
+  net.b3 = Bs + 2 * kMlpH;
+  net.b4 = Bs + 3 * kMlpH;
+  net.npair = gnet.npair;
+  net.s1 = kMlpW1Ld;
+  net.s2 = kMlpWLd;
+  __syncthreads();
   const int nrow_ix = counters[1];
   double* __restrict__ normpart_row =
       (nrow_ix >= 0 && nrow_ix < norm_rows) ? normpart + (size_t)nrow_ix * n_wg_total : nullptr;
-  using M = Mma<P>;
-  using F = Fmt<P>;
-  using E = typename F::E;
-  constexpr int CH = Chunk<P>::CH;
-  constexpr int RT = 16;
-  extern __shared__ __align__(16) double lds[];
-  __shared__ double red[4];
-  const int pk = find_packet(blk_start, n_pk, blockIdx.x);
-  const int local = blockIdx.x - blk_start[pk];
-  const PkDesc dsc = pks[pk];
-  const double* __restrict__ uk = uk_all + dsc.off;
-  double* __restrict__ uprev = uprev_all + dsc.off;
-  const typename HType<P>::T* __restrict__ h = h_all + dsc.off;
-  const int nrt = (nr + RT - 1) / RT;
-  const int nh = nR >> 1;
-  const int kp = round_up(nh, M::KS);
-  const int ld = tile_ld<P>(kp);
-  const int ps = 2 * RT * ld;
-  const int i0 = (local % nrt) * RT;
-  const int slab = local / nrt;
-  const int o = slab / ng, n = slab % ng;
-  const size_t plane = (size_t)nR * nr;
-  double* X = lds;                                             // [le][nR][RT]
-  E* SD = reinterpret_cast<E*>(lds + (size_t)ne * nR * RT);    // S^T, D^T of one elec
-  const size_t sd_bytes = ((size_t)F::PLANES * ps * sizeof(E) + 15) / 16 * 16;
-  char* scratch = reinterpret_cast<char*>(SD) + sd_bytes;
-  const int l = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  __bf16* Hs = reinterpret_cast<__bf16*>(scratch + (size_t)w * (16 * kMlpLd * 2 + 16 * 16 * 4));
-  float* Vs = reinterpret_cast<float*>(reinterpret_cast<char*>(Hs) + 16 * kMlpLd * 2);
-  {
-    const int tt = threadIdx.x & 15, r0 = threadIdx.x >> 4;
-    const int ii = i0 + tt;
-    for (int le = 0; le < ne; ++le) {
-      const double* src = uk + ((size_t)(o * ne + le) * ng + n) * plane + ii;
-      double* dst = X + (size_t)le * nR * RT + tt;
-      for (int mm = r0; mm < nR; mm += 16) dst[mm * RT] = (ii < nr) ? src[(size_t)mm * nr] : 0.0;
-    }
-  }
-  const int MT = (nh + 15) >> 4;
-  typename M::acc_t acc[kMlpMaxMT][kMlpMaxElec][2];
+  const long plane = (long)nR * nr;
+  const long n_pts = (long)ng * plane;
+  const size_t es = (size_t)ng * plane;   // one (helicity, elec) block of a packet
+  const int row = l & 15, pl = l & 31, hf = l >> 5;
+  for (long b = blockIdx.x; b * 256 < n_pts; b += gridDim.x) {
+#pragma unroll 1
+    for (int pass = 0; pass < 2; ++pass) {
+      const long p0 = b * 256 + w * 64 + pass * 32;
+      float f[2][3];
 #pragma unroll
-  for (int le = 0; le < kMlpMaxElec; ++le) {
-    if (le >= ne) break;
-    __syncthreads();
-    const double* Xl = X + (size_t)le * nR * RT;
-    {
-      const int tt = threadIdx.x & 15;
-      for (int k = threadIdx.x >> 4; k < kp; k += 16) {
-        double a = 0.0, b = 0.0;
-        if (k < nh) {
-          a = Xl[k * RT + tt];
-          b = Xl[(nR - 1 - k) * RT + tt];
+      for (int mt = 0; mt < 2; ++mt) {
+        long p = p0 + 16 * mt + row;
+        p = p < n_pts ? p : n_pts - 1;
+        const int n = (int)(p / plane), m = (int)((p / nr) % nR), i = (int)(p % nr);
+        float d[3];
+        jacobi_distances(rg[i], Rg[m], xg[n], cB, cC, d);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) f[mt][c] = (d[c] - kFeatCenter) / kFeatScale;
+      }
+      mlp_wave<2>(net, f, Hs, Vs, l);
+      // lane l finishes point p0 + l % 32 for the helicities of parity l / 32
+      const long p = p0 + pl;
+      const bool ok = p < n_pts;
+      const long pc = ok ? p : n_pts - 1;
+      const double dmp = D[pc % plane];
+      double V[NPAIR];
+#pragma unroll
+      for (int q = 0; q < NPAIR; ++q) V[q] = (double)Vs[pl * 16 + q];
+      for (int pk = 0; pk < n_pk; ++pk) {
+        const PkDesc d = pks[pk];
+        double nsum = 0.0;
+        for (int o = hf; o < d.n_om; o += 2) {
+          const size_t base = d.off + (size_t)o * NE * es + (size_t)pc;
+          double u[NE], y[NE], up[NE];
+#pragma unroll
+          for (int le = 0; le < NE; ++le) {
+            u[le] = uk_all[base + le * es];
+            y[le] = (double)y_all[base + le * es];
+            up[le] = first ? 0.0 : uprev_all[base + le * es];
+          }
+#pragma unroll
+          for (int le = 0; le < NE; ++le) {
+            double sacc = y[le];
+#pragma unroll
+            for (int l2 = 0; l2 < NE; ++l2) {
+              const int a0 = le < l2 ? le : l2, a1 = le < l2 ? l2 : le;
+              const int pi = a0 * NE - a0 * (a0 - 1) / 2 + (a1 - a0);
+              sacc += V[pi] * u[l2];
+            }
+            const double wv = (sacc - E0 * u[le]) * inv_dE;
+            const double un = first ? dmp * wv : dmp * (2.0 * wv - dmp * up[le]);
+            if (ok) {
+              uprev_all[base + le * es] = un;
+              nsum += un * un;
+            }
+          }
         }
-        F::put(SD, ps, tt * ld + k, a + b);
-        F::put(SD, ps, RT * ld + tt * ld + k, a - b);
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int r = 0; r < kMlpMaxMT; ++r) {
-      const int mt = w + 4 * r;
-      if (mt >= MT) break;
-      const E* As = Ts + (size_t)mt * 16 * ldt;
-      const E* Ad = Td + (size_t)mt * 16 * ldt;
-      acc[r][le][0] = M::zero();
-      acc[r][le][1] = M::zero();
-      for (int k0 = 0; k0 < kp; k0 += CH * M::KS) {
-        typename M::frag_t fs[CH], fd[CH];
-#pragma unroll
-        for (int q = 0; q < CH; ++q)
-          if (k0 + q * M::KS < kp) {
-            fs[q] = F::frag(As, ldt, pst, l, k0 + q * M::KS);
-            fd[q] = F::frag(Ad, ldt, pst, l, k0 + q * M::KS);
-          }
-#pragma unroll
-        for (int q = 0; q < CH; ++q)
-          if (k0 + q * M::KS < kp) {
-            M::mma(acc[r][le][0], fs[q], F::frag(SD, ld, ps, l, k0 + q * M::KS));
-            M::mma(acc[r][le][1], fd[q], F::frag(SD + RT * ld, ld, ps, l, k0 + q * M::KS));
-          }
+        for (int off = 32; off > 0; off >>= 1) nsum += __shfl_down(nsum, off, 64);
+        if (l == 0) red[w * n_pk + pk] += nsum;
       }
     }
   }
-  const int t = l & 15;
-  const int i = i0 + t;
-  const double xn = xg[n];
-  const double ri = rg[i < nr ? i : nr - 1];
-  double nsum = 0.0;
-#pragma unroll
-  for (int r = 0; r < kMlpMaxMT; ++r) {
-    const int mt = w + 4 * r;
-    if (mt >= MT) break;
-    for (int side = 0; side < 2; ++side)
-      for (int rr = 0; rr < 16; ++rr) {
-        const int a = mt * 16 + rr;
-        if (a >= nh) break;
-        const int mm = side ? nR - 1 - a : a;
-        float f[3];
-        jacobi_distances(ri, Rg[mm], xn, cB, cC, f);
-        for (int c = 0; c < 3; ++c) f[c] = (f[c] - kFeatCenter) / kFeatScale;
-        mlp_wave16(net, f, Hs, Vs, l);
-        const int v = vsel<P>(l, rr);
-        if (v < 0 || i >= nr) continue;
-        const size_t pt = (size_t)n * plane + (size_t)mm * nr + i;
-        double Vm[kMlpMaxElec * (kMlpMaxElec + 1) / 2];
-        for (int q = 0; q < net.npair; ++q) Vm[q] = (double)Vs[t * 16 + q];
-#pragma unroll
-        for (int le = 0; le < kMlpMaxElec; ++le) {
-          if (le >= ne) break;
-          const double ys = pick(acc[r][le][0], v) * M::kUnscale;
-          const double yd = pick(acc[r][le][1], v) * M::kUnscale;
-          const size_t idx = (size_t)(o * ne + le) * ng * plane + pt;
-          const double ukv = X[((size_t)le * nR + mm) * RT + t];
-          double sacc = (side ? ys - yd : ys + yd) + (double)h[idx];
-          for (int l2 = 0; l2 < ne; ++l2) {
-            const int a0 = le < l2 ? le : l2, a1 = le < l2 ? l2 : le;
-            const int pi = a0 * ne - a0 * (a0 - 1) / 2 + (a1 - a0);
-            sacc += Vm[pi] * X[((size_t)l2 * nR + mm) * RT + t];
-          }
-          const double wv = (sacc - E0 * ukv) * inv_dE;
-          const double dmp = D[(size_t)mm * nr + i];
-          const double un = first ? dmp * wv : dmp * (2.0 * wv - dmp * uprev[idx]);
-          uprev[idx] = un;
-          nsum += un * un;
-        }
-      }
-  }
-  for (int off = 32; off > 0; off >>= 1) nsum += __shfl_down(nsum, off, 64);
-  if (l == 0) red[w] = nsum;
   __syncthreads();
-  if (threadIdx.x == 0 && normpart_row) normpart_row[dsc.wg_off + local] = red[0] + red[1] + red[2] + red[3];
+  for (int pk = threadIdx.x; pk < n_pk; pk += 256)
+    if (normpart_row)
+      normpart_row[(size_t)pk * gridDim.x + blockIdx.x] =
+          red[pk] + red[n_pk + pk] + red[2 * n_pk + pk] + red[3 * n_pk + pk];
 }
 
 }  // namespace tdwp

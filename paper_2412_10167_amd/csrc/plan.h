@@ -156,7 +156,9 @@ struct tdwp_plan_s {
   double* d_rg = nullptr;         // grids on the device (r, R, cos gamma)
   double* d_Rg = nullptr;
   double* d_xg = nullptr;
-  size_t lds_radR_mlp = 0;
+  int mlp_grid = 0;               // resident workgroups of the learned-potential pass
+  size_t* d_wg_off_mlp = nullptr; // its norm-partial layout (per packet: offset, count)
+  int* d_n_wg_mlp = nullptr;
   // device step counters ([0] ring row, [1] norm-partial row) and captured steps
   int* d_counters = nullptr;
   int norm_row = 0;

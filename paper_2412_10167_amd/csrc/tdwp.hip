@@ -23,6 +23,7 @@ namespace {
 
 constexpr size_t kLdsBudget = 64 * 1024;       // general kernels
 size_t kLdsMax = 64 * 1024;                    // queried per device in tdwp_plan
+int kNumCU = 256;                              // compute units, queried per device
 
 // With TDWP_DEBUG set in the environment, HIP errors are reported on stderr.
 int hip_fail(hipError_t e, const char* what, int line) {
@@ -354,7 +355,7 @@ int upload_tables(Plan* P) {
 template <int PR>
 void set_lds_limits() {
   if (kLdsMax <= 64 * 1024) return;
-  const void* fns[20] = {(const void*)k_radr<PR>, (const void*)k_ang<PR, 1, 1>,
+  const void* fns[24] = {(const void*)k_radr<PR>, (const void*)k_ang<PR, 1, 1>,
                          (const void*)k_ang<PR, 2, 1>, (const void*)k_ang<PR, 4, 1>,
                          (const void*)k_ang<PR, 1, kMaxOmega>, (const void*)k_ang<PR, 2, kMaxOmega>,
                          (const void*)k_ang<PR, 4, kMaxOmega>, (const void*)k_radR_epi<PR, 1>,
@@ -363,7 +364,9 @@ void set_lds_limits() {
                          (const void*)k_angr<PR, 2, 1>, (const void*)k_angr<PR, 4, 1>,
                          (const void*)k_angr<PR, 1, 8>, (const void*)k_angr<PR, 2, 8>,
                          (const void*)k_angr<PR, 4, 8>, (const void*)k_angr<PR, 1, 16>,
-                         (const void*)k_angr<PR, 2, 16>, (const void*)k_angr<PR, 4, 16>};
+                         (const void*)k_angr<PR, 2, 16>, (const void*)k_angr<PR, 4, 16>,
+                         (const void*)k_mlp_epi<PR, 1>, (const void*)k_mlp_epi<PR, 2>,
+                         (const void*)k_mlp_epi<PR, 3>, (const void*)k_mlp_epi<PR, 4>};
   for (const void* f : fns) {
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsMax);
     if (e != hipSuccess) {
@@ -381,6 +384,10 @@ void query_lds_limit() {
   (void)hipGetLastError();
   const size_t lim = (size_t)std::max(a, b);
   if (lim >= 64 * 1024) kLdsMax = lim;
+  int cu = 0;
+  if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cu > 0)
+    kNumCU = cu;
+  (void)hipGetLastError();
 }
 
 int layout_and_allocate(Plan* P) {
@@ -443,6 +450,9 @@ int layout_and_allocate(Plan* P) {
   P->acc_total = aoff;
   P->snap_total = snoff;
   P->n_wg_total = wgoff;
+  // the learned-potential pass writes one norm partial per (resident workgroup, packet)
+  P->mlp_grid = kNumCU;
+  P->n_wg_total = std::max(P->n_wg_total, (size_t)P->packets.size() * (size_t)P->mlp_grid);
   // device buffers
   TRY(dev_alloc(P, (void**)&P->d_u[0], P->n_total * sizeof(double)));
   TRY(dev_alloc(P, (void**)&P->d_u[1], P->n_total * sizeof(double)));
@@ -509,6 +519,12 @@ int layout_and_allocate(Plan* P) {
   }
   TRY(alloc_copy(P, &P->d_wg_off, wg_off));
   TRY(alloc_copy(P, &P->d_n_wg, n_wg));
+  for (size_t ip = 0; ip < P->packets.size(); ++ip) {
+    wg_off[ip] = ip * (size_t)P->mlp_grid;
+    n_wg[ip] = P->mlp_grid;
+  }
+  TRY(alloc_copy(P, &P->d_wg_off_mlp, wg_off));
+  TRY(alloc_copy(P, &P->d_n_wg_mlp, n_wg));
   // batched-launch index maps
   std::vector<long> line_start(1, 0);
   std::vector<unsigned long> slice_off;
@@ -900,13 +916,28 @@ int enqueue_step(Plan* P, int cur, int first, int rec, Timing* T) {
   TRY(timed_end(P, T, 4));
   TRY(timed_begin(P, T));
   if (P->pot_mode == TDWP_POT_MLP) {
+    // y = T_R u + h in h's place, then the network and the rest of the step per point
+    auto split = [&](auto kern) {
+      hipLaunchKernelGGL(kern, dim3(radial_blocks(P, P->blocks_radR)), dim3(256), P->lds_radR,
+                         P->stream, uk, uo, h, pkd, P->d_blk_radR, np, (const E*)P->d_TRsF,
+                         (const E*)P->d_TRdF, P->nRhk, P->nRhk * P->nRhk, P->d_V, P->d_D, ng, nR,
+                         nr, P->E0, 1.0 / P->dE, first, P->d_normpart, P->n_wg_total,
+                         (const int*)P->d_counters, kNormChunk);
+    };
     const double mbc = P->cfg.mass_B + P->cfg.mass_C;
-    hipLaunchKernelGGL(k_radR_epi_mlp<PR>, dim3(P->blocks_radR), dim3(256), P->lds_radR_mlp,
-                       P->stream, uk, uo, h, pkd, P->d_blk_radR, np, (const E*)P->d_TRsF,
-                       (const E*)P->d_TRdF, P->nRhk, P->nRhk * P->nRhk, mlp_net(P), P->d_rg,
-                       P->d_Rg, P->d_xg, P->cfg.mass_C / mbc, P->cfg.mass_B / mbc, P->d_D, ne, ng,
-                       nR, nr, P->E0, 1.0 / P->dE, first, P->d_normpart, P->n_wg_total,
-                       (const int*)P->d_counters, kNormChunk);
+    auto epi = [&](auto kern) {
+      hipLaunchKernelGGL(kern, dim3(P->mlp_grid), dim3(256), mlp_epi_lds(np), P->stream,
+                         mlp_net(P), P->d_rg, P->d_Rg, P->d_xg, P->cfg.mass_C / mbc,
+                         P->cfg.mass_B / mbc, ng, nR, nr, pkd, np, uk, uo, (const HT*)h, P->d_D,
+                         P->E0, 1.0 / P->dE, first, P->d_normpart, P->n_wg_total,
+                         (const int*)P->d_counters, kNormChunk);
+    };
+    switch (ne) {
+      case 1: split(k_radR_epi<PR, 1, true>); epi(k_mlp_epi<PR, 1>); break;
+      case 2: split(k_radR_epi<PR, 2, true>); epi(k_mlp_epi<PR, 2>); break;
+      case 3: split(k_radR_epi<PR, 3, true>); epi(k_mlp_epi<PR, 3>); break;
+      default: split(k_radR_epi<PR, 4, true>); epi(k_mlp_epi<PR, 4>); break;
+    }
   } else {
     auto launch = [&](auto kern) {
       hipLaunchKernelGGL(kern, dim3(radial_blocks(P, P->blocks_radR)), dim3(256), P->lds_radR,
@@ -1106,9 +1137,11 @@ int run_steps(Plan* P, long n_steps, double* norms_out, Timing* T) {
       }
     }
     const int nq = np * chunk;
+    const bool mlp_layout = P->fast && P->pot_mode == TDWP_POT_MLP;
     hipLaunchKernelGGL(k_norm_reduce, dim3((nq + 255) / 256), dim3(256), 0, P->stream,
-                       P->d_norms, P->d_normpart, P->n_wg_total, P->d_wg_off, P->d_n_wg,
-                       np, chunk);
+                       P->d_norms, P->d_normpart, P->n_wg_total,
+                       mlp_layout ? P->d_wg_off_mlp : P->d_wg_off,
+                       mlp_layout ? P->d_n_wg_mlp : P->d_n_wg, np, chunk);
     HIP_TRY(hipGetLastError());
     hn.resize((size_t)np * kNormChunk);
     HIP_TRY(hipMemcpyAsync(hn.data(), P->d_norms, hn.size() * sizeof(double),
@@ -1608,20 +1641,11 @@ int tdwp_set_potential_mlp(tdwp_plan_t p, const double* v, size_t n_values,
   if (n_values != (size_t)p->npair * plane) return TDWP_EINVAL;
   if (o->n_samples < 1 || !o->sample_idx || !o->init_params || !o->order) return TDWP_EINVAL;
   if (o->batch < 1 || o->batch > 4096 || o->batch > o->n_samples || o->epochs < 0) return TDWP_EINVAL;
-  if (!(o->lr > 0)) return TDWP_EINVAL;
-  if (!p->fast || (p->nR / 2 + 15) / 16 > 4 * kMlpMaxMT || p->ne > kMlpMaxElec) return TDWP_EINVAL;
+  if (!(o->lr > 0) || !(o->lr_final >= 0) || o->lr_final > o->lr) return TDWP_EINVAL;
+  if (!p->fast || p->ne > kMaxElec || mlp_epi_lds((int)p->packets.size()) > kLdsMax) return TDWP_EINVAL;
   for (int i = 0; i < o->n_samples; ++i) {
     if (o->sample_idx[i] < 0 || (size_t)o->sample_idx[i] >= plane) return TDWP_EINVAL;
     if (o->order[i] < 0 || o->order[i] >= o->n_samples) return TDWP_EINVAL;
-  }
-  {
-    const int prec = p->cfg.precision;
-    const size_t eb = elem_bytes(prec) * planes_of(prec);
-    const int kpR = round_up(p->nR / 2, (int)ks_of(prec));
-    const size_t sd = ((size_t)2 * 16 * ld_of(prec, kpR) * eb + 15) / 16 * 16;
-    p->lds_radR_mlp = (size_t)p->ne * p->nR * 16 * sizeof(double) + sd +
-                      4 * ((size_t)16 * kMlpLd * 2 + 16 * 16 * 4);
-    if (p->lds_radR_mlp > kLdsMax) return TDWP_EINVAL;
   }
   HIP_TRY(hipMemcpyAsync(p->d_V, v, n_values * sizeof(double), hipMemcpyHostToDevice, p->stream));
   const int npar = mlp_param_count(p->npair);
@@ -1664,8 +1688,13 @@ int tdwp_set_potential_mlp(tdwp_plan_t p, const double* v, size_t n_values,
       ++step;
       const float c1 = (float)(1.0 - std::pow(b1, (double)step));
       const float c2 = (float)(1.0 - std::pow(b2, (double)step));
+      // cosine decay from lr to lr_final over the run (constant when lr_final is 0)
+      const double frac = (o->epochs * (long)nb > 1) ? (double)(step - 1) / (double)(o->epochs * (long)nb - 1) : 0.0;
+      const double lr = o->lr_final > 0
+                            ? o->lr_final + 0.5 * (o->lr - o->lr_final) * (1.0 + std::cos(M_PI * frac))
+                            : o->lr;
       hipLaunchKernelGGL(k_adam, dim3((npar + 255) / 256), dim3(256), 0, p->stream, p->d_mlp_theta, g,
-                         m1, m2, npar, (float)o->lr, (float)b1, (float)b2, 1e-8f, c1, c2);
+                         m1, m2, npar, (float)lr, (float)b1, (float)b2, 1e-8f, c1, c2);
       HIP_TRY(hipGetLastError());
     }
   // final training loss over every sample (forward only; the gradient is discarded)

@@ -63,7 +63,8 @@ class Packet(ctypes.Structure):
 class MlpOptions(ctypes.Structure):
     _fields_ = [("n_samples", ctypes.c_int), ("sample_idx", ctypes.POINTER(ctypes.c_long)),
                 ("init_params", ctypes.POINTER(ctypes.c_float)), ("order", ctypes.POINTER(ctypes.c_int)),
-                ("batch", ctypes.c_int), ("epochs", ctypes.c_int), ("lr", ctypes.c_double)]
+                ("batch", ctypes.c_int), ("epochs", ctypes.c_int), ("lr", ctypes.c_double),
+                ("lr_final", ctypes.c_double)]
 
 
 class Channel(ctypes.Structure):
@@ -265,7 +266,7 @@ class Plan:
         return _check(self.lib.tdwp_mlp_n_params(self.handle), "tdwp_mlp_n_params")
 
     def set_potential_mlp(self, vtable, sample_idx, init_params, order, batch=1024, epochs=10,
-                          lr=1e-3):
+                          lr=1e-3, lr_final=0.0):
         """Trains the surrogate on the device; returns (final loss, rms error, max error)."""
         v = _f64(vtable)
         idx = np.ascontiguousarray(sample_idx, dtype=np.int64)
@@ -276,7 +277,7 @@ class Plan:
                        sample_idx=idx.ctypes.data_as(ctypes.POINTER(ctypes.c_long)),
                        init_params=th.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
                        order=od.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
-                       batch=batch, epochs=epochs, lr=lr)
+                       batch=batch, epochs=epochs, lr=lr, lr_final=lr_final)
         rep = np.zeros(3)
         _check(self.lib.tdwp_set_potential_mlp(self.handle, _ptr(v), v.size, ctypes.byref(o), _ptr(rep)),
                "tdwp_set_potential_mlp")
