@@ -147,6 +147,7 @@ def mlp_bench(args, torch, problem, config):
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
     loss, rms, mx = info["mlp_report"]
+    print(f"trained in {train_s:.1f} s: grid rms {rms * 27211.386:.2f} meV", file=sys.stderr, flush=True)
 
     def rate(plan):
         plan.propagate(args.warmup, norms=False)
@@ -160,6 +161,22 @@ def mlp_bench(args, torch, problem, config):
 
     r_table, r_mlp = rate(plan_t), rate(plan_m)
     kt = plan_m.time_kernels(args.kernel_steps)
+    pe = None
+    if args.mlp_pe_steps > 0:
+        res = {}
+        for key, plan in (("table", plan_t), ("mlp", plan_m)):
+            problem.install_packets(plan, spec)
+            plan.propagate(args.mlp_pe_steps, norms=False)
+            print(f"{key}: {args.mlp_pe_steps} steps propagated", file=sys.stderr, flush=True)
+            parts = []
+            for pk in spec["packets"]:
+                chans = problem.channels(plan, spec, pk["unit"], min(10, spec["n_gamma"] - 1), 2)
+                p_inel, p_reac = plan.state_to_state(pk["unit"], pk["slot"], chans)
+                parts += [p_inel.ravel(), p_reac.ravel()]
+            res[key] = np.concatenate(parts)
+        d = np.abs(res["mlp"] - res["table"])
+        pe = dict(steps=args.mlp_pe_steps, probabilities=int(d.size), max_abs_diff=float(d.max()),
+                  mean_abs_diff=float(d.mean()), max_probability=float(np.max(np.abs(res["table"]))))
     plan_t.close()
     plan_m.close()
     eh_mev = 27211.386245988
@@ -182,6 +199,7 @@ def mlp_bench(args, torch, problem, config):
                                 "seconds": round(train_s, 2), "final_loss": loss,
                                 "grid_rms_meV": round(rms * eh_mev, 3),
                                 "grid_max_meV": round(mx * eh_mev, 3)},
+                   "pe_network_vs_table": pe,
                    "kernels_avg_us": {k: round(v, 2) for k, v in kt.items()}},
     }
     print(json.dumps(out))
@@ -245,6 +263,9 @@ def main():
     ap.add_argument("--mlp-batch", type=int, default=1024)
     ap.add_argument("--mlp-lr", type=float, default=2e-3)
     ap.add_argument("--mlp-lr-final", type=float, default=2e-5)
+    ap.add_argument("--mlp-pe-steps", type=int, default=0,
+                    help="also propagate both plans from k = 0 for this many steps and report "
+                         "the largest P(E) difference between the network and the table")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="also run one device copy of this many MiB (counter calibration)")
     args = ap.parse_args()

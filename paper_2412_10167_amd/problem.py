@@ -32,14 +32,21 @@ def build(spec, precision="fp64", bounds=None, stream="current", vtable=None, ml
         info["mlp_report"] = plan.set_potential_mlp(vtable, **mlp)
     if autotune:
         info["autotune"] = plan.autotune(autotune)
+    install_packets(plan, spec, info)
+    return plan, info
+
+
+def install_packets(plan, spec, info=None):
+    """(Re)installs every initial packet of the workload: propagation restarts at k = 0."""
+    r = plan.grid()[0]
     for pk in spec["packets"]:
         va = asymptotic_potential(spec, r, pk["elec0"])
         e, chi = plan.diatomic_states(va, pk["j0"], pk["v0"] + 1)
         E, c = e[pk["v0"]], chi[pk["v0"]]
         plan.set_initial_packet(pk, c, E)
-        info["e0"][(pk["unit"], pk["slot"])] = E
-        info["chi0"][(pk["unit"], pk["slot"])] = c
-    return plan, info
+        if info is not None:
+            info["e0"][(pk["unit"], pk["slot"])] = E
+            info["chi0"][(pk["unit"], pk["slot"])] = c
 
 
 def channels(plan, spec, unit, jmax, vmax, elecs=None, omegas=None):
