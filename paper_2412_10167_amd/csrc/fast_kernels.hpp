@@ -523,7 +523,7 @@ __global__ __launch_bounds__(256) void k_ang(const double* __restrict__ u_all,
 // zero elsewhere (rows j < Omega or j >= ng are zero too).  A wave computes one
 // (j tile, t tile) for every helicity, so a lane holds C[.][j][t] for all Omega of
 // its rows j and the mixing U diag(min(B_r j(j+1) + B_R ell_a, rot_cut)) U^T runs in
-// registers (U and ell read through the cache).  The mixed coefficients go to
+// registers (U and ell staged in LDS).  The mixed coefficients go to
 // C[o][class][t][jj] in X's place for the back transform of ang_back.  TPW tiles
 // per wave times MAXOM helicities bound the accumulators held across the barrier.
 template <int P, int NT, int MAXOM>
@@ -562,6 +562,25 @@ __global__ __launch_bounds__(256) void k_angr(const double* __restrict__ u_all,
   const int le = local / (nrt * nR);
   const size_t plane = (size_t)nR * nr;
   E* X = reinterpret_cast<E*>(lds);
+  // the unit's helicity blocks U and eigenvalues ell, in the mixing precision,
+  // staged after the tiles
+  using MX = typename HType<P>::T;
+  MX* Ul = reinterpret_cast<MX*>(reinterpret_cast<char*>(lds) +
+                                 ((size_t)F::PLANES * ps * sizeof(E) + 15) / 16 * 16);
+  MX* ell_l = Ul + d.n_U;
+  {
+    const MX* gU;
+    const MX* gl;
+    if constexpr (P == kP64) {
+      gU = d.U;
+      gl = d.ell;
+    } else {
+      gU = d.Uf;
+      gl = d.ellf;
+    }
+    for (int q = threadIdx.x; q < d.n_U; q += 256) Ul[q] = gU[q];
+    for (int q = threadIdx.x; q < d.n_ell; q += 256) ell_l[q] = gl[q];
+  }
   ang_load<P, RT>(X, u, n_om, ne, le, ng, kpa, ld, tile, ps, m, i0, nr, plane);
   __syncthreads();
   const int l = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -602,16 +621,8 @@ __global__ __launch_bounds__(256) void k_angr(const double* __restrict__ u_all,
     }
   }
   __syncthreads();   // X is read by every wave before the coefficients replace it
-  using MX = typename HType<P>::T;
-  const MX* __restrict__ mixU;
-  const MX* __restrict__ mixl;
-  if constexpr (P == kP64) {
-    mixU = d.U;
-    mixl = d.ell;
-  } else {
-    mixU = d.Uf;
-    mixl = d.ellf;
-  }
+  const MX* __restrict__ mixU = Ul;
+  const MX* __restrict__ mixl = ell_l;
   const MX bRm = (MX)BR[m];
   const MX cap = (MX)rot_cut;
   const int om_hi = om_lo + n_om - 1;

@@ -276,9 +276,11 @@ bool ang_config(Plan* P, int nt, int* regs, size_t* lds) {
   const size_t tiles = ((size_t)max_om * 2 * 16 * nt * ld_of(prec, kpa) * eb + 15) / 16 * 16;
   const int mom = max_om <= 1 ? 1 : (max_om <= 8 ? 8 : 16);
   const int tpw = ((P->ng + 15) / 16 * nt + 3) / 4;
-  if (P->ang_pref != 1 && max_om <= kMaxOmega && tpw <= 16 / mom && tiles <= kLdsMax) {
+  // k_angr stages U and ell in the mixing precision (FP64 form: double, else float)
+  const size_t mix_tab = ang_tab / (prec == TDWP_FP64 ? 1 : 2);
+  if (P->ang_pref != 1 && max_om <= kMaxOmega && tpw <= 16 / mom && tiles + mix_tab <= kLdsMax) {
     *regs = mom;
-    *lds = tiles;
+    *lds = tiles + mix_tab;
     return true;
   }
   if (P->ang_pref == 2) return false;
