@@ -699,6 +699,22 @@ __global__ __launch_bounds__(256) void k_angr(const double* __restrict__ u_all,
 // contraction) so that one memory latency is paid per batch, not per element.
 constexpr int kLoadBatch = 8;
 
+// Called by thread 0 of every workgroup of a step's last pass after its last
+// read of the counters: the workgroup that finishes last advances the ring row
+// by `recorded` and the norm row by one, and re-arms the arrival count
+// counters[2] (every other workgroup has read counters[0..1] by then).
+__device__ __forceinline__ void advance_if_last(int* counters, int recorded) {
+  const unsigned done = atomicAdd(reinterpret_cast<unsigned*>(counters + 2), 1u);
+  if (done == gridDim.x - 1) {
+    counters[0] += recorded;
+    counters[1] += 1;
+    counters[2] = 0;
+  }
+}
+// Row stride (doubles) of the FP64 tile (padding it to 18, 20 or 24 measured no
+// faster while it costs occupancy).
+constexpr int kXLd = 16;
+
 template <int P, int NE, bool SPLIT = false>
 __global__ __launch_bounds__(256) void k_radR_epi(
     const double* __restrict__ uk_all, double* __restrict__ uprev_all,
@@ -706,8 +722,8 @@ __global__ __launch_bounds__(256) void k_radR_epi(
     const int* __restrict__ blk_start, int n_pk, const typename Fmt<P>::E* __restrict__ Ts,
     const typename Fmt<P>::E* __restrict__ Td, int ldt, int pst, const double* __restrict__ V,
     const double* __restrict__ D, int ng, int nR, int nr, double E0, double inv_dE,
-    int first, double* __restrict__ normpart, size_t n_wg_total, const int* __restrict__ counters,
-    int norm_rows) {
+    int first, double* __restrict__ normpart, size_t n_wg_total, int* __restrict__ counters,
+    int norm_rows, int recorded) {
   using M = Mma<P>;
   using F = Fmt<P>;
   using E = typename F::E;
@@ -738,8 +754,8 @@ __global__ __launch_bounds__(256) void k_radR_epi(
   const int slab = local / nrt;
   const int o = slab / ng, n = slab % ng;
   const size_t plane = (size_t)nR * nr;
-  double* X = lds;                                             // [le][nR][RT]
-  E* SD = reinterpret_cast<E*>(lds + (size_t)NE * nR * RT);    // S^T [t][k], then D^T
+  double* X = lds;                                             // [le][nR][kXLd]
+  E* SD = reinterpret_cast<E*>(lds + (size_t)NE * nR * kXLd);  // S^T [t][k], then D^T
   {
     const int tt = threadIdx.x & 15, r0 = threadIdx.x >> 4;
     const int ii = i0 + tt;
@@ -748,7 +764,7 @@ __global__ __launch_bounds__(256) void k_radR_epi(
 #pragma unroll
     for (int le = 0; le < NE; ++le) {
       const double* src = uk + ((size_t)(o * NE + le) * ng + n) * plane + iic;
-      double* dst = X + (size_t)le * nR * RT + tt;
+      double* dst = X + (size_t)le * nR * kXLd + tt;
       for (int m0 = r0; m0 < nR; m0 += 16 * kLoadBatch) {
         double vb[kLoadBatch];
 #pragma unroll
@@ -759,7 +775,7 @@ __global__ __launch_bounds__(256) void k_radR_epi(
 #pragma unroll
         for (int b = 0; b < kLoadBatch; ++b) {
           const int mm = m0 + 16 * b;
-          if (mm < nR) dst[mm * RT] = okc ? vb[b] : 0.0;
+          if (mm < nR) dst[mm * kXLd] = okc ? vb[b] : 0.0;
         }
       }
     }
@@ -772,14 +788,14 @@ __global__ __launch_bounds__(256) void k_radR_epi(
 #pragma unroll 1
   for (int le = 0; le < NE; ++le) {
     __syncthreads();
-    const double* Xl = X + (size_t)le * nR * RT;
+    const double* Xl = X + (size_t)le * nR * kXLd;
     {
       const int tt = threadIdx.x & 15;
       for (int k = threadIdx.x >> 4; k < kp; k += 16) {
         double a = 0.0, b = 0.0;
         if (k < nh) {
-          a = Xl[k * RT + tt];
-          b = Xl[(nR - 1 - k) * RT + tt];
+          a = Xl[k * kXLd + tt];
+          b = Xl[(nR - 1 - k) * kXLd + tt];
         }
         F::put(SD, ps, tt * ld + k, a + b);
         F::put(SD, ps, RT * ld + tt * ld + k, a - b);
@@ -849,9 +865,9 @@ __global__ __launch_bounds__(256) void k_radR_epi(
             h[idx] = (HT)sacc;
             continue;
           }
-          const double ukv = Xl[mm * RT + t];
+          const double ukv = Xl[mm * kXLd + t];
 #pragma unroll
-          for (int l2 = 0; l2 < NE; ++l2) sacc += vv[q][l2] * X[((size_t)l2 * nR + mm) * RT + t];
+          for (int l2 = 0; l2 < NE; ++l2) sacc += vv[q][l2] * X[((size_t)l2 * nR + mm) * kXLd + t];
           const double wv = (sacc - E0 * ukv) * inv_dE;
           const double dmp = dv[q];
           const double un = first ? dmp * wv : dmp * (2.0 * wv - dmp * pv[q]);
@@ -867,6 +883,9 @@ __global__ __launch_bounds__(256) void k_radR_epi(
     __syncthreads();
     if (threadIdx.x == 0 && normpart_row) normpart_row[dsc.wg_off + local] = red[0] + red[1] + red[2] + red[3];
   }
+  }
+  if constexpr (!SPLIT) {
+    if (threadIdx.x == 0) advance_if_last(counters, recorded);
   }
 }
 
@@ -960,6 +979,7 @@ __global__ void k_set_counters(int* counters, int ring_row, int norm_row) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     counters[0] = ring_row;
     counters[1] = norm_row;
+    counters[2] = 0;
   }
 }
 }  // namespace tdwp

@@ -343,8 +343,8 @@ __global__ __launch_bounds__(256) void k_mlp_epi(
     const PkDesc* __restrict__ pks, int n_pk, const double* __restrict__ uk_all,
     double* __restrict__ uprev_all, const typename HType<P>::T* __restrict__ y_all,
     const double* __restrict__ D, double E0, double inv_dE, int first,
-    double* __restrict__ normpart, size_t n_wg_total, const int* __restrict__ counters,
-    int norm_rows) {
+    double* __restrict__ normpart, size_t n_wg_total, int* __restrict__ counters,
+    int norm_rows, int recorded) {
   constexpr int NPAIR = NE * (NE + 1) / 2;
   extern __shared__ __align__(16) double lds[];
   const int l = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -458,6 +458,7 @@ __global__ __launch_bounds__(256) void k_mlp_epi(
     if (normpart_row)
       normpart_row[(size_t)pk * gridDim.x + blockIdx.x] =
           red[pk] + red[n_pk + pk] + red[2 * n_pk + pk] + red[3 * n_pk + pk];
+  if (threadIdx.x == 0) advance_if_last(counters, recorded);
 }
 
 }  // namespace tdwp

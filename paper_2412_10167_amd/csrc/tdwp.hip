@@ -321,7 +321,7 @@ void choose_fast_path(Plan* P) {
   }
   if (P->nta == 0) return;
   P->ntr = 1;
-  P->lds_radR = (size_t)P->ne * P->nR * 16 * sizeof(double) + (size_t)2 * 16 * ld_of(prec, kpR) * eb;
+  P->lds_radR = (size_t)P->ne * P->nR * kXLd * sizeof(double) + (size_t)2 * 16 * ld_of(prec, kpR) * eb;
   if (P->lds_radr > kLdsMax || P->lds_ang > kLdsMax || P->lds_radR > kLdsMax) return;
   P->fast = true;
 }
@@ -924,7 +924,7 @@ int enqueue_step(Plan* P, int cur, int first, int rec, Timing* T) {
                          P->stream, uk, uo, h, pkd, P->d_blk_radR, np, (const E*)P->d_TRsF,
                          (const E*)P->d_TRdF, P->nRhk, P->nRhk * P->nRhk, P->d_V, P->d_D, ng, nR,
                          nr, P->E0, 1.0 / P->dE, first, P->d_normpart, P->n_wg_total,
-                         (const int*)P->d_counters, kNormChunk);
+                         P->d_counters, kNormChunk, rec);
     };
     const double mbc = P->cfg.mass_B + P->cfg.mass_C;
     auto epi = [&](auto kern) {
@@ -932,7 +932,7 @@ int enqueue_step(Plan* P, int cur, int first, int rec, Timing* T) {
                          mlp_net(P), P->d_rg, P->d_Rg, P->d_xg, P->cfg.mass_C / mbc,
                          P->cfg.mass_B / mbc, ng, nR, nr, pkd, np, uk, uo, (const HT*)h, P->d_D,
                          P->E0, 1.0 / P->dE, first, P->d_normpart, P->n_wg_total,
-                         (const int*)P->d_counters, kNormChunk);
+                         P->d_counters, kNormChunk, rec);
     };
     switch (ne) {
       case 1: split(k_radR_epi<PR, 1, true>); epi(k_mlp_epi<PR, 1>); break;
@@ -946,8 +946,8 @@ int enqueue_step(Plan* P, int cur, int first, int rec, Timing* T) {
                          P->stream, uk, uo,
                          h, pkd, P->d_blk_radR, np, (const E*)P->d_TRsF, (const E*)P->d_TRdF,
                          P->nRhk, P->nRhk * P->nRhk, P->d_V, P->d_D, ng, nR, nr, P->E0,
-                         1.0 / P->dE, first, P->d_normpart, P->n_wg_total,
-                         (const int*)P->d_counters, kNormChunk);
+                         1.0 / P->dE, first, P->d_normpart, P->n_wg_total, P->d_counters,
+                         kNormChunk, rec);
     };
     switch (ne) {
       case 1: launch(k_radR_epi<PR, 1>); break;
@@ -956,8 +956,7 @@ int enqueue_step(Plan* P, int cur, int first, int rec, Timing* T) {
       default: launch(k_radR_epi<PR, 4>); break;
     }
   }
-  hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, P->stream, P->d_counters, rec, 1);
-  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipGetLastError());   // the pass's last workgroup has advanced the counters
   TRY(timed_end(P, T, 1));
   return TDWP_OK;
 }

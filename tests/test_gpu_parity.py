@@ -232,6 +232,69 @@ def test_full_size_config2_first_steps():
     plan.close()
 
 
+@pytest.mark.parametrize("K", [0, 1])
+def test_zero_and_one_step_probabilities(K):
+    banner(f"{K} steps: packet, norms and P(E) from the k <= {K} terms (J=5 Omega 1..3, 2 states)")
+    spec = _coriolis_spec(5, 1, 3, 2)
+    problem = _problem()
+    plan, _ = problem.build(spec)
+    norms = plan.propagate(K)
+    assert norms.shape == (1, K)
+    op, ref = oracle_packets(spec, K, keep=(K,))
+    run, e0, _ = ref[(0, 0)]
+    assert rel_err(plan.get_packet(0, 0, 0), run["vectors"][K]) < PKT_TOL
+    chans = problem.channels(plan, spec, 0, 3, 1)
+    p_inel, p_reac = plan.state_to_state(0, 0, chans)
+    res = O.analyse(op, 0, spec["packets"][0], run, e0, oracle_channels(op, spec, chans))
+    assert np.max(np.abs(p_reac - res["p_reac"])) < PE_TOL
+    assert np.max(np.abs(p_inel - res["p_inel"])) < PE_TOL
+    # no channels: the reactive probabilities alone
+    p_none, p_reac2 = plan.state_to_state(0, 0, [])
+    assert p_none.shape == (0, spec["n_energy"]) and np.array_equal(p_reac2, p_reac)
+    plan.close()
+
+
+def _full_size_sampled(wl, K, keep):
+    """Full-size plan of workload wl on the GPU; the packets in `keep` ((unit, slot)
+    pairs) against an oracle run of just their units with the plan's bounds."""
+    spec = config(wl)
+    problem = _problem()
+    plan, _ = problem.build(spec)
+    plan.propagate(K)
+    lo, hi = plan.spectral_bounds()
+    units = sorted({u for u, _ in keep})
+    sub = dict(spec)
+    sub["units"] = [spec["units"][u] for u in units]
+    sub["packets"] = [dict(p, unit=units.index(p["unit"])) for p in spec["packets"]
+                      if (p["unit"], p["slot"]) in keep]
+    op = O.Operator(sub, bounds=(lo, hi))
+    for pk in sub["packets"]:
+        va = asymptotic_potential(sub, op.r, pk["elec0"])
+        e, chi = O.diatomic_states(op, va, pk["j0"], pk["v0"] + 1)
+        u0 = O.initial_packet(op, pk["unit"], pk, chi[pk["v0"]])
+        run = O.propagate(op, pk["unit"], u0, K, keep_vectors=(K,))
+        got = plan.get_packet(units[pk["unit"]], pk["slot"], 0)
+        err = rel_err(got, run["vectors"][K])
+        print(f"[result] unit {units[pk['unit']]} slot {pk['slot']}: packet rel {err:.2e}", flush=True)
+        assert err < PKT_TOL
+    plan.close()
+
+
+def test_full_size_config3_first_steps():
+    banner("config 3 full size 192x160x64, J=20 Omega 0..8, 2 states: 2 steps")
+    _full_size_sampled(3, 2, {(0, 0)})
+
+
+def test_full_size_config4_sampled_packets():
+    banner("config 4 full size (21 units x 3 packets, 128x128x48): 2 steps, J=0 and J=40 packets")
+    _full_size_sampled(4, 2, {(0, 0), (20, 2)})
+
+
+def test_full_size_config5_first_step():
+    banner("config 5 full size 256x256x96, J=4 Omega 0..4, 3 states: 1 step")
+    _full_size_sampled(5, 1, {(0, 0)})
+
+
 def test_errors_are_reported():
     banner("error paths: ESTATE, ERANGE, EINVAL")
     from paper_2412_10167_amd.tdwp import Plan, TdwpError
