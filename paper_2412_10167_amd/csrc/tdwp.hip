@@ -1215,8 +1215,17 @@ int tdwp_plan(const tdwp_config* cfg, tdwp_plan_t* out) {
     return st;
   }
   if (P->fast) {
-    const int nt = cached_tile(P);
-    if (nt == 1 || nt == 2 || nt == 4) (void)set_ang_tiles(P, nt);
+    // cached choice: 10 * kernel + tile (kernel 1: LDS mixing, 2: register mixing)
+    const int c = cached_tile(P);
+    const int nt = c % 10, kern = c / 10;
+    if ((nt == 1 || nt == 2 || nt == 4) && kern <= 2) {
+      const int keep = P->ang_pref;
+      P->ang_pref = kern;
+      if (set_ang_tiles(P, nt) != TDWP_OK) {
+        P->ang_pref = keep;
+        (void)set_ang_tiles(P, P->nta);
+      }
+    }
   }
   if (P->bounds_given) {
     P->e_min = cfg->e_min;
@@ -1539,44 +1548,57 @@ int tdwp_autotune(tdwp_plan_t p, int steps, char* report, size_t report_len) {
   HIP_TRY(hipMemsetAsync(p->d_u[0], 0, p->n_total * sizeof(double), p->stream));
   HIP_TRY(hipMemsetAsync(p->d_u[1], 0, p->n_total * sizeof(double), p->stream));
   std::string rep;
-  int best = p->nta;
+  const int keep_pref = p->ang_pref, keep_nt = p->nta;
+  int best_k = -1, best_nt = keep_nt;
   double best_us = 1e300;
-  for (int nt : {4, 2, 1}) {
-    if (set_ang_tiles(p, nt) != TDWP_OK) continue;
-    T.ms[0] = 0.0;
-    T.calls[0] = 0;
-    reset_propagation(p);
-    int st = sync_counters(p);
-    for (int s2 = 0; s2 < steps + 1 && st == TDWP_OK; ++s2) {   // the first step warms up
-      if (s2 == 1) {
-        T.ms[0] = 0.0;
-        T.calls[0] = 0;
+  // angular kernel (2: helicity mixing in registers, 1: through LDS) x tile width
+  for (int kern : {2, 1})
+    for (int nt : {4, 2, 1}) {
+      p->ang_pref = kern;
+      if (set_ang_tiles(p, nt) != TDWP_OK) continue;
+      T.ms[0] = 0.0;
+      T.calls[0] = 0;
+      reset_propagation(p);
+      int st = sync_counters(p);
+      for (int s2 = 0; s2 < steps + 1 && st == TDWP_OK; ++s2) {   // the first step warms up
+        if (s2 == 1) {
+          T.ms[0] = 0.0;
+          T.calls[0] = 0;
+        }
+        st = one_step(p, 0, &T);
       }
-      st = one_step(p, 0, &T);
+      reset_propagation(p);
+      if (st != TDWP_OK) {
+        (void)hipEventDestroy(T.ev[0]);
+        (void)hipEventDestroy(T.ev[1]);
+        p->ang_pref = keep_pref;
+        (void)set_ang_tiles(p, keep_nt);
+        return st;
+      }
+      const double us = 1000.0 * T.ms[0] / std::max<long>(T.calls[0], 1);
+      char buf[64];
+      std::snprintf(buf, sizeof buf, "%sang_k%d_nt%d:%.1fus", rep.empty() ? "" : ";", kern, nt, us);
+      rep += buf;
+      if (us < best_us) {
+        best_us = us;
+        best_k = kern;
+        best_nt = nt;
+      }
     }
-    reset_propagation(p);
-    if (st != TDWP_OK) {
-      (void)hipEventDestroy(T.ev[0]);
-      (void)hipEventDestroy(T.ev[1]);
-      return st;
-    }
-    const double us = 1000.0 * T.ms[0] / std::max<long>(T.calls[0], 1);
-    char buf[64];
-    std::snprintf(buf, sizeof buf, "%sang_nt=%d:%.1fus", rep.empty() ? "" : ";", nt, us);
-    rep += buf;
-    if (us < best_us) {
-      best_us = us;
-      best = nt;
-    }
-  }
   (void)hipEventDestroy(T.ev[0]);
   (void)hipEventDestroy(T.ev[1]);
-  TRY(set_ang_tiles(p, best));
-  store_tile(p, best);
+  if (best_k < 0) {   // no variant fits: keep the plan's choice
+    p->ang_pref = keep_pref;
+    TRY(set_ang_tiles(p, keep_nt));
+  } else {
+    p->ang_pref = best_k;
+    TRY(set_ang_tiles(p, best_nt));
+    store_tile(p, 10 * best_k + best_nt);
+  }
   drop_graphs(p);
   reset_propagation(p);
   if (report && report_len) {
-    rep += ";chosen=" + std::to_string(best);
+    rep += ";chosen=k" + std::to_string(p->ang_regs ? 2 : 1) + "_nt" + std::to_string(p->nta);
     std::strncpy(report, rep.c_str(), report_len - 1);
     report[report_len - 1] = 0;
   }
