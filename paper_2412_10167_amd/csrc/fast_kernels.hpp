@@ -34,8 +34,17 @@ struct PkDesc {
   const int* ell_off;
   const int* n_om_j;
   int n_U, n_ell;         // sizes of U and ell (staged into LDS by k_ang)
-  const float* Uf;        // FP32 copies (register mixing of the mixed forms)
-  const float* ellf;
+  // padded blocks of the register mixing ([j][b][a] with a < the kernel's MAXOM,
+  // b < n_om; eigenvalues [j][MAXOM]) in FP64 and FP32, and their sizes
+  // the tridiagonal blocks ([j][2 MAXOM + 2]: diagonal, coupling of helicities o and
+  // o + 1, smallest and largest eigenvalue)
+  const double* mixU;
+  const double* mixell;
+  const double* mixL;
+  const float* mixUf;
+  const float* mixellf;
+  const float* mixLf;
+  int n_mixL;
 };
 
 // Index p with start[p] <= b < start[p + 1] (start has n + 1 entries).
@@ -562,24 +571,25 @@ __global__ __launch_bounds__(256) void k_angr(const double* __restrict__ u_all,
   const int le = local / (nrt * nR);
   const size_t plane = (size_t)nR * nr;
   E* X = reinterpret_cast<E*>(lds);
-  // the unit's helicity blocks U and eigenvalues ell, in the mixing precision,
-  // staged after the tiles
+  // the unit's tridiagonal l^2 blocks ([j][2 MAXOM + 2]) in the mixing precision,
+  // staged after the tiles; the padded eigenvectors stay in global memory
   using MX = typename HType<P>::T;
-  MX* Ul = reinterpret_cast<MX*>(reinterpret_cast<char*>(lds) +
+  MX* Ll = reinterpret_cast<MX*>(reinterpret_cast<char*>(lds) +
                                  ((size_t)F::PLANES * ps * sizeof(E) + 15) / 16 * 16);
-  MX* ell_l = Ul + d.n_U;
+  const MX* gU;
+  const MX* gl;
   {
-    const MX* gU;
-    const MX* gl;
+    const MX* gL;
     if constexpr (P == kP64) {
-      gU = d.U;
-      gl = d.ell;
+      gL = d.mixL;
+      gU = d.mixU;
+      gl = d.mixell;
     } else {
-      gU = d.Uf;
-      gl = d.ellf;
+      gL = d.mixLf;
+      gU = d.mixUf;
+      gl = d.mixellf;
     }
-    for (int q = threadIdx.x; q < d.n_U; q += 256) Ul[q] = gU[q];
-    for (int q = threadIdx.x; q < d.n_ell; q += 256) ell_l[q] = gl[q];
+    for (int q = threadIdx.x; q < d.n_mixL; q += 256) Ll[q] = gL[q];
   }
   ang_load<P, RT>(X, u, n_om, ne, le, ng, kpa, ld, tile, ps, m, i0, nr, plane);
   __syncthreads();
@@ -621,8 +631,6 @@ __global__ __launch_bounds__(256) void k_angr(const double* __restrict__ u_all,
     }
   }
   __syncthreads();   // X is read by every wave before the coefficients replace it
-  const MX* __restrict__ mixU = Ul;
-  const MX* __restrict__ mixl = ell_l;
   const MX bRm = (MX)BR[m];
   const MX cap = (MX)rot_cut;
   const int om_hi = om_lo + n_om - 1;
@@ -645,31 +653,52 @@ __global__ __launch_bounds__(256) void k_angr(const double* __restrict__ u_all,
       for (int o = 0; o < MAXOM; ++o)
         cv[o] = (o < nj) ? (MX)((double)acc[tp][o][v] * M::kUnscale) : (MX)0;
       const MX rot = (MX)(br * (double)j * (double)(j + 1));
-      const MX* __restrict__ Uj = mixU + d.ang_off[j];
-      const MX* __restrict__ lj = mixl + d.ell_off[j];
-      if (MAXOM == 1 || nj == 1) {
-        MX e = rot + bRm * lj[0];
+      const MX* __restrict__ Lj = Ll + j * (2 * MAXOM + 2);
+      // The factor is min(rot + B_R l, cap) on the eigenvalues l of the l^2 block.
+      // Below the cap for all of them it is rot + B_R L with L the tridiagonal block
+      // itself; at the cap for all of them it is the cap.  Otherwise (a band of
+      // (j, r) only) the eigenvectors are applied, from global memory.
+      const MX elo = rot + bRm * Lj[2 * MAXOM], ehi = rot + bRm * Lj[2 * MAXOM + 1];
+      if (MAXOM == 1) {
+        MX e = elo;
         if (rot_cut > 0.0) e = e < cap ? e : cap;
         cv[0] *= e;
+      } else if (rot_cut <= 0.0 || ehi <= cap) {
+        MX outv[MAXOM];
+#pragma unroll
+        for (int a = 0; a < MAXOM; ++a) {
+          MX s = Lj[a] * cv[a];
+          if (a > 0) s += Lj[MAXOM + a - 1] * cv[a - 1];
+          if (a + 1 < MAXOM) s += Lj[MAXOM + a] * cv[a + 1];
+          outv[a] = rot * cv[a] + bRm * s;
+        }
+#pragma unroll
+        for (int a = 0; a < MAXOM; ++a) cv[a] = outv[a];
+      } else if (elo >= cap) {
+#pragma unroll
+        for (int a = 0; a < MAXOM; ++a) cv[a] *= cap;
       } else {
-        // one eigenvector column per iteration: project, scale, scatter back
+        // one eigenvector column per iteration: project, scale, scatter back.  The
+        // padded block is the identity outside the j's own nj x nj block and the
+        // coefficients there are zero, so the sums over all MAXOM entries and the
+        // unit's n_om columns (a wave-uniform count) add exact zeros only.
+        const MX* __restrict__ Uj = gU + (size_t)j * n_om * MAXOM;
+        const MX* __restrict__ lj = gl + j * MAXOM;
         MX outv[MAXOM];
 #pragma unroll
         for (int a = 0; a < MAXOM; ++a) outv[a] = (MX)0;
-        for (int b = 0; b < nj; ++b) {
+        for (int b = 0; b < n_om; ++b) {
           MX uc[MAXOM];
 #pragma unroll
-          for (int a = 0; a < MAXOM; ++a) uc[a] = Uj[(a < nj ? a : nj - 1) * nj + b];
+          for (int a = 0; a < MAXOM; ++a) uc[a] = Uj[b * MAXOM + a];
           MX sacc = (MX)0;
 #pragma unroll
-          for (int a = 0; a < MAXOM; ++a)
-            if (a < nj) sacc += uc[a] * cv[a];
+          for (int a = 0; a < MAXOM; ++a) sacc += uc[a] * cv[a];
           MX e = rot + bRm * lj[b];
           if (rot_cut > 0.0) e = e < cap ? e : cap;
           const MX tb = sacc * e;
 #pragma unroll
-          for (int a = 0; a < MAXOM; ++a)
-            if (a < nj) outv[a] += uc[a] * tb;
+          for (int a = 0; a < MAXOM; ++a) outv[a] += uc[a] * tb;
         }
 #pragma unroll
         for (int a = 0; a < MAXOM; ++a) cv[a] = outv[a];

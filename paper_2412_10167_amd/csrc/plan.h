@@ -25,8 +25,18 @@ struct UnitInfo {
   std::vector<double> ang_U, ang_ell;
   double* d_U = nullptr;
   double* d_ell = nullptr;
-  float* d_Uf = nullptr;     // FP32 copies for the register mixing of the mixed forms
-  float* d_ellf = nullptr;
+  // The same blocks padded for the register mixing: every j holds n_om columns b
+  // of mix_ld entries a ([j][b][a], identity outside the j's own block) and
+  // mix_ld eigenvalues ([j][b], zero outside), in FP64 and FP32.
+  // and, per j, the tridiagonal l^2 block itself ([j][2 mix_ld + 2]: diagonal,
+  // coupling of Omega and Omega + 1, smallest and largest eigenvalue), in FP64 and FP32.
+  std::vector<double> mix_U, mix_ell, mix_L;
+  double* d_mixU = nullptr;
+  double* d_mixell = nullptr;
+  double* d_mixL = nullptr;
+  float* d_mixUf = nullptr;
+  float* d_mixellf = nullptr;
+  float* d_mixLf = nullptr;
   int* d_ang_off = nullptr;
   int* d_ell_off = nullptr;
   int* d_n_om_j = nullptr;

@@ -25,6 +25,10 @@ constexpr size_t kLdsBudget = 64 * 1024;       // general kernels
 size_t kLdsMax = 64 * 1024;                    // queried per device in tdwp_plan
 int kNumCU = 256;                              // compute units, queried per device
 
+// helicity width of the register-mixing angular kernel (its MAXOM) for units of
+// up to n_om helicity blocks
+int mix_width(int n_om) { return n_om <= 1 ? 1 : (n_om <= 8 ? 8 : 16); }
+
 // With TDWP_DEBUG set in the environment, HIP errors are reported on stderr.
 int hip_fail(hipError_t e, const char* what, int line) {
   if (std::getenv("TDWP_DEBUG"))
@@ -206,6 +210,40 @@ int build_tables(Plan* P) {
     }
     P->units.push_back(U);
   }
+  // padded blocks of the register mixing (k_angr): width = the kernel's MAXOM
+  {
+    int max_n = 0;
+    for (auto& U : P->units) max_n = std::max(max_n, U.n_om);
+    const int S = mix_width(max_n);
+    for (auto& U : P->units) {
+      U.mix_U.assign((size_t)P->ng * U.n_om * S, 0.0);
+      U.mix_ell.assign((size_t)P->ng * S, 0.0);
+      U.mix_L.assign((size_t)P->ng * (2 * S + 2), 0.0);
+      for (int j = 0; j < P->ng; ++j) {
+        const int nj = U.n_om_j[j];
+        if (nj > 0) {
+          std::vector<double> L;
+          ell2_block(U.J, j, U.om_lo, U.om_lo + nj - 1, L);
+          double* row = U.mix_L.data() + (size_t)j * (2 * S + 2);
+          double lmin = 0.0, lmax = 0.0;
+          for (int a = 0; a < nj; ++a) {
+            row[a] = L[(size_t)a * nj + a];
+            if (a + 1 < nj) row[S + a] = L[(size_t)a * nj + a + 1];
+            const double e = U.ang_ell[U.ell_off[j] + a];
+            lmin = a ? std::min(lmin, e) : e;
+            lmax = a ? std::max(lmax, e) : e;
+          }
+          row[2 * S] = lmin;
+          row[2 * S + 1] = lmax;
+        }
+        for (int b = 0; b < U.n_om; ++b)
+          for (int a = 0; a < S; ++a)
+            U.mix_U[((size_t)j * U.n_om + b) * S + a] =
+                (a < nj && b < nj) ? U.ang_U[U.ang_off[j] + a * nj + b] : (a == b ? 1.0 : 0.0);
+        for (int b = 0; b < nj; ++b) U.mix_ell[(size_t)j * S + b] = U.ang_ell[U.ell_off[j] + b];
+      }
+    }
+  }
   // half-size operators of the matrix-core path (even sizes only)
   if (P->nr % 2 == 0 && P->nR % 2 == 0 && P->ng % 2 == 0) {
     auto split = [](const std::vector<double>& T, int N, int nhk, std::vector<double>& Ts,
@@ -268,16 +306,17 @@ bool ang_config(Plan* P, int nt, int* regs, size_t* lds) {
   const size_t eb = elem_bytes(prec) * planes_of(prec);
   const int kpa = round_up(P->ng / 2, (int)ks_of(prec));
   int max_om = 0;
-  size_t ang_tab = 0;
+  size_t ang_tab = 0, mix_n = 0;
   for (auto& U : P->units) {
     max_om = std::max(max_om, U.n_om);
     ang_tab = std::max(ang_tab, (U.ang_U.size() + U.ang_ell.size()) * sizeof(double));
+    mix_n = std::max(mix_n, U.mix_L.size());
   }
   const size_t tiles = ((size_t)max_om * 2 * 16 * nt * ld_of(prec, kpa) * eb + 15) / 16 * 16;
-  const int mom = max_om <= 1 ? 1 : (max_om <= 8 ? 8 : 16);
+  const int mom = mix_width(max_om);
   const int tpw = ((P->ng + 15) / 16 * nt + 3) / 4;
-  // k_angr stages U and ell in the mixing precision (FP64 form: double, else float)
-  const size_t mix_tab = ang_tab / (prec == TDWP_FP64 ? 1 : 2);
+  // k_angr stages the tridiagonal blocks in the mixing precision (FP64 form: double, else float)
+  const size_t mix_tab = mix_n * (prec == TDWP_FP64 ? sizeof(double) : sizeof(float));
   if (P->ang_pref != 1 && max_om <= kMaxOmega && tpw <= 16 / mom && tiles + mix_tab <= kLdsMax) {
     *regs = mom;
     *lds = tiles + mix_tab;
@@ -370,7 +409,14 @@ void set_lds_limits() {
                          (const void*)k_mlp_epi<PR, 1>, (const void*)k_mlp_epi<PR, 2>,
                          (const void*)k_mlp_epi<PR, 3>, (const void*)k_mlp_epi<PR, 4>};
   for (const void* f : fns) {
-    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsMax);
+    // the dynamic share is what the device allows beyond the kernel's static LDS
+    hipFuncAttributes fa{};
+    size_t stat = 0;
+    if (hipFuncGetAttributes(&fa, f) == hipSuccess) stat = fa.sharedSizeBytes;
+    (void)hipGetLastError();
+    if (stat >= kLdsMax) continue;
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)(kLdsMax - stat));
     if (e != hipSuccess) {
       hip_fail(e, "hipFuncSetAttribute", __LINE__);
       (void)hipGetLastError();
@@ -476,8 +522,12 @@ int layout_and_allocate(Plan* P) {
     std::vector<double> lv = U.ang_ell.empty() ? std::vector<double>{0.0} : U.ang_ell;
     TRY(alloc_copy(P, &U.d_U, Uv));
     TRY(alloc_copy(P, &U.d_ell, lv));
-    TRY(alloc_copy(P, &U.d_Uf, std::vector<float>(Uv.begin(), Uv.end())));
-    TRY(alloc_copy(P, &U.d_ellf, std::vector<float>(lv.begin(), lv.end())));
+    TRY(alloc_copy(P, &U.d_mixU, U.mix_U));
+    TRY(alloc_copy(P, &U.d_mixell, U.mix_ell));
+    TRY(alloc_copy(P, &U.d_mixL, U.mix_L));
+    TRY(alloc_copy(P, &U.d_mixUf, std::vector<float>(U.mix_U.begin(), U.mix_U.end())));
+    TRY(alloc_copy(P, &U.d_mixellf, std::vector<float>(U.mix_ell.begin(), U.mix_ell.end())));
+    TRY(alloc_copy(P, &U.d_mixLf, std::vector<float>(U.mix_L.begin(), U.mix_L.end())));
     TRY(alloc_copy(P, &U.d_ang_off, U.ang_off));
     TRY(alloc_copy(P, &U.d_ell_off, U.ell_off));
     TRY(alloc_copy(P, &U.d_n_om_j, U.n_om_j));
@@ -570,7 +620,8 @@ int layout_and_allocate(Plan* P) {
       const UnitInfo& U = P->units[pk.unit];
       pd.push_back(PkDesc{pk.off, pk.wg_off, U.n_om, U.om_lo, U.d_U, U.d_ell, U.d_ang_off,
                           U.d_ell_off, U.d_n_om_j, (int)U.ang_U.size(), (int)U.ang_ell.size(),
-                          U.d_Uf, U.d_ellf});
+                          U.d_mixU, U.d_mixell, U.d_mixL, U.d_mixUf, U.d_mixellf, U.d_mixLf,
+                          (int)U.mix_L.size()});
       ba.push_back(ba.back() + nrt_a * nR * ne);
       br.push_back(br.back() + nrt_r * U.n_om * ng);
     }

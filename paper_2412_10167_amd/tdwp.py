@@ -88,6 +88,14 @@ def load_library():
     if not os.path.exists(path):
         raise RuntimeError(f"tdwp HIP library not found at {path}; build it with "
                            "`python -m paper_2412_10167_amd.build_lib` or __graft_entry__.build()")
+    # torch ships its own copy of the HIP runtime and loads it by path; were the
+    # library loaded first, the process would hold two runtimes and torch's streams
+    # and device memory would be foreign to the library's.  Importing torch first
+    # makes the library bind to that same runtime (both carry one soname).
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(path)
     dp = ctypes.POINTER(ctypes.c_double)
     P = ctypes.c_void_p
