@@ -535,7 +535,7 @@ __global__ __launch_bounds__(256) void k_ang(const double* __restrict__ u_all,
 // registers (U and ell staged in LDS).  The mixed coefficients go to
 // C[o][class][t][jj] in X's place for the back transform of ang_back.  TPW tiles
 // per wave times MAXOM helicities bound the accumulators held across the barrier.
-template <int P, int NT, int MAXOM>
+template <int P, int NT, int MAXOM, int TPW>
 __global__ __launch_bounds__(256) void k_angr(const double* __restrict__ u_all,
                                               typename HType<P>::T* __restrict__ h_all,
                                               const PkDesc* __restrict__ pks,
@@ -552,7 +552,7 @@ __global__ __launch_bounds__(256) void k_angr(const double* __restrict__ u_all,
   using E = typename F::E;
   constexpr int CH = Chunk<P>::CH;
   constexpr int RT = 16 * NT;
-  constexpr int TPW = 16 / MAXOM;
+  static_assert(TPW * MAXOM <= 16, "accumulators per wave");
   extern __shared__ __align__(16) double lds[];
   const int pk = find_packet(blk_start, n_pk, blockIdx.x);
   const int local = blockIdx.x - blk_start[pk];

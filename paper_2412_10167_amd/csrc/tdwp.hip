@@ -9,6 +9,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "host_tables.h"
@@ -390,25 +391,48 @@ int upload_tables(Plan* P) {
   return TDWP_OK;
 }
 
+// Calls f with the register-mixing angular kernel for tile width nt, helicity width
+// mom and at least tpw column tiles per wave.
+template <int PR, class F>
+void with_angr(int nt, int mom, int tpw, F&& f) {
+  auto by_nt = [&](auto ntc) {
+    constexpr int NT = decltype(ntc)::value;
+    if (mom == 1) {
+      if (tpw <= 4) f(k_angr<PR, NT, 1, 4>);
+      else if (tpw <= 8) f(k_angr<PR, NT, 1, 8>);
+      else f(k_angr<PR, NT, 1, 16>);
+    } else if (mom == 8) {
+      if (tpw <= 1) f(k_angr<PR, NT, 8, 1>);
+      else f(k_angr<PR, NT, 8, 2>);
+    } else {
+      f(k_angr<PR, NT, 16, 1>);
+    }
+  };
+  if (nt == 4) by_nt(std::integral_constant<int, 4>{});
+  else if (nt == 2) by_nt(std::integral_constant<int, 2>{});
+  else by_nt(std::integral_constant<int, 1>{});
+}
+
 // Raises the dynamic-LDS limit of the matrix-core kernels above the 64 KB
 // default where the device allows it; a refusal only matters if a launch
 // actually needs more, which choose_fast_path has already excluded.
 template <int PR>
 void set_lds_limits() {
   if (kLdsMax <= 64 * 1024) return;
-  const void* fns[24] = {(const void*)k_radr<PR>, (const void*)k_ang<PR, 1, 1>,
+  const void* fns[15] = {(const void*)k_radr<PR>, (const void*)k_ang<PR, 1, 1>,
                          (const void*)k_ang<PR, 2, 1>, (const void*)k_ang<PR, 4, 1>,
                          (const void*)k_ang<PR, 1, kMaxOmega>, (const void*)k_ang<PR, 2, kMaxOmega>,
                          (const void*)k_ang<PR, 4, kMaxOmega>, (const void*)k_radR_epi<PR, 1>,
                          (const void*)k_radR_epi<PR, 2>, (const void*)k_radR_epi<PR, 3>,
-                         (const void*)k_radR_epi<PR, 4>, (const void*)k_angr<PR, 1, 1>,
-                         (const void*)k_angr<PR, 2, 1>, (const void*)k_angr<PR, 4, 1>,
-                         (const void*)k_angr<PR, 1, 8>, (const void*)k_angr<PR, 2, 8>,
-                         (const void*)k_angr<PR, 4, 8>, (const void*)k_angr<PR, 1, 16>,
-                         (const void*)k_angr<PR, 2, 16>, (const void*)k_angr<PR, 4, 16>,
-                         (const void*)k_mlp_epi<PR, 1>, (const void*)k_mlp_epi<PR, 2>,
-                         (const void*)k_mlp_epi<PR, 3>, (const void*)k_mlp_epi<PR, 4>};
-  for (const void* f : fns) {
+                         (const void*)k_radR_epi<PR, 4>, (const void*)k_mlp_epi<PR, 1>,
+                         (const void*)k_mlp_epi<PR, 2>, (const void*)k_mlp_epi<PR, 3>,
+                         (const void*)k_mlp_epi<PR, 4>};
+  std::vector<const void*> all(fns, fns + 15);
+  for (int nt : {1, 2, 4})
+    for (int mom : {1, 8, 16})
+      for (int tpw : {1, 2, 4, 8, 16})
+        with_angr<PR>(nt, mom, tpw, [&](auto kern) { all.push_back((const void*)kern); });
+  for (const void* f : all) {
     // the dynamic share is what the device allows beyond the kernel's static LDS
     hipFuncAttributes fa{};
     size_t stat = 0;
@@ -929,18 +953,10 @@ int enqueue_step(Plan* P, int cur, int first, int rec, Timing* T) {
     };
     int max_om = 0;
     for (auto& U : P->units) max_om = std::max(max_om, U.n_om);
-    if (P->ang_regs == 1) {
-      if (P->nta == 4) launch_r(k_angr<PR, 4, 1>);
-      else if (P->nta == 2) launch_r(k_angr<PR, 2, 1>);
-      else launch_r(k_angr<PR, 1, 1>);
-    } else if (P->ang_regs == 8) {
-      if (P->nta == 4) launch_r(k_angr<PR, 4, 8>);
-      else if (P->nta == 2) launch_r(k_angr<PR, 2, 8>);
-      else launch_r(k_angr<PR, 1, 8>);
-    } else if (P->ang_regs == 16) {
-      if (P->nta == 4) launch_r(k_angr<PR, 4, 16>);
-      else if (P->nta == 2) launch_r(k_angr<PR, 2, 16>);
-      else launch_r(k_angr<PR, 1, 16>);
+    if (P->ang_regs) {
+      // column tiles per wave: (j tiles) x (r tiles) over the four waves
+      const int tpw = ((ng + 15) / 16 * P->nta + 3) / 4;
+      with_angr<PR>(P->nta, P->ang_regs, tpw, launch_r);
     } else if (max_om == 1) {
       if (P->nta == 4) launch(k_ang<PR, 4, 1>);
       else if (P->nta == 2) launch(k_ang<PR, 2, 1>);
