@@ -274,46 +274,67 @@ __global__ __launch_bounds__(256) void k_radr(const double* __restrict__ u,
 
 // Loads the sums / differences of mirrored Gauss-Legendre nodes of every helicity of
 // one (R index m, r tile, elec le) column block: X[o][class][t][k] in compute format.
-// (Helicity, node pair) items of a thread's column are loaded 8 at a time from
-// clamped, in-range addresses.
+// Each thread owns one column t and the node pairs (k, k + 1) for k = 2 (kf + kstep q);
+// the (helicity, q) sequence is the same for every thread, so its bookkeeping is
+// wave-uniform, and the block base is uniform with 32-bit per-lane offsets (a packet
+// holds fewer than 2^29 values).  Addresses are clamped in range; items are loaded
+// four pairs (16 values) at a time.
 template <int P, int RT>
 __device__ __forceinline__ void ang_load(typename Fmt<P>::E* __restrict__ X,
                                          const double* __restrict__ u, int n_om, int ne, int le,
                                          int ng, int kpa, int ld, int tile, int ps, int m,
                                          int i0, int nr, size_t plane) {
   using F = Fmt<P>;
+  using E = typename F::E;
+  constexpr int kstep = 256 / RT;   // threads per column
+  constexpr int B = 4;
   const int ngh = ng >> 1;
-  const int t = threadIdx.x % RT, k_first = threadIdx.x / RT;
-  constexpr int kstep = 256 / RT;
-  constexpr int B = 8;
-  const int i = i0 + t;
-  const bool okc = i < nr;
-  const double* ub = u + (size_t)m * nr + (okc ? i : nr - 1);
-  const int n_items = n_om * kpa;
-  const float inv_kpa = 1.0f / (float)kpa;   // exact quotients: items < 2^13
-  for (int it0 = k_first; it0 < n_items; it0 += kstep * B) {
-    double av[B], bv[B];
+  const int t = threadIdx.x % RT, kf = threadIdx.x / RT;
+  const int nq = ((kpa >> 1) + kstep - 1) / kstep;   // pairs per thread and helicity
+  const int n_items = n_om * nq;
+  const bool okc = i0 + t < nr;
+  const double* __restrict__ ub = u + ((size_t)le * ng * plane + (size_t)m * nr + i0);
+  const unsigned pl = (unsigned)plane;
+  const unsigned tcol = (unsigned)(okc ? t : nr - 1 - i0);
+  const unsigned lastp = (unsigned)(ngh - 1) * pl, topp = (unsigned)(ng - 1) * pl;
+  const unsigned kfp = (unsigned)(2 * kf) * pl, q_step = (unsigned)(2 * kstep) * pl;
+  const unsigned o_step = (unsigned)(ne * ng) * pl;
+  E* __restrict__ Xt = X + t * ld + 2 * kf;
+  int o_next = 0, q_next = 0;
+  for (int it0 = 0; it0 < n_items; it0 += B) {
+    int ob[B], qb[B];
 #pragma unroll
     for (int b = 0; b < B; ++b) {
-      int it = it0 + kstep * b;
-      it = it < n_items ? it : n_items - 1;
-      const int o = (int)(((float)it + 0.5f) * inv_kpa);
-      int k = it - o * kpa;
-      k = k < ngh ? k : ngh - 1;
-      const size_t col = (size_t)(o * ne + le) * ng;
-      av[b] = ub[(col + k) * plane];
-      bv[b] = ub[(col + ng - 1 - k) * plane];
+      ob[b] = o_next;
+      qb[b] = q_next;
+      if (++q_next == nq) {
+        q_next = 0;
+        ++o_next;
+      }
+    }
+    double av[B][2], bv[B][2];
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+      const bool in = it0 + b < n_items;
+      const int o = in ? ob[b] : n_om - 1, q = in ? qb[b] : nq - 1;
+      const unsigned so = (unsigned)o * o_step + tcol;
+      const unsigned r0 = min(kfp + (unsigned)q * q_step, lastp);
+      const unsigned r1 = min(r0 + pl, lastp);
+      av[b][0] = ub[so + r0];
+      av[b][1] = ub[so + r1];
+      bv[b][0] = ub[so + (topp - r0)];
+      bv[b][1] = ub[so + (topp - r1)];
     }
 #pragma unroll
     for (int b = 0; b < B; ++b) {
-      const int it = it0 + kstep * b;
-      if (it < n_items) {
-        const int o = (int)(((float)it + 0.5f) * inv_kpa);
-        const int k = it - o * kpa;
-        const bool ok = okc && k < ngh;
-        const double a = ok ? av[b] : 0.0, bb = ok ? bv[b] : 0.0;
-        F::put(X + (o * 2 + 0) * tile + t * ld, ps, k, a + bb);
-        F::put(X + (o * 2 + 1) * tile + t * ld, ps, k, a - bb);
+      const int k = 2 * (kf + kstep * qb[b]);
+      if (it0 + b < n_items && k < kpa) {
+        const bool ok0 = okc && k < ngh, ok1 = okc && k + 1 < ngh;
+        const double a0 = ok0 ? av[b][0] : 0.0, c0 = ok0 ? bv[b][0] : 0.0;
+        const double a1 = ok1 ? av[b][1] : 0.0, c1 = ok1 ? bv[b][1] : 0.0;
+        E* x = Xt + (ob[b] * 2) * tile + 2 * kstep * qb[b];
+        F::put2(x, ps, 0, a0 + c0, a1 + c1);
+        F::put2(x + tile, ps, 0, a0 - c0, a1 - c1);
       }
     }
   }
@@ -367,19 +388,23 @@ __device__ __forceinline__ void ang_back(const typename Fmt<P>::E* __restrict__ 
           }
       }
     }
-    const size_t col = (size_t)(o * ne + le) * ng;
+    // uniform block base, 32-bit per-lane offsets (a packet holds < 2^29 values);
+    // the unscaling and the sum / difference in h's precision
+    using HT = typename HType<P>::T;
+    HT* __restrict__ hb = h + ((size_t)(o * ne + le) * ng * plane + (size_t)m * nr + i0);
+    const unsigned pl = (unsigned)plane;
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) {
-      const int i = i0 + nt * 16 + (l & 15);
-      if (i >= nr) continue;
+      const int tc = nt * 16 + (l & 15);
+      if (i0 + tc >= nr) continue;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int n = mt * 16 + M::row(l, v);
         if (n >= ngh) continue;
-        const double h0 = (double)acc[0][nt][v] * M::kUnscale;
-        const double h1 = (double)acc[1][nt][v] * M::kUnscale;
-        h[(col + n) * plane + (size_t)m * nr + i] = (typename HType<P>::T)(h0 + h1);
-        h[(col + ng - 1 - n) * plane + (size_t)m * nr + i] = (typename HType<P>::T)(h0 - h1);
+        const HT h0 = (HT)acc[0][nt][v] * (HT)M::kUnscale;
+        const HT h1 = (HT)acc[1][nt][v] * (HT)M::kUnscale;
+        hb[(unsigned)n * pl + tc] = h0 + h1;
+        hb[(unsigned)(ng - 1 - n) * pl + tc] = h0 - h1;
       }
     }
   }
@@ -641,7 +666,7 @@ __global__ __launch_bounds__(256) void k_angr(const double* __restrict__ u_all,
     const int mt = tix % MTj, nt = tix / MTj;
     const int t = nt * 16 + (l & 15);
     const int i = i0 + t;
-    const double br = Br[i < nr ? i : nr - 1];
+    const MX br = (MX)Br[i < nr ? i : nr - 1];
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int j = mt * 16 + M::row(l, v);
@@ -651,8 +676,8 @@ __global__ __launch_bounds__(256) void k_angr(const double* __restrict__ u_all,
       MX cv[MAXOM];
 #pragma unroll
       for (int o = 0; o < MAXOM; ++o)
-        cv[o] = (o < nj) ? (MX)((double)acc[tp][o][v] * M::kUnscale) : (MX)0;
-      const MX rot = (MX)(br * (double)j * (double)(j + 1));
+        cv[o] = (o < nj) ? (MX)acc[tp][o][v] * (MX)M::kUnscale : (MX)0;
+      const MX rot = br * (MX)(j * (j + 1));
       const MX* __restrict__ Lj = Ll + j * (2 * MAXOM + 2);
       // The factor is min(rot + B_R l, cap) on the eigenvalues l of the l^2 block.
       // Below the cap for all of them it is rot + B_R L with L the tridiagonal block

@@ -141,6 +141,12 @@ template <> struct Fmt<kP64> {
     return t[(l & 15) * ld + k0 + (l >> 4)];
   }
   __device__ static void put(E* t, int ps, int idx, double x) { (void)ps; t[idx] = x; }
+  // two consecutive entries (idx even)
+  __device__ static void put2(E* t, int ps, int idx, double x0, double x1) {
+    (void)ps;
+    t[idx] = x0;
+    t[idx + 1] = x1;
+  }
   __device__ static double get(const E* t, int ps, int idx) { (void)ps; return t[idx]; }
 };
 
@@ -153,6 +159,11 @@ template <> struct Fmt<kP32> {
     return t[(l & 15) * ld + k0 + (l >> 4)];
   }
   __device__ static void put(E* t, int ps, int idx, double x) { (void)ps; t[idx] = (float)x; }
+  __device__ static void put2(E* t, int ps, int idx, double x0, double x1) {
+    (void)ps;
+    t[idx] = (float)x0;
+    t[idx + 1] = (float)x1;
+  }
   __device__ static double get(const E* t, int ps, int idx) { (void)ps; return (double)t[idx]; }
 };
 
@@ -173,6 +184,14 @@ template <class S, class V, int PR> struct SplitFmt {
     const E h = (E)v;
     t[idx] = h;
     t[ps + idx] = (E)(v - (float)h);
+  }
+  // two consecutive entries (idx and ps even): one 32-bit store per plane
+  __device__ static void put2(E* t, int ps, int idx, double x0, double x1) {
+    using V2 = E __attribute__((ext_vector_type(2)));
+    const float v0 = (float)x0 * kScale, v1 = (float)x1 * kScale;
+    const E h0 = (E)v0, h1 = (E)v1;
+    *reinterpret_cast<V2*>(t + idx) = V2{h0, h1};
+    *reinterpret_cast<V2*>(t + ps + idx) = V2{(E)(v0 - (float)h0), (E)(v1 - (float)h1)};
   }
   __device__ static double get(const E* t, int ps, int idx) {
     return ((double)(float)t[idx] + (double)(float)t[ps + idx]) / (double)kScale;

@@ -343,7 +343,11 @@ void choose_fast_path(Plan* P) {
   const int kpa = round_up(P->ng / 2, ks);
   const size_t soft = std::min<size_t>(80 * 1024, kLdsMax);   // two workgroups per CU
   int max_om = 0;
-  for (auto& U : P->units) max_om = std::max(max_om, U.n_om);
+  for (auto& U : P->units) {
+    max_om = std::max(max_om, U.n_om);
+    // the step kernels address a packet with 32-bit byte offsets of doubles
+    if ((size_t)U.n_om * P->ne * P->ng * P->nR * P->nr >= ((size_t)1 << 29)) return;
+  }
   P->lds_radr = (size_t)2 * kRadrLines * ld_of(prec, kpr) * eb;
   (void)kpa;
   (void)max_om;
