@@ -37,11 +37,13 @@ PEAKS = {  # MI355X published dense peaks
 }
 
 
-def kernel_model(spec, name, precision):
+def kernel_model(spec, name, precision, fused=False):
     """Algorithmic work of one launch of kernel `name` on this single-unit workload:
     (bound, amount, unit, peak).  Flops count the executed multiply-adds of the
     even/odd-split contractions (2 per MAC); bytes count each HBM array the
-    kernel must touch once (packet FP64, H-partials FP64 or FP32, potential FP64)."""
+    kernel must touch once (packet FP64, H-partials FP64 or FP32, potential FP64).
+    fused: the r pass shares the angular launch and writes T_r u to a buffer of
+    its own, which the R pass reads."""
     nr, nR, ng, ne = spec["n_r"], spec["n_R"], spec["n_gamma"], spec["n_elec"]
     n_blk = sum((u["omega_max"] - (0 if u["parity"] * (-1) ** u["J"] == 1 else 1) + 1) * u["n_packets"]
                 for u in spec["units"])
@@ -52,13 +54,17 @@ def kernel_model(spec, name, precision):
         # T_R split: nR flops per value; bytes: u_k, h, u_{k-1}, V (shared by the
         # helicity blocks of a point), u_{k+1}
         flops, byts = values * nR, values * (8 + hb + 8 + 8 * ne * (ne + 1) / 2 / (n_blk * ne) + 8)
-    elif name == "radial_r":
+        if fused:
+            byts += values * hb
+    elif name == "radial_r" and not fused:
         # T_r split: nr flops per value; bytes: u_k, h read and written
         flops, byts = values * nr, values * (8 + 2 * hb)
     elif name == "angular":
         # forward by absolute j (2 ng flops per value), back by parity class (ng);
         # bytes: u_k, h written
         flops, byts = values * 3 * ng, values * (8 + hb)
+        if fused:   # plus the r pass: u_k read again, T_r u written
+            flops, byts = flops + values * nr, byts + values * (8 + hb)
     else:
         return None
     if fp64 and flops / byts > PEAKS["fp64"][0] * 1e3 / PEAKS["hbm"][0]:
@@ -314,10 +320,12 @@ def main():
     plan, ms, wall = timed(args.precision, args.steps, args.warmup)
     steps_per_s = args.steps / (ms / 1e3)
     kt = plan.time_kernels(args.kernel_steps)
-    per_step = {k: v for k, v in kt.items()}
-    dom = max((k for k in per_step if kernel_model(spec, k, args.precision)), key=lambda k: per_step[k])
+    fused = bool(plan.stat("fuse_r"))
+    per_step = {k: v for k, v in kt.items() if not (fused and k == "radial_r")}
+    dom = max((k for k in per_step if kernel_model(spec, k, args.precision, fused)),
+              key=lambda k: per_step[k])
     traffic = measured_traffic(dom, args.workload, args.precision)
-    bound, amount, unit, peak, _ = kernel_model(spec, dom, args.precision)
+    bound, amount, unit, peak, _ = kernel_model(spec, dom, args.precision, fused)
     achieved = amount / (per_step[dom] * 1e-6)
     roofline = dict(bound=bound, achieved=round(achieved, 3), peak=peak, unit=unit,
                     frac=round(achieved / peak, 4), traffic=traffic, kernel=dom,
@@ -365,6 +373,7 @@ def main():
                    "fp64_steps_per_s": round(fp64_rate, 2) if fp64_rate else None,
                    "speedup_vs_fp64": round(steps_per_s / fp64_rate, 3) if fp64_rate else None,
                    "autotune": tune_reports or None,
+                   "fused_r": fused,
                    "pe_vs_fp64": pe,
                    "wall_s": round(wall, 3)},
         "roofline": roofline,

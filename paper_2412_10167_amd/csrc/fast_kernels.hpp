@@ -94,13 +94,16 @@ struct SliceArgs {
   const int* blk_pk;               // packet holding the first line of each workgroup
 };
 
-template <int P>
-__global__ __launch_bounds__(256) void k_radr(const double* __restrict__ u,
-                                              typename HType<P>::T* __restrict__ h,
-                                              const typename Fmt<P>::E* __restrict__ Ts,
-                                              const typename Fmt<P>::E* __restrict__ Td,
-                                              int ldt, int pst, int nr, long nlines,
-                                              SliceArgs sa) {
+// ACC: h += T_r u (h holds the angular terms); otherwise h receives T_r u alone
+// (the r pass then runs beside the angular pass and the R pass adds both).
+// Blocks bid0, bid0 + bstride, ... of the pass.
+template <int P, bool ACC>
+__device__ __forceinline__ void radr_blk(const double* __restrict__ u,
+                                         typename HType<P>::T* __restrict__ h,
+                                         const typename Fmt<P>::E* __restrict__ Ts,
+                                         const typename Fmt<P>::E* __restrict__ Td, int ldt,
+                                         int pst, int nr, long nlines, const SliceArgs& sa,
+                                         long bid0, long bstride) {
   using M = Mma<P>;
   using F = Fmt<P>;
   using E = typename F::E;
@@ -116,8 +119,7 @@ __global__ __launch_bounds__(256) void k_radr(const double* __restrict__ u,
   const bool rec_ok = crow >= 0 && crow < sa.ring_len;
   double* ring_row = rec_ok ? sa.ring_base + (size_t)crow * sa.ring_stride : nullptr;
   const long nblk = (nlines + kRadrLines - 1) / kRadrLines;
-  // a workgroup takes blocks blockIdx.x, blockIdx.x + gridDim.x, ...
-  for (long blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+  for (long blk = bid0; blk < nblk; blk += bstride) {
   __syncthreads();   // the previous block's operands have been read
   const long line0 = blk * kRadrLines;
   // wave w loads lines w, w+4, ...; lanes run along the half line; the loads of
@@ -227,8 +229,8 @@ __global__ __launch_bounds__(256) void k_radr(const double* __restrict__ u,
   for (int nt = (w >> 1); nt < NT; nt += 2) {
     // the angular pass has written h already: read this lane's 8 values first
     // (clamped, in-range addresses; outputs outside the range are skipped below)
-    typename HType<P>::T hp[4], hm[4];
-    {
+    typename HType<P>::T hp[4] = {}, hm[4] = {};
+    if constexpr (ACC) {
       int a = nt * 16 + (l & 15);
       a = a < nh ? a : nh - 1;
 #pragma unroll
@@ -264,12 +266,27 @@ __global__ __launch_bounds__(256) void k_radr(const double* __restrict__ u,
       if (gl < nlines && a < nh) {
         const double ys = (double)cs[v] * M::kUnscale;
         const double yd = (double)cd[v] * M::kUnscale;
-        h[gl * nr + a] = (typename HType<P>::T)((double)hp[v] + ys + yd);
-        h[gl * nr + nr - 1 - a] = (typename HType<P>::T)((double)hm[v] + ys - yd);
+        if constexpr (ACC) {
+          h[gl * nr + a] = (typename HType<P>::T)((double)hp[v] + ys + yd);
+          h[gl * nr + nr - 1 - a] = (typename HType<P>::T)((double)hm[v] + ys - yd);
+        } else {
+          h[gl * nr + a] = (typename HType<P>::T)(ys + yd);
+          h[gl * nr + nr - 1 - a] = (typename HType<P>::T)(ys - yd);
+        }
       }
     }
   }
   }
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void k_radr(const double* __restrict__ u,
+                                              typename HType<P>::T* __restrict__ h,
+                                              const typename Fmt<P>::E* __restrict__ Ts,
+                                              const typename Fmt<P>::E* __restrict__ Td,
+                                              int ldt, int pst, int nr, long nlines,
+                                              SliceArgs sa) {
+  radr_blk<P, true>(u, h, Ts, Td, ldt, pst, nr, nlines, sa, blockIdx.x, gridDim.x);
 }
 
 // Loads the sums / differences of mirrored Gauss-Legendre nodes of every helicity of
@@ -420,16 +437,15 @@ __device__ __forceinline__ void ang_back(const typename Fmt<P>::E* __restrict__ 
 constexpr int kAngMaxAcc = 12;   // 16x16 accumulators per wave held across the barrier
 
 template <int P, int NT, int MAXOM>
-__global__ __launch_bounds__(256) void k_ang(const double* __restrict__ u_all,
-                                             typename HType<P>::T* __restrict__ h_all,
-                                             const PkDesc* __restrict__ pks,
-                                             const int* __restrict__ blk_start, int n_pk, int ne,
-                                             int ng, int nR, int nr,
-                                             const typename Fmt<P>::E* __restrict__ Pc,
-                                             const typename Fmt<P>::E* __restrict__ PcT,
-                                             int ngk, int psp,
-                                             const double* __restrict__ Br,
-                                             const double* __restrict__ BR, double rot_cut) {
+__device__ __forceinline__ void ang_blk(const double* __restrict__ u_all,
+                                        typename HType<P>::T* __restrict__ h_all,
+                                        const PkDesc* __restrict__ pks,
+                                        const int* __restrict__ blk_start, int n_pk, int ne,
+                                        int ng, int nR, int nr,
+                                        const typename Fmt<P>::E* __restrict__ Pc,
+                                        const typename Fmt<P>::E* __restrict__ PcT, int ngk,
+                                        int psp, const double* __restrict__ Br,
+                                        const double* __restrict__ BR, double rot_cut, int bid) {
   using M = Mma<P>;
   using F = Fmt<P>;
   using E = typename F::E;
@@ -437,8 +453,8 @@ __global__ __launch_bounds__(256) void k_ang(const double* __restrict__ u_all,
   constexpr int RT = 16 * NT;
   constexpr int RES = kAngMaxAcc / NT;
   extern __shared__ __align__(16) double lds[];
-  const int pk = find_packet(blk_start, n_pk, blockIdx.x);
-  const int local = blockIdx.x - blk_start[pk];
+  const int pk = find_packet(blk_start, n_pk, bid);
+  const int local = bid - blk_start[pk];
   const PkDesc d = pks[pk];
   const double* __restrict__ u = u_all + d.off;
   typename HType<P>::T* __restrict__ h = h_all + d.off;
@@ -561,17 +577,15 @@ __global__ __launch_bounds__(256) void k_ang(const double* __restrict__ u_all,
 // C[o][class][t][jj] in X's place for the back transform of ang_back.  TPW tiles
 // per wave times MAXOM helicities bound the accumulators held across the barrier.
 template <int P, int NT, int MAXOM, int TPW>
-__global__ __launch_bounds__(256) void k_angr(const double* __restrict__ u_all,
-                                              typename HType<P>::T* __restrict__ h_all,
-                                              const PkDesc* __restrict__ pks,
-                                              const int* __restrict__ blk_start, int n_pk, int ne,
-                                              int ng, int nR, int nr,
-                                              const typename Fmt<P>::E* __restrict__ Pf, int ngr,
-                                              int psf,
-                                              const typename Fmt<P>::E* __restrict__ PcT,
-                                              int ngk, int psp,
-                                              const double* __restrict__ Br,
-                                              const double* __restrict__ BR, double rot_cut) {
+__device__ __forceinline__ void angr_blk(const double* __restrict__ u_all,
+                                         typename HType<P>::T* __restrict__ h_all,
+                                         const PkDesc* __restrict__ pks,
+                                         const int* __restrict__ blk_start, int n_pk, int ne,
+                                         int ng, int nR, int nr,
+                                         const typename Fmt<P>::E* __restrict__ Pf, int ngr,
+                                         int psf, const typename Fmt<P>::E* __restrict__ PcT,
+                                         int ngk, int psp, const double* __restrict__ Br,
+                                         const double* __restrict__ BR, double rot_cut, int bid) {
   using M = Mma<P>;
   using F = Fmt<P>;
   using E = typename F::E;
@@ -579,8 +593,8 @@ __global__ __launch_bounds__(256) void k_angr(const double* __restrict__ u_all,
   constexpr int RT = 16 * NT;
   static_assert(TPW * MAXOM <= 16, "accumulators per wave");
   extern __shared__ __align__(16) double lds[];
-  const int pk = find_packet(blk_start, n_pk, blockIdx.x);
-  const int local = blockIdx.x - blk_start[pk];
+  const int pk = find_packet(blk_start, n_pk, bid);
+  const int local = bid - blk_start[pk];
   const PkDesc d = pks[pk];
   const double* __restrict__ u = u_all + d.off;
   typename HType<P>::T* __restrict__ h = h_all + d.off;
@@ -741,6 +755,73 @@ __global__ __launch_bounds__(256) void k_angr(const double* __restrict__ u_all,
                   m, i0, nr, plane);
 }
 
+// Arguments of the angular pass and of the r pass, for the launches that run
+// both side by side.
+struct AngArgs {
+  const double* u_all;
+  void* h_all;
+  const PkDesc* pks;
+  const int* blk_start;
+  int n_pk, ne, ng, nR, nr;
+  const void* Pfwd;   // forward table: Pc (LDS-mixing kernel) or Pf (register mixing)
+  int ngr, psf;
+  const void* PcT;
+  int ngk, psp;
+  const double* Br;
+  const double* BR;
+  double rot_cut;
+};
+struct RadrArgs {
+  const double* u;
+  void* h2;           // receives T_r u
+  const void* Ts;
+  const void* Td;
+  int ldt, pst, nr;
+  long nlines;
+  SliceArgs sa;
+};
+
+template <int P, int NT, int MAXOM>
+__global__ __launch_bounds__(256) void k_ang(AngArgs a) {
+  using E = typename Fmt<P>::E;
+  ang_blk<P, NT, MAXOM>(a.u_all, (typename HType<P>::T*)a.h_all, a.pks, a.blk_start, a.n_pk, a.ne,
+                        a.ng, a.nR, a.nr, (const E*)a.Pfwd, (const E*)a.PcT, a.ngk, a.psp, a.Br,
+                        a.BR, a.rot_cut, blockIdx.x);
+}
+template <int P, int NT, int MAXOM, int TPW>
+__global__ __launch_bounds__(256) void k_angr(AngArgs a) {
+  using E = typename Fmt<P>::E;
+  angr_blk<P, NT, MAXOM, TPW>(a.u_all, (typename HType<P>::T*)a.h_all, a.pks, a.blk_start, a.n_pk,
+                              a.ne, a.ng, a.nR, a.nr, (const E*)a.Pfwd, a.ngr, a.psf,
+                              (const E*)a.PcT, a.ngk, a.psp, a.Br, a.BR, a.rot_cut, blockIdx.x);
+}
+// The angular pass (blocks 0 .. n_ang-1) and the r pass (the rest) in one launch:
+// neither reads what the other writes, so their memory latencies overlap.
+template <int P, int NT, int MAXOM>
+__global__ __launch_bounds__(256) void k_ang_radr(AngArgs a, RadrArgs r, int n_ang) {
+  using E = typename Fmt<P>::E;
+  using HT = typename HType<P>::T;
+  if ((int)blockIdx.x < n_ang)
+    ang_blk<P, NT, MAXOM>(a.u_all, (HT*)a.h_all, a.pks, a.blk_start, a.n_pk, a.ne, a.ng, a.nR,
+                          a.nr, (const E*)a.Pfwd, (const E*)a.PcT, a.ngk, a.psp, a.Br, a.BR,
+                          a.rot_cut, blockIdx.x);
+  else
+    radr_blk<P, false>(r.u, (HT*)r.h2, (const E*)r.Ts, (const E*)r.Td, r.ldt, r.pst, r.nr,
+                       r.nlines, r.sa, (long)blockIdx.x - n_ang, (long)gridDim.x - n_ang);
+}
+template <int P, int NT, int MAXOM, int TPW>
+__global__ __launch_bounds__(256) void k_angr_radr(AngArgs a, RadrArgs r, int n_ang) {
+  using E = typename Fmt<P>::E;
+  using HT = typename HType<P>::T;
+  if ((int)blockIdx.x < n_ang)
+    angr_blk<P, NT, MAXOM, TPW>(a.u_all, (HT*)a.h_all, a.pks, a.blk_start, a.n_pk, a.ne, a.ng,
+                                a.nR, a.nr, (const E*)a.Pfwd, a.ngr, a.psf, (const E*)a.PcT, a.ngk,
+                                a.psp, a.Br, a.BR, a.rot_cut, blockIdx.x);
+  else
+    radr_blk<P, false>(r.u, (HT*)r.h2, (const E*)r.Ts, (const E*)r.Td, r.ldt, r.pst, r.nr,
+                       r.nlines, r.sa, (long)blockIdx.x - n_ang, (long)gridDim.x - n_ang);
+}
+
 // ---- T_R along R, potential, scaling, recursion, damping, norm partial ---------------
 // (SPLIT: only y = T_R u + h is formed and stored in h's place; the learned-potential
 // pass k_mlp_epi adds the potential and finishes the step.)
@@ -769,10 +850,11 @@ __device__ __forceinline__ void advance_if_last(int* counters, int recorded) {
 // faster while it costs occupancy).
 constexpr int kXLd = 16;
 
-template <int P, int NE, bool SPLIT = false>
+template <int P, int NE, bool SPLIT = false, bool TWO = false>
 __global__ __launch_bounds__(256) void k_radR_epi(
     const double* __restrict__ uk_all, double* __restrict__ uprev_all,
-    typename HType<P>::T* __restrict__ h_all, const PkDesc* __restrict__ pks,
+    typename HType<P>::T* __restrict__ h_all, const typename HType<P>::T* __restrict__ h2_all,
+    const PkDesc* __restrict__ pks,
     const int* __restrict__ blk_start, int n_pk, const typename Fmt<P>::E* __restrict__ Ts,
     const typename Fmt<P>::E* __restrict__ Td, int ldt, int pst, const double* __restrict__ V,
     const double* __restrict__ D, int ng, int nR, int nr, double E0, double inv_dE,
@@ -799,6 +881,8 @@ __global__ __launch_bounds__(256) void k_radR_epi(
   const double* __restrict__ uk = uk_all + dsc.off;
   double* __restrict__ uprev = uprev_all + dsc.off;
   HT* __restrict__ h = h_all + dsc.off;
+  // TWO: T_r u in a separate buffer (the r pass ran beside the angular pass)
+  const HT* __restrict__ h2 = TWO ? h2_all + dsc.off : h;
   const int nrt = (nr + RT - 1) / RT;
   const int nh = nR >> 1;
   const int kp = round_up(nh, M::KS);
@@ -860,7 +944,7 @@ __global__ __launch_bounds__(256) void k_radR_epi(
       // epilogue operands of this lane's 8 outputs (rows a and n_R-1-a), loaded
       // before the contraction so their latency overlaps it
       // (addresses clamped into range; outputs outside it are skipped below)
-      HT hv[8];
+      HT hv[8], hw[8] = {};
       double dv[8], pv[8], vv[8][NE];
       const int ic = i < nr ? i : nr - 1;
 #pragma unroll
@@ -874,6 +958,7 @@ __global__ __launch_bounds__(256) void k_radR_epi(
           const size_t pt = (size_t)n * plane + (size_t)mm * nr + ic;
           const size_t idx = (size_t)(o * NE + le) * ng * plane + pt;
           hv[q] = h[idx];
+          if constexpr (TWO) hw[q] = h2[idx];
           if constexpr (!SPLIT) {
             dv[q] = D[(size_t)mm * nr + ic];
             pv[q] = first ? 0.0 : uprev[idx];
@@ -914,7 +999,7 @@ __global__ __launch_bounds__(256) void k_radR_epi(
           const int q = 2 * v + side;
           const int mm = side ? nR - 1 - a : a;
           const size_t idx = (size_t)(o * NE + le) * ng * plane + (size_t)n * plane + (size_t)mm * nr + i;
-          double sacc = (side ? ys - yd : ys + yd) + (double)hv[q];
+          double sacc = (side ? ys - yd : ys + yd) + (TWO ? (double)hv[q] + (double)hw[q] : (double)hv[q]);
           if constexpr (SPLIT) {   // T_R u + h only; the potential and the recursion follow
             h[idx] = (HT)sacc;
             continue;

@@ -92,6 +92,7 @@ struct tdwp_plan_s {
   int ang_regs = 0;          // angular kernel: 0 k_ang, else k_angr with this many helicities
   long radial_grid = 0;      // workgroups of the two radial passes (0: one per block)
   int ang_pref = 0;          // angular kernel: 0 automatic, 1 k_ang, 2 k_angr
+  bool fuse_r = true;        // angular and r passes in one launch (T_r u into d_h2)
   int nrhk = 0, nRhk = 0, ngk = 0, ngr = 0;
   size_t lds_radr = 0, lds_ang = 0, lds_radR = 0;
   std::vector<double> Trs, Trd, TRs, TRd, Pc;
@@ -122,6 +123,7 @@ struct tdwp_plan_s {
   bool own_stream = false;
   double* d_u[2] = {nullptr, nullptr};
   double* d_h = nullptr;
+  double* d_h2 = nullptr;    // T_r u when the r pass shares the angular launch
   double* d_V = nullptr;
   double* d_Tr = nullptr;
   double* d_TR = nullptr;

@@ -395,22 +395,47 @@ int upload_tables(Plan* P) {
   return TDWP_OK;
 }
 
+// Kernel choice for the angular pass alone (Plain) or with the r pass (Fused).
+struct PlainAng {};
+struct FusedAng {};
+template <int PR, int NT, int M, int TPW>
+auto angr_ptr(PlainAng) { return k_angr<PR, NT, M, TPW>; }
+template <int PR, int NT, int M, int TPW>
+auto angr_ptr(FusedAng) { return k_angr_radr<PR, NT, M, TPW>; }
+template <int PR, int NT, int M>
+auto ang_ptr(PlainAng) { return k_ang<PR, NT, M>; }
+template <int PR, int NT, int M>
+auto ang_ptr(FusedAng) { return k_ang_radr<PR, NT, M>; }
+
 // Calls f with the register-mixing angular kernel for tile width nt, helicity width
 // mom and at least tpw column tiles per wave.
-template <int PR, class F>
-void with_angr(int nt, int mom, int tpw, F&& f) {
+template <int PR, class Tag, class F>
+void with_angr(int nt, int mom, int tpw, Tag tag, F&& f) {
   auto by_nt = [&](auto ntc) {
     constexpr int NT = decltype(ntc)::value;
     if (mom == 1) {
-      if (tpw <= 4) f(k_angr<PR, NT, 1, 4>);
-      else if (tpw <= 8) f(k_angr<PR, NT, 1, 8>);
-      else f(k_angr<PR, NT, 1, 16>);
+      if (tpw <= 4) f(angr_ptr<PR, NT, 1, 4>(tag));
+      else if (tpw <= 8) f(angr_ptr<PR, NT, 1, 8>(tag));
+      else f(angr_ptr<PR, NT, 1, 16>(tag));
     } else if (mom == 8) {
-      if (tpw <= 1) f(k_angr<PR, NT, 8, 1>);
-      else f(k_angr<PR, NT, 8, 2>);
+      if (tpw <= 1) f(angr_ptr<PR, NT, 8, 1>(tag));
+      else f(angr_ptr<PR, NT, 8, 2>(tag));
     } else {
-      f(k_angr<PR, NT, 16, 1>);
+      f(angr_ptr<PR, NT, 16, 1>(tag));
     }
+  };
+  if (nt == 4) by_nt(std::integral_constant<int, 4>{});
+  else if (nt == 2) by_nt(std::integral_constant<int, 2>{});
+  else by_nt(std::integral_constant<int, 1>{});
+}
+
+// The same for the LDS-mixing angular kernel (one helicity or up to kMaxOmega).
+template <int PR, class Tag, class F>
+void with_ang(int nt, bool single, Tag tag, F&& f) {
+  auto by_nt = [&](auto ntc) {
+    constexpr int NT = decltype(ntc)::value;
+    if (single) f(ang_ptr<PR, NT, 1>(tag));
+    else f(ang_ptr<PR, NT, kMaxOmega>(tag));
   };
   if (nt == 4) by_nt(std::integral_constant<int, 4>{});
   else if (nt == 2) by_nt(std::integral_constant<int, 2>{});
@@ -423,19 +448,28 @@ void with_angr(int nt, int mom, int tpw, F&& f) {
 template <int PR>
 void set_lds_limits() {
   if (kLdsMax <= 64 * 1024) return;
-  const void* fns[15] = {(const void*)k_radr<PR>, (const void*)k_ang<PR, 1, 1>,
-                         (const void*)k_ang<PR, 2, 1>, (const void*)k_ang<PR, 4, 1>,
-                         (const void*)k_ang<PR, 1, kMaxOmega>, (const void*)k_ang<PR, 2, kMaxOmega>,
-                         (const void*)k_ang<PR, 4, kMaxOmega>, (const void*)k_radR_epi<PR, 1>,
-                         (const void*)k_radR_epi<PR, 2>, (const void*)k_radR_epi<PR, 3>,
-                         (const void*)k_radR_epi<PR, 4>, (const void*)k_mlp_epi<PR, 1>,
-                         (const void*)k_mlp_epi<PR, 2>, (const void*)k_mlp_epi<PR, 3>,
-                         (const void*)k_mlp_epi<PR, 4>};
-  std::vector<const void*> all(fns, fns + 15);
-  for (int nt : {1, 2, 4})
+  const void* fns[13] = {(const void*)k_radr<PR>,         (const void*)k_radR_epi<PR, 1>,
+                         (const void*)k_radR_epi<PR, 2>,  (const void*)k_radR_epi<PR, 3>,
+                         (const void*)k_radR_epi<PR, 4>,  (const void*)k_mlp_epi<PR, 1>,
+                         (const void*)k_mlp_epi<PR, 2>,   (const void*)k_mlp_epi<PR, 3>,
+                         (const void*)k_mlp_epi<PR, 4>,
+                         (const void*)k_radR_epi<PR, 1, false, true>,
+                         (const void*)k_radR_epi<PR, 2, false, true>,
+                         (const void*)k_radR_epi<PR, 3, false, true>,
+                         (const void*)k_radR_epi<PR, 4, false, true>};
+  std::vector<const void*> all(fns, fns + 13);
+  auto add = [&](auto kern) { all.push_back((const void*)kern); };
+  for (int nt : {1, 2, 4}) {
+    for (bool single : {true, false}) {
+      with_ang<PR>(nt, single, PlainAng{}, add);
+      with_ang<PR>(nt, single, FusedAng{}, add);
+    }
     for (int mom : {1, 8, 16})
-      for (int tpw : {1, 2, 4, 8, 16})
-        with_angr<PR>(nt, mom, tpw, [&](auto kern) { all.push_back((const void*)kern); });
+      for (int tpw : {1, 2, 4, 8, 16}) {
+        with_angr<PR>(nt, mom, tpw, PlainAng{}, add);
+        with_angr<PR>(nt, mom, tpw, FusedAng{}, add);
+      }
+  }
   for (const void* f : all) {
     // the dynamic share is what the device allows beyond the kernel's static LDS
     hipFuncAttributes fa{};
@@ -533,6 +567,7 @@ int layout_and_allocate(Plan* P) {
   TRY(dev_alloc(P, (void**)&P->d_u[0], P->n_total * sizeof(double)));
   TRY(dev_alloc(P, (void**)&P->d_u[1], P->n_total * sizeof(double)));
   TRY(dev_alloc(P, (void**)&P->d_h, P->n_total * sizeof(double)));
+  if (P->fast) TRY(dev_alloc(P, (void**)&P->d_h2, P->n_total * sizeof(double)));
   TRY(dev_alloc(P, (void**)&P->d_V, (size_t)P->npair * ng * nR * nr * sizeof(double)));
   TRY(alloc_copy(P, &P->d_Tr, P->Tr));
   TRY(alloc_copy(P, &P->d_TR, P->TR));
@@ -941,58 +976,60 @@ int enqueue_step(Plan* P, int cur, int first, int rec, Timing* T) {
   const int nr = P->nr, nR = P->nR, ng = P->ng, ne = P->ne;
   const int np = (int)P->packets.size();
   const PkDesc* pkd = (const PkDesc*)P->d_pkdesc;
+  const long nlines = (long)(P->n_total / nr);
+  const int nrh = nr / 2;
+  SliceArgs sa{rec, 0, P->d_line_start, P->d_slice_off, np, nR, P->m_inf,
+               P->d_flux_split, P->d_flux_split + nrh, P->d_flux_split + 2 * nrh,
+               P->d_flux_split + 3 * nrh, 1.0 / std::sqrt(P->dR), P->d_ring, P->slice_total,
+               P->d_counters, P->ring_len, P->d_radr_pk};
+  const unsigned nblk_r = radial_blocks(P, (nlines + kRadrLines - 1) / kRadrLines);
+  const bool fuse = P->fuse_r;
+  HT* h2 = fuse ? reinterpret_cast<HT*>(P->d_h2) : nullptr;
   TRY(timed_begin(P, T));
   {
-    const int psp = (int)P->Pc.size();
-    auto launch = [&](auto kern) {
-      hipLaunchKernelGGL(kern, dim3(P->blocks_ang), dim3(256), P->lds_ang_max, P->stream, uk, h,
-                         pkd, P->d_blk_ang, np, ne, ng, nR, nr, (const E*)P->d_PcF,
-                         (const E*)P->d_PcTF, P->ngk, psp, P->d_Br, P->d_BR, P->cfg.rot_cut);
+    AngArgs aa{uk, h, pkd, P->d_blk_ang, np, ne, ng, nR, nr, nullptr, P->ngr, (int)P->Pf.size(),
+               P->d_PcTF, P->ngk, (int)P->Pc.size(), P->d_Br, P->d_BR, P->cfg.rot_cut};
+    RadrArgs ra{uk, h2, P->d_TrsF, P->d_TrdF, P->nrhk, P->nrhk * P->nrhk, nr, nlines, sa};
+    auto plain = [&](auto kern) {
+      hipLaunchKernelGGL(kern, dim3(P->blocks_ang), dim3(256), P->lds_ang_max, P->stream, aa);
     };
-    auto launch_r = [&](auto kern) {
-      hipLaunchKernelGGL(kern, dim3(P->blocks_ang), dim3(256), P->lds_ang_max, P->stream, uk, h,
-                         pkd, P->d_blk_ang, np, ne, ng, nR, nr, (const E*)P->d_PfF, P->ngr,
-                         (int)P->Pf.size(), (const E*)P->d_PcTF, P->ngk, psp, P->d_Br, P->d_BR,
-                         P->cfg.rot_cut);
+    // the r-pass blocks follow the angular blocks in the same grid
+    auto fused = [&](auto kern) {
+      hipLaunchKernelGGL(kern, dim3(P->blocks_ang + nblk_r), dim3(256),
+                         std::max(P->lds_ang_max, P->lds_radr), P->stream, aa, ra,
+                         (int)P->blocks_ang);
     };
     int max_om = 0;
     for (auto& U : P->units) max_om = std::max(max_om, U.n_om);
     if (P->ang_regs) {
+      aa.Pfwd = P->d_PfF;
       // column tiles per wave: (j tiles) x (r tiles) over the four waves
       const int tpw = ((ng + 15) / 16 * P->nta + 3) / 4;
-      with_angr<PR>(P->nta, P->ang_regs, tpw, launch_r);
-    } else if (max_om == 1) {
-      if (P->nta == 4) launch(k_ang<PR, 4, 1>);
-      else if (P->nta == 2) launch(k_ang<PR, 2, 1>);
-      else launch(k_ang<PR, 1, 1>);
+      if (fuse) with_angr<PR>(P->nta, P->ang_regs, tpw, FusedAng{}, fused);
+      else with_angr<PR>(P->nta, P->ang_regs, tpw, PlainAng{}, plain);
     } else {
-      if (P->nta == 4) launch(k_ang<PR, 4, kMaxOmega>);
-      else if (P->nta == 2) launch(k_ang<PR, 2, kMaxOmega>);
-      else launch(k_ang<PR, 1, kMaxOmega>);
+      aa.Pfwd = P->d_PcF;
+      if (fuse) with_ang<PR>(P->nta, max_om == 1, FusedAng{}, fused);
+      else with_ang<PR>(P->nta, max_om == 1, PlainAng{}, plain);
     }
   }
   HIP_TRY(hipGetLastError());
   TRY(timed_end(P, T, 0));
-  TRY(timed_begin(P, T));
-  {
-    const long nlines = (long)(P->n_total / nr);
-    const int h2 = nr / 2;
-    SliceArgs sa{rec, 0, P->d_line_start, P->d_slice_off, np, nR, P->m_inf,
-                 P->d_flux_split, P->d_flux_split + h2, P->d_flux_split + 2 * h2,
-                 P->d_flux_split + 3 * h2, 1.0 / std::sqrt(P->dR), P->d_ring, P->slice_total,
-                 P->d_counters, P->ring_len, P->d_radr_pk};
-    hipLaunchKernelGGL(k_radr<PR>, dim3(radial_blocks(P, (nlines + kRadrLines - 1) / kRadrLines)),
-                       dim3(256), P->lds_radr, P->stream, uk, h, (const E*)P->d_TrsF,
-                       (const E*)P->d_TrdF, P->nrhk, P->nrhk * P->nrhk, nr, nlines, sa);
+  if (!fuse) {
+    TRY(timed_begin(P, T));
+    hipLaunchKernelGGL(k_radr<PR>, dim3(nblk_r), dim3(256), P->lds_radr, P->stream, uk, h,
+                       (const E*)P->d_TrsF, (const E*)P->d_TrdF, P->nrhk, P->nrhk * P->nrhk, nr,
+                       nlines, sa);
+    HIP_TRY(hipGetLastError());
+    TRY(timed_end(P, T, 4));
   }
-  HIP_TRY(hipGetLastError());
-  TRY(timed_end(P, T, 4));
   TRY(timed_begin(P, T));
   if (P->pot_mode == TDWP_POT_MLP) {
     // y = T_R u + h in h's place, then the network and the rest of the step per point
     auto split = [&](auto kern) {
       hipLaunchKernelGGL(kern, dim3(radial_blocks(P, P->blocks_radR)), dim3(256), P->lds_radR,
-                         P->stream, uk, uo, h, pkd, P->d_blk_radR, np, (const E*)P->d_TRsF,
+                         P->stream, uk, uo, h, (const HT*)h2, pkd, P->d_blk_radR, np,
+                         (const E*)P->d_TRsF,
                          (const E*)P->d_TRdF, P->nRhk, P->nRhk * P->nRhk, P->d_V, P->d_D, ng, nR,
                          nr, P->E0, 1.0 / P->dE, first, P->d_normpart, P->n_wg_total,
                          P->d_counters, kNormChunk, rec);
@@ -1006,25 +1043,26 @@ int enqueue_step(Plan* P, int cur, int first, int rec, Timing* T) {
                          P->d_counters, kNormChunk, rec);
     };
     switch (ne) {
-      case 1: split(k_radR_epi<PR, 1, true>); epi(k_mlp_epi<PR, 1>); break;
-      case 2: split(k_radR_epi<PR, 2, true>); epi(k_mlp_epi<PR, 2>); break;
-      case 3: split(k_radR_epi<PR, 3, true>); epi(k_mlp_epi<PR, 3>); break;
-      default: split(k_radR_epi<PR, 4, true>); epi(k_mlp_epi<PR, 4>); break;
+      case 1: fuse ? split(k_radR_epi<PR, 1, true, true>) : split(k_radR_epi<PR, 1, true>); epi(k_mlp_epi<PR, 1>); break;
+      case 2: fuse ? split(k_radR_epi<PR, 2, true, true>) : split(k_radR_epi<PR, 2, true>); epi(k_mlp_epi<PR, 2>); break;
+      case 3: fuse ? split(k_radR_epi<PR, 3, true, true>) : split(k_radR_epi<PR, 3, true>); epi(k_mlp_epi<PR, 3>); break;
+      default: fuse ? split(k_radR_epi<PR, 4, true, true>) : split(k_radR_epi<PR, 4, true>); epi(k_mlp_epi<PR, 4>); break;
     }
   } else {
     auto launch = [&](auto kern) {
       hipLaunchKernelGGL(kern, dim3(radial_blocks(P, P->blocks_radR)), dim3(256), P->lds_radR,
                          P->stream, uk, uo,
-                         h, pkd, P->d_blk_radR, np, (const E*)P->d_TRsF, (const E*)P->d_TRdF,
+                         h, (const HT*)h2, pkd, P->d_blk_radR, np, (const E*)P->d_TRsF,
+                         (const E*)P->d_TRdF,
                          P->nRhk, P->nRhk * P->nRhk, P->d_V, P->d_D, ng, nR, nr, P->E0,
                          1.0 / P->dE, first, P->d_normpart, P->n_wg_total, P->d_counters,
                          kNormChunk, rec);
     };
     switch (ne) {
-      case 1: launch(k_radR_epi<PR, 1>); break;
-      case 2: launch(k_radR_epi<PR, 2>); break;
-      case 3: launch(k_radR_epi<PR, 3>); break;
-      default: launch(k_radR_epi<PR, 4>); break;
+      case 1: fuse ? launch(k_radR_epi<PR, 1, false, true>) : launch(k_radR_epi<PR, 1>); break;
+      case 2: fuse ? launch(k_radR_epi<PR, 2, false, true>) : launch(k_radR_epi<PR, 2>); break;
+      case 3: fuse ? launch(k_radR_epi<PR, 3, false, true>) : launch(k_radR_epi<PR, 3>); break;
+      default: fuse ? launch(k_radR_epi<PR, 4, false, true>) : launch(k_radR_epi<PR, 4>); break;
     }
   }
   HIP_TRY(hipGetLastError());   // the pass's last workgroup has advanced the counters
@@ -1286,10 +1324,12 @@ int tdwp_plan(const tdwp_config* cfg, tdwp_plan_t* out) {
     return st;
   }
   if (P->fast) {
-    // cached choice: 10 * kernel + tile (kernel 1: LDS mixing, 2: register mixing)
+    // cached choice: 100 * (r pass fused) + 10 * kernel + tile (kernel 1: LDS
+    // mixing, 2: register mixing)
     const int c = cached_tile(P);
-    const int nt = c % 10, kern = c / 10;
-    if ((nt == 1 || nt == 2 || nt == 4) && kern <= 2) {
+    const int nt = c % 10, kern = (c / 10) % 10, fz = c / 100;
+    if ((nt == 1 || nt == 2 || nt == 4) && kern <= 2 && fz <= 1) {
+      P->fuse_r = fz == 1;
       const int keep = P->ang_pref;
       P->ang_pref = kern;
       if (set_ang_tiles(P, nt) != TDWP_OK) {
@@ -1620,22 +1660,25 @@ int tdwp_autotune(tdwp_plan_t p, int steps, char* report, size_t report_len) {
   HIP_TRY(hipMemsetAsync(p->d_u[1], 0, p->n_total * sizeof(double), p->stream));
   std::string rep;
   const int keep_pref = p->ang_pref, keep_nt = p->nta;
-  int best_k = -1, best_nt = keep_nt;
+  const bool keep_fuse = p->fuse_r;
+  int best_k = -1, best_nt = keep_nt, best_f = keep_fuse ? 1 : 0;
   double best_us = 1e300;
-  // angular kernel (2: helicity mixing in registers, 1: through LDS) x tile width
+  // r pass beside the angular pass or after it x angular kernel (2: helicity mixing
+  // in registers, 1: through LDS) x tile width; the angular and r passes are timed
+  for (int fz : {1, 0})
   for (int kern : {2, 1})
     for (int nt : {4, 2, 1}) {
+      p->fuse_r = fz == 1;
       p->ang_pref = kern;
       if (set_ang_tiles(p, nt) != TDWP_OK) continue;
-      T.ms[0] = 0.0;
-      T.calls[0] = 0;
       reset_propagation(p);
       int st = sync_counters(p);
       for (int s2 = 0; s2 < steps + 1 && st == TDWP_OK; ++s2) {   // the first step warms up
-        if (s2 == 1) {
-          T.ms[0] = 0.0;
-          T.calls[0] = 0;
-        }
+        if (s2 <= 1)
+          for (int q : {0, 4}) {
+            T.ms[q] = 0.0;
+            T.calls[q] = 0;
+          }
         st = one_step(p, 0, &T);
       }
       reset_propagation(p);
@@ -1643,33 +1686,39 @@ int tdwp_autotune(tdwp_plan_t p, int steps, char* report, size_t report_len) {
         (void)hipEventDestroy(T.ev[0]);
         (void)hipEventDestroy(T.ev[1]);
         p->ang_pref = keep_pref;
+        p->fuse_r = keep_fuse;
         (void)set_ang_tiles(p, keep_nt);
         return st;
       }
-      const double us = 1000.0 * T.ms[0] / std::max<long>(T.calls[0], 1);
+      const double us = 1000.0 * (T.ms[0] + T.ms[4]) / std::max<long>(T.calls[0], 1);
       char buf[64];
-      std::snprintf(buf, sizeof buf, "%sang_k%d_nt%d:%.1fus", rep.empty() ? "" : ";", kern, nt, us);
+      std::snprintf(buf, sizeof buf, "%sf%d_k%d_nt%d:%.1fus", rep.empty() ? "" : ";", fz, kern, nt,
+                    us);
       rep += buf;
       if (us < best_us) {
         best_us = us;
         best_k = kern;
         best_nt = nt;
+        best_f = fz;
       }
     }
   (void)hipEventDestroy(T.ev[0]);
   (void)hipEventDestroy(T.ev[1]);
   if (best_k < 0) {   // no variant fits: keep the plan's choice
     p->ang_pref = keep_pref;
+    p->fuse_r = keep_fuse;
     TRY(set_ang_tiles(p, keep_nt));
   } else {
     p->ang_pref = best_k;
+    p->fuse_r = best_f == 1;
     TRY(set_ang_tiles(p, best_nt));
-    store_tile(p, 10 * best_k + best_nt);
+    store_tile(p, 100 * best_f + 10 * best_k + best_nt);
   }
   drop_graphs(p);
   reset_propagation(p);
   if (report && report_len) {
-    rep += ";chosen=k" + std::to_string(p->ang_regs ? 2 : 1) + "_nt" + std::to_string(p->nta);
+    rep += ";chosen=f" + std::to_string(p->fuse_r ? 1 : 0) + "_k" + std::to_string(p->ang_regs ? 2 : 1) +
+           "_nt" + std::to_string(p->nta);
     std::strncpy(report, rep.c_str(), report_len - 1);
     report[report_len - 1] = 0;
   }
@@ -1702,6 +1751,11 @@ int tdwp_set_option(tdwp_plan_t p, int option, long value) {
       drop_graphs(p);
       return TDWP_OK;
     }
+    case TDWP_OPT_FUSE_R:
+      if (value != 0 && value != 1) return TDWP_EINVAL;
+      p->fuse_r = value != 0;
+      drop_graphs(p);
+      return TDWP_OK;
     case TDWP_OPT_RADIAL_GRID:
       if (value < 0 || value > (1L << 30)) return TDWP_EINVAL;
       p->radial_grid = value;
@@ -1719,6 +1773,7 @@ int tdwp_get_stat(tdwp_plan_t p, int stat, long* value) {
     case TDWP_STAT_ANG_TILE: *value = p->fast ? p->nta : 0; return TDWP_OK;
     case TDWP_STAT_ANG_KERNEL: *value = p->fast ? (p->ang_regs ? 2 : 1) : 0; return TDWP_OK;
     case TDWP_STAT_MATRIX_CORE_PATH: *value = p->fast ? 1 : 0; return TDWP_OK;
+    case TDWP_STAT_FUSE_R: *value = (p->fast && p->fuse_r) ? 1 : 0; return TDWP_OK;
     default: return TDWP_EINVAL;
   }
 }

@@ -19,8 +19,8 @@ EXPORTED_SYMBOLS = (
     "tdwp_mlp_gradient", "tdwp_mlp_eval", "tdwp_mlp_grid", "tdwp_autotune",
     "tdwp_set_option", "tdwp_get_stat",
 )
-OPTIONS = {"graphs": 0, "ang_tile": 1, "radial_grid": 2, "ang_kernel": 3}
-STATS = {"graph_steps": 0, "ang_tile": 1, "matrix_core_path": 2, "ang_kernel": 3}
+OPTIONS = {"graphs": 0, "ang_tile": 1, "radial_grid": 2, "ang_kernel": 3, "fuse_r": 4}
+STATS = {"graph_steps": 0, "ang_tile": 1, "matrix_core_path": 2, "ang_kernel": 3, "fuse_r": 4}
 
 
 class TdwpError(RuntimeError):

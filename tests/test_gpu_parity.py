@@ -357,15 +357,18 @@ def test_angular_tile_variants(nt):
         plan.close()
 
 
+@pytest.mark.parametrize("fuse", [1, 0])
 @pytest.mark.parametrize("kernel", [1, 2])
-def test_angular_kernels(kernel):
-    banner(f"angular kernel {kernel}: J=0, J=5 Omega 1..3 2 states, J=20 Omega 0..8 2 states")
+def test_angular_kernels(kernel, fuse):
+    banner(f"angular kernel {kernel}, r pass {'in the same launch' if fuse else 'after it'}: "
+           "J=0, J=5 Omega 1..3 2 states, J=20 Omega 0..8 2 states")
     problem = _problem()
     for spec in (small_variant(1, n_R=24, n_r=20, n_gamma=10), _coriolis_spec(5, 1, 3, 2),
                  _coriolis_spec(20, 1, 8, 2)):
         plan, _ = problem.build(spec)
         plan.set_option("ang_kernel", kernel)
-        assert plan.stat("ang_kernel") == kernel
+        plan.set_option("fuse_r", fuse)
+        assert plan.stat("ang_kernel") == kernel and plan.stat("fuse_r") == fuse
         K = 40
         plan.propagate(K)
         op, ref = oracle_packets(spec, K, keep=(K,))
