@@ -850,8 +850,18 @@ __device__ __forceinline__ void advance_if_last(int* counters, int recorded) {
 // faster while it costs occupancy).
 constexpr int kXLd = 16;
 
+// The u_k tile is kept in LDS in h's precision: FP64 in the FP64 form; FP32 in the
+// mixed forms, where it feeds the split contraction operand and the local V u and
+// E0 u terms of H u (rounding at 2^-24, below the contraction's own error).  The
+// mixed forms load one operator chunk at a time and, with one electronic state, ask
+// for four waves per SIMD so that registers do not bound occupancy (measured: with
+// two or more states the request costs more in spills than it gains).
+template <int P, int NE>
+constexpr int radR_waves() { return (P == kP64 || NE > 1) ? 1 : 4; }
+
 template <int P, int NE, bool SPLIT = false, bool TWO = false>
-__global__ __launch_bounds__(256) void k_radR_epi(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(radR_waves<P, NE>())))
+void k_radR_epi(
     const double* __restrict__ uk_all, double* __restrict__ uprev_all,
     typename HType<P>::T* __restrict__ h_all, const typename HType<P>::T* __restrict__ h2_all,
     const PkDesc* __restrict__ pks,
@@ -864,7 +874,8 @@ __global__ __launch_bounds__(256) void k_radR_epi(
   using F = Fmt<P>;
   using E = typename F::E;
   using HT = typename HType<P>::T;
-  constexpr int CH = Chunk<P>::CH;
+  constexpr int CH = (M::KS == 4) ? Chunk<P>::CH : 1;
+  using XT = typename HType<P>::T;
   constexpr int RT = 16;
   extern __shared__ __align__(16) double lds[];
   const int nrow_ix = counters[1];
@@ -892,8 +903,9 @@ __global__ __launch_bounds__(256) void k_radR_epi(
   const int slab = local / nrt;
   const int o = slab / ng, n = slab % ng;
   const size_t plane = (size_t)nR * nr;
-  double* X = lds;                                             // [le][nR][kXLd]
-  E* SD = reinterpret_cast<E*>(lds + (size_t)NE * nR * kXLd);  // S^T [t][k], then D^T
+  XT* X = reinterpret_cast<XT*>(lds);   // [le][nR][kXLd]
+  E* SD = reinterpret_cast<E*>(reinterpret_cast<char*>(lds) +
+                               (size_t)NE * nR * kXLd * sizeof(XT));   // S^T [t][k], then D^T
   {
     const int tt = threadIdx.x & 15, r0 = threadIdx.x >> 4;
     const int ii = i0 + tt;
@@ -902,7 +914,7 @@ __global__ __launch_bounds__(256) void k_radR_epi(
 #pragma unroll
     for (int le = 0; le < NE; ++le) {
       const double* src = uk + ((size_t)(o * NE + le) * ng + n) * plane + iic;
-      double* dst = X + (size_t)le * nR * kXLd + tt;
+      XT* dst = X + (size_t)le * nR * kXLd + tt;
       for (int m0 = r0; m0 < nR; m0 += 16 * kLoadBatch) {
         double vb[kLoadBatch];
 #pragma unroll
@@ -913,7 +925,7 @@ __global__ __launch_bounds__(256) void k_radR_epi(
 #pragma unroll
         for (int b = 0; b < kLoadBatch; ++b) {
           const int mm = m0 + 16 * b;
-          if (mm < nR) dst[mm * kXLd] = okc ? vb[b] : 0.0;
+          if (mm < nR) dst[mm * kXLd] = okc ? (XT)vb[b] : (XT)0;
         }
       }
     }
@@ -926,14 +938,14 @@ __global__ __launch_bounds__(256) void k_radR_epi(
 #pragma unroll 1
   for (int le = 0; le < NE; ++le) {
     __syncthreads();
-    const double* Xl = X + (size_t)le * nR * kXLd;
+    const XT* Xl = X + (size_t)le * nR * kXLd;
     {
       const int tt = threadIdx.x & 15;
       for (int k = threadIdx.x >> 4; k < kp; k += 16) {
         double a = 0.0, b = 0.0;
         if (k < nh) {
-          a = Xl[k * kXLd + tt];
-          b = Xl[(nR - 1 - k) * kXLd + tt];
+          a = (double)Xl[k * kXLd + tt];
+          b = (double)Xl[(nR - 1 - k) * kXLd + tt];
         }
         F::put(SD, ps, tt * ld + k, a + b);
         F::put(SD, ps, RT * ld + tt * ld + k, a - b);
@@ -944,7 +956,7 @@ __global__ __launch_bounds__(256) void k_radR_epi(
       // epilogue operands of this lane's 8 outputs (rows a and n_R-1-a), loaded
       // before the contraction so their latency overlaps it
       // (addresses clamped into range; outputs outside it are skipped below)
-      HT hv[8], hw[8] = {};
+      HT hv[8];
       double dv[8], pv[8], vv[8][NE];
       const int ic = i < nr ? i : nr - 1;
 #pragma unroll
@@ -957,8 +969,9 @@ __global__ __launch_bounds__(256) void k_radR_epi(
           const int mm = side ? nR - 1 - a : a;
           const size_t pt = (size_t)n * plane + (size_t)mm * nr + ic;
           const size_t idx = (size_t)(o * NE + le) * ng * plane + pt;
-          hv[q] = h[idx];
-          if constexpr (TWO) hw[q] = h2[idx];
+          // with the r pass beside the angular one: h + T_r u, summed in h's precision
+          if constexpr (TWO) hv[q] = h[idx] + h2[idx];
+          else hv[q] = h[idx];
           if constexpr (!SPLIT) {
             dv[q] = D[(size_t)mm * nr + ic];
             pv[q] = first ? 0.0 : uprev[idx];
@@ -999,14 +1012,15 @@ __global__ __launch_bounds__(256) void k_radR_epi(
           const int q = 2 * v + side;
           const int mm = side ? nR - 1 - a : a;
           const size_t idx = (size_t)(o * NE + le) * ng * plane + (size_t)n * plane + (size_t)mm * nr + i;
-          double sacc = (side ? ys - yd : ys + yd) + (TWO ? (double)hv[q] + (double)hw[q] : (double)hv[q]);
+          double sacc = (side ? ys - yd : ys + yd) + (double)hv[q];
           if constexpr (SPLIT) {   // T_R u + h only; the potential and the recursion follow
             h[idx] = (HT)sacc;
             continue;
           }
-          const double ukv = Xl[mm * kXLd + t];
+          const double ukv = (double)Xl[mm * kXLd + t];
 #pragma unroll
-          for (int l2 = 0; l2 < NE; ++l2) sacc += vv[q][l2] * X[((size_t)l2 * nR + mm) * kXLd + t];
+          for (int l2 = 0; l2 < NE; ++l2)
+            sacc += vv[q][l2] * (double)X[((size_t)l2 * nR + mm) * kXLd + t];
           const double wv = (sacc - E0 * ukv) * inv_dE;
           const double dmp = dv[q];
           const double un = first ? dmp * wv : dmp * (2.0 * wv - dmp * pv[q]);

@@ -365,7 +365,8 @@ void choose_fast_path(Plan* P) {
   }
   if (P->nta == 0) return;
   P->ntr = 1;
-  P->lds_radR = (size_t)P->ne * P->nR * kXLd * sizeof(double) + (size_t)2 * 16 * ld_of(prec, kpR) * eb;
+  P->lds_radR = (size_t)P->ne * P->nR * kXLd * (prec == TDWP_FP64 ? sizeof(double) : sizeof(float)) +
+                (size_t)2 * 16 * ld_of(prec, kpR) * eb;
   if (P->lds_radr > kLdsMax || P->lds_ang > kLdsMax || P->lds_radR > kLdsMax) return;
   P->fast = true;
 }
