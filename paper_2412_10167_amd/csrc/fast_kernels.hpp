@@ -796,9 +796,15 @@ __global__ __launch_bounds__(256) void k_angr(AngArgs a) {
                               (const E*)a.PcT, a.ngk, a.psp, a.Br, a.BR, a.rot_cut, blockIdx.x);
 }
 // The angular pass (blocks 0 .. n_ang-1) and the r pass (the rest) in one launch:
-// neither reads what the other writes, so their memory latencies overlap.
+// neither reads what the other writes, so their memory latencies overlap.  With one
+// helicity the mixed forms ask for four waves per SIMD (the register allocator then
+// fits both bodies in 128 registers without spilling; the FP64 form would spill).
+template <int P, int MAXOM>
+constexpr int fused_waves() { return (P != kP64 && MAXOM <= 1) ? 4 : 1; }
+
 template <int P, int NT, int MAXOM>
-__global__ __launch_bounds__(256) void k_ang_radr(AngArgs a, RadrArgs r, int n_ang) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(fused_waves<P, MAXOM>())))
+void k_ang_radr(AngArgs a, RadrArgs r, int n_ang) {
   using E = typename Fmt<P>::E;
   using HT = typename HType<P>::T;
   if ((int)blockIdx.x < n_ang)
@@ -810,7 +816,8 @@ __global__ __launch_bounds__(256) void k_ang_radr(AngArgs a, RadrArgs r, int n_a
                        r.nlines, r.sa, (long)blockIdx.x - n_ang, (long)gridDim.x - n_ang);
 }
 template <int P, int NT, int MAXOM, int TPW>
-__global__ __launch_bounds__(256) void k_angr_radr(AngArgs a, RadrArgs r, int n_ang) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(fused_waves<P, MAXOM>())))
+void k_angr_radr(AngArgs a, RadrArgs r, int n_ang) {
   using E = typename Fmt<P>::E;
   using HT = typename HType<P>::T;
   if ((int)blockIdx.x < n_ang)
