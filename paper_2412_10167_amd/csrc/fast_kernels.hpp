@@ -874,7 +874,7 @@ void k_radR_epi(
     const PkDesc* __restrict__ pks,
     const int* __restrict__ blk_start, int n_pk, const typename Fmt<P>::E* __restrict__ Ts,
     const typename Fmt<P>::E* __restrict__ Td, int ldt, int pst, const double* __restrict__ V,
-    const double* __restrict__ D, int ng, int nR, int nr, double E0, double inv_dE,
+    const double* __restrict__ Dsep, int ng, int nR, int nr, double E0, double inv_dE,
     int first, double* __restrict__ normpart, size_t n_wg_total, int* __restrict__ counters,
     int norm_rows, int recorded) {
   using M = Mma<P>;
@@ -941,6 +941,7 @@ void k_radR_epi(
   const int MT = (nh + 15) >> 4;
   const int t = l & 15;
   const int i = i0 + t;
+  const double dr_i = Dsep[i < nr ? i : nr - 1];   // damping exp(-phi_r(r_i))
   double nsum = 0.0;
 #pragma unroll 1
   for (int le = 0; le < NE; ++le) {
@@ -980,7 +981,7 @@ void k_radR_epi(
           if constexpr (TWO) hv[q] = h[idx] + h2[idx];
           else hv[q] = h[idx];
           if constexpr (!SPLIT) {
-            dv[q] = D[(size_t)mm * nr + ic];
+            dv[q] = Dsep[nr + mm];   // damping exp(-phi_R(R)); times the r factor below
             pv[q] = first ? 0.0 : uprev[idx];
 #pragma unroll
             for (int l2 = 0; l2 < NE; ++l2) {
@@ -1029,7 +1030,7 @@ void k_radR_epi(
           for (int l2 = 0; l2 < NE; ++l2)
             sacc += vv[q][l2] * (double)X[((size_t)l2 * nR + mm) * kXLd + t];
           const double wv = (sacc - E0 * ukv) * inv_dE;
-          const double dmp = dv[q];
+          const double dmp = dv[q] * dr_i;
           const double un = first ? dmp * wv : dmp * (2.0 * wv - dmp * pv[q]);
           uprev[idx] = un;
           nsum += un * un;

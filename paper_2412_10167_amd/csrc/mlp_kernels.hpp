@@ -342,7 +342,7 @@ __global__ __launch_bounds__(256) void k_mlp_epi(
     const double* __restrict__ xg, double cB, double cC, int ng, int nR, int nr,
     const PkDesc* __restrict__ pks, int n_pk, const double* __restrict__ uk_all,
     double* __restrict__ uprev_all, const typename HType<P>::T* __restrict__ y_all,
-    const double* __restrict__ D, double E0, double inv_dE, int first,
+    const double* __restrict__ Dsep, double E0, double inv_dE, int first,
     double* __restrict__ normpart, size_t n_wg_total, int* __restrict__ counters,
     int norm_rows, int recorded) {
   constexpr int NPAIR = NE * (NE + 1) / 2;
@@ -415,7 +415,7 @@ __global__ __launch_bounds__(256) void k_mlp_epi(
       const long p = p0 + pl;
       const bool ok = p < n_pts;
       const long pc = ok ? p : n_pts - 1;
-      const double dmp = D[pc % plane];
+      const double dmp = Dsep[pc % nr] * Dsep[nr + (pc % plane) / nr];   // exp(-phi_r) exp(-phi_R)
       double V[NPAIR];
 #pragma unroll
       for (int q = 0; q < NPAIR; ++q) V[q] = (double)Vs[pl * 16 + q];

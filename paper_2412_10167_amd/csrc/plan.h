@@ -72,7 +72,7 @@ struct tdwp_plan_s {
   std::vector<PacketInfo> packets;
   int nr = 0, nR = 0, ng = 0, ne = 0, npair = 0;
   double mu = 0, m = 0, dr = 0, dR = 0, Lr = 0, LR = 0, r_wall = 0, R_wall = 0;
-  std::vector<double> r, R, x, w, Tr, TR, er, eR, Br, BR, D, arow, drow;
+  std::vector<double> r, R, x, w, Tr, TR, er, eR, Br, BR, D, Dsep, arow, drow;
   std::vector<double> Ptab;   // [omega 0..max_om][j 0..ng-1][n], zero rows for j < omega
   int max_om = 0;
   int m_inf = 0;
@@ -129,6 +129,7 @@ struct tdwp_plan_s {
   double* d_TR = nullptr;
   double* d_P = nullptr;
   double* d_D = nullptr;
+  double* d_Dsep = nullptr;   // damping factors [r (n_r), R (n_R)]
   double* d_Br = nullptr;
   double* d_BR = nullptr;
   double* d_arow = nullptr;

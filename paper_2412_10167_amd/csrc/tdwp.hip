@@ -148,7 +148,13 @@ int build_tables(Plan* P) {
   P->BR.resize(P->nR);
   for (int i = 0; i < P->nr; ++i) P->Br[i] = 1.0 / (2.0 * P->m * P->r[i] * P->r[i]);
   for (int i = 0; i < P->nR; ++i) P->BR[i] = 1.0 / (2.0 * P->mu * P->R[i] * P->R[i]);
-  // damping D(R, r) = exp(-phi_r(r) - phi_R(R))
+  // damping D(R, r) = exp(-phi_r(r) - phi_R(R)), and its two factors
+  // [exp(-phi_r(r_i)) ..., exp(-phi_R(R_m)) ...] for the matrix-core R pass
+  P->Dsep.resize((size_t)P->nr + P->nR);
+  for (int i = 0; i < P->nr; ++i)
+    P->Dsep[i] = std::exp(-absorb(P->r[i], c.abs_r_start, c.abs_r_strength, c.abs_r_power));
+  for (int mm = 0; mm < P->nR; ++mm)
+    P->Dsep[P->nr + mm] = std::exp(-absorb(P->R[mm], c.abs_R_start, c.abs_R_strength, c.abs_R_power));
   P->D.resize((size_t)P->nR * P->nr);
   for (int mm = 0; mm < P->nR; ++mm)
     for (int i = 0; i < P->nr; ++i)
@@ -574,6 +580,7 @@ int layout_and_allocate(Plan* P) {
   TRY(alloc_copy(P, &P->d_TR, P->TR));
   TRY(alloc_copy(P, &P->d_P, P->Ptab));
   TRY(alloc_copy(P, &P->d_D, P->D));
+  TRY(alloc_copy(P, &P->d_Dsep, P->Dsep));
   TRY(alloc_copy(P, &P->d_Br, P->Br));
   TRY(alloc_copy(P, &P->d_rg, P->r));
   TRY(alloc_copy(P, &P->d_Rg, P->R));
@@ -1031,7 +1038,7 @@ int enqueue_step(Plan* P, int cur, int first, int rec, Timing* T) {
       hipLaunchKernelGGL(kern, dim3(radial_blocks(P, P->blocks_radR)), dim3(256), P->lds_radR,
                          P->stream, uk, uo, h, (const HT*)h2, pkd, P->d_blk_radR, np,
                          (const E*)P->d_TRsF,
-                         (const E*)P->d_TRdF, P->nRhk, P->nRhk * P->nRhk, P->d_V, P->d_D, ng, nR,
+                         (const E*)P->d_TRdF, P->nRhk, P->nRhk * P->nRhk, P->d_V, P->d_Dsep, ng, nR,
                          nr, P->E0, 1.0 / P->dE, first, P->d_normpart, P->n_wg_total,
                          P->d_counters, kNormChunk, rec);
     };
@@ -1039,7 +1046,7 @@ int enqueue_step(Plan* P, int cur, int first, int rec, Timing* T) {
     auto epi = [&](auto kern) {
       hipLaunchKernelGGL(kern, dim3(P->mlp_grid), dim3(256), mlp_epi_lds(np), P->stream,
                          mlp_net(P), P->d_rg, P->d_Rg, P->d_xg, P->cfg.mass_C / mbc,
-                         P->cfg.mass_B / mbc, ng, nR, nr, pkd, np, uk, uo, (const HT*)h, P->d_D,
+                         P->cfg.mass_B / mbc, ng, nR, nr, pkd, np, uk, uo, (const HT*)h, P->d_Dsep,
                          P->E0, 1.0 / P->dE, first, P->d_normpart, P->n_wg_total,
                          P->d_counters, kNormChunk, rec);
     };
@@ -1055,7 +1062,7 @@ int enqueue_step(Plan* P, int cur, int first, int rec, Timing* T) {
                          P->stream, uk, uo,
                          h, (const HT*)h2, pkd, P->d_blk_radR, np, (const E*)P->d_TRsF,
                          (const E*)P->d_TRdF,
-                         P->nRhk, P->nRhk * P->nRhk, P->d_V, P->d_D, ng, nR, nr, P->E0,
+                         P->nRhk, P->nRhk * P->nRhk, P->d_V, P->d_Dsep, ng, nR, nr, P->E0,
                          1.0 / P->dE, first, P->d_normpart, P->n_wg_total, P->d_counters,
                          kNormChunk, rec);
     };
