@@ -873,7 +873,8 @@ void k_radR_epi(
     typename HType<P>::T* __restrict__ h_all, const typename HType<P>::T* __restrict__ h2_all,
     const PkDesc* __restrict__ pks,
     const int* __restrict__ blk_start, int n_pk, const typename Fmt<P>::E* __restrict__ Ts,
-    const typename Fmt<P>::E* __restrict__ Td, int ldt, int pst, const double* __restrict__ V,
+    const typename Fmt<P>::E* __restrict__ Td, int ldt, int pst,
+    const typename HType<P>::T* __restrict__ V,
     const double* __restrict__ Dsep, int ng, int nR, int nr, double E0, double inv_dE,
     int first, double* __restrict__ normpart, size_t n_wg_total, int* __restrict__ counters,
     int norm_rows, int recorded) {
@@ -965,7 +966,8 @@ void k_radR_epi(
       // before the contraction so their latency overlaps it
       // (addresses clamped into range; outputs outside it are skipped below)
       HT hv[8];
-      double dv[8], pv[8], vv[8][NE];
+      double dv[8], pv[8];
+      HT vv[8][NE];   // the potential in h's precision
       const int ic = i < nr ? i : nr - 1;
 #pragma unroll
       for (int v = 0; v < 4; ++v)
@@ -1028,7 +1030,7 @@ void k_radR_epi(
           const double ukv = (double)Xl[mm * kXLd + t];
 #pragma unroll
           for (int l2 = 0; l2 < NE; ++l2)
-            sacc += vv[q][l2] * (double)X[((size_t)l2 * nR + mm) * kXLd + t];
+            sacc += (double)vv[q][l2] * (double)X[((size_t)l2 * nR + mm) * kXLd + t];
           const double wv = (sacc - E0 * ukv) * inv_dE;
           const double dmp = dv[q] * dr_i;
           const double un = first ? dmp * wv : dmp * (2.0 * wv - dmp * pv[q]);
@@ -1048,6 +1050,13 @@ void k_radR_epi(
   if constexpr (!SPLIT) {
     if (threadIdx.x == 0) advance_if_last(counters, recorded);
   }
+}
+
+// FP32 copy of an FP64 array (the potential table read by the mixed forms' R pass).
+__global__ void k_to_f32(const double* __restrict__ src, float* __restrict__ dst, size_t n) {
+  for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
+       q += (size_t)gridDim.x * blockDim.x)
+    dst[q] = (float)src[q];
 }
 
 // Converts an FP64 operator table to compute format (planes ps elements apart).

@@ -130,6 +130,7 @@ struct tdwp_plan_s {
   double* d_P = nullptr;
   double* d_D = nullptr;
   double* d_Dsep = nullptr;   // damping factors [r (n_r), R (n_R)]
+  float* d_Vf = nullptr;      // FP32 copy of the potential table (mixed forms)
   double* d_Br = nullptr;
   double* d_BR = nullptr;
   double* d_arow = nullptr;

@@ -576,6 +576,8 @@ int layout_and_allocate(Plan* P) {
   TRY(dev_alloc(P, (void**)&P->d_h, P->n_total * sizeof(double)));
   if (P->fast) TRY(dev_alloc(P, (void**)&P->d_h2, P->n_total * sizeof(double)));
   TRY(dev_alloc(P, (void**)&P->d_V, (size_t)P->npair * ng * nR * nr * sizeof(double)));
+  if (P->fast && P->cfg.precision != TDWP_FP64)
+    TRY(dev_alloc(P, (void**)&P->d_Vf, (size_t)P->npair * ng * nR * nr * sizeof(float)));
   TRY(alloc_copy(P, &P->d_Tr, P->Tr));
   TRY(alloc_copy(P, &P->d_TR, P->TR));
   TRY(alloc_copy(P, &P->d_P, P->Ptab));
@@ -993,6 +995,8 @@ int enqueue_step(Plan* P, int cur, int first, int rec, Timing* T) {
   const unsigned nblk_r = radial_blocks(P, (nlines + kRadrLines - 1) / kRadrLines);
   const bool fuse = P->fuse_r;
   HT* h2 = fuse ? reinterpret_cast<HT*>(P->d_h2) : nullptr;
+  // the potential table in h's precision (an FP32 copy in the mixed forms)
+  const HT* vtab = reinterpret_cast<const HT*>(PR == kP64 ? (const void*)P->d_V : (const void*)P->d_Vf);
   TRY(timed_begin(P, T));
   {
     AngArgs aa{uk, h, pkd, P->d_blk_ang, np, ne, ng, nR, nr, nullptr, P->ngr, (int)P->Pf.size(),
@@ -1038,7 +1042,7 @@ int enqueue_step(Plan* P, int cur, int first, int rec, Timing* T) {
       hipLaunchKernelGGL(kern, dim3(radial_blocks(P, P->blocks_radR)), dim3(256), P->lds_radR,
                          P->stream, uk, uo, h, (const HT*)h2, pkd, P->d_blk_radR, np,
                          (const E*)P->d_TRsF,
-                         (const E*)P->d_TRdF, P->nRhk, P->nRhk * P->nRhk, P->d_V, P->d_Dsep, ng, nR,
+                         (const E*)P->d_TRdF, P->nRhk, P->nRhk * P->nRhk, vtab, P->d_Dsep, ng, nR,
                          nr, P->E0, 1.0 / P->dE, first, P->d_normpart, P->n_wg_total,
                          P->d_counters, kNormChunk, rec);
     };
@@ -1062,7 +1066,7 @@ int enqueue_step(Plan* P, int cur, int first, int rec, Timing* T) {
                          P->stream, uk, uo,
                          h, (const HT*)h2, pkd, P->d_blk_radR, np, (const E*)P->d_TRsF,
                          (const E*)P->d_TRdF,
-                         P->nRhk, P->nRhk * P->nRhk, P->d_V, P->d_Dsep, ng, nR, nr, P->E0,
+                         P->nRhk, P->nRhk * P->nRhk, vtab, P->d_Dsep, ng, nR, nr, P->E0,
                          1.0 / P->dE, first, P->d_normpart, P->n_wg_total, P->d_counters,
                          kNormChunk, rec);
     };
@@ -1403,6 +1407,10 @@ int tdwp_set_potential(tdwp_plan_t p, int mode, const double* v, size_t n_values
   const size_t plane = (size_t)p->ng * p->nR * p->nr;
   if (n_values != (size_t)p->npair * plane) return TDWP_EINVAL;
   HIP_TRY(hipMemcpyAsync(p->d_V, v, n_values * sizeof(double), hipMemcpyHostToDevice, p->stream));
+  if (p->d_Vf) {
+    hipLaunchKernelGGL(k_to_f32, dim3(1024), dim3(256), 0, p->stream, p->d_V, p->d_Vf, n_values);
+    HIP_TRY(hipGetLastError());
+  }
   HIP_TRY(hipStreamSynchronize(p->stream));
   if (!p->bounds_given) TRY(bounds_from_table(p, v));
   drop_graphs(p);
