@@ -246,9 +246,11 @@ enum tdwp_option {
   TDWP_OPT_ANG_KERNEL = 3,  /* angular kernel: 0 (default) automatic, 1 helicity mixing
                                through LDS, 2 helicity mixing in registers; a kernel that
                                does not fit the plan's shapes is refused with TDWP_EINVAL  */
-  TDWP_OPT_FUSE_R = 4       /* 1 (default): the angular pass and the r pass in one launch
+  TDWP_OPT_FUSE_R = 4,      /* 1 (default): the angular pass and the r pass in one launch
                                (T_r u into a buffer of its own); 0: two launches, the r
                                pass adding T_r u to the angular terms                      */
+  TDWP_OPT_ANG_XCD = 5      /* 1: angular blocks dealt to the XCDs in contiguous runs;
+                               0 (default): in launch order                                */
 };
 enum tdwp_stat {
   TDWP_STAT_GRAPH_STEPS = 0,        /* steps taken so far by graph replay      */

@@ -48,6 +48,17 @@ struct PkDesc {
 };
 
 // Index p with start[p] <= b < start[p + 1] (start has n + 1 entries).
+// Workgroups are dealt to the eight XCDs of the device in turn.  xcd_order gives
+// each XCD a contiguous run of the n blocks (a bijection on the first 8 floor(n/8),
+// the rest unchanged), so that neighbouring column tiles, which share cache lines
+// of the FP32 arrays, are read through the same L2 (the R pass, whose 16-column
+// tiles read h and V in 64-byte runs; for the angular pass it helps some shapes
+// and not others, so it is a choice of the autotuner there).
+__device__ __forceinline__ int xcd_order(int b, int n) {
+  const int n8 = n & ~7;
+  return b < n8 ? (b & 7) * (n8 >> 3) + (b >> 3) : b;
+}
+
 __device__ __forceinline__ int find_packet(const int* __restrict__ start, int n, int b) {
   int lo = 0, hi = n - 1;
   while (lo < hi) {
@@ -445,7 +456,8 @@ __device__ __forceinline__ void ang_blk(const double* __restrict__ u_all,
                                         const typename Fmt<P>::E* __restrict__ Pc,
                                         const typename Fmt<P>::E* __restrict__ PcT, int ngk,
                                         int psp, const double* __restrict__ Br,
-                                        const double* __restrict__ BR, double rot_cut, int bid) {
+                                        const double* __restrict__ BR, double rot_cut, int bid,
+                                        int xcd) {
   using M = Mma<P>;
   using F = Fmt<P>;
   using E = typename F::E;
@@ -453,6 +465,7 @@ __device__ __forceinline__ void ang_blk(const double* __restrict__ u_all,
   constexpr int RT = 16 * NT;
   constexpr int RES = kAngMaxAcc / NT;
   extern __shared__ __align__(16) double lds[];
+  if (xcd) bid = xcd_order(bid, blk_start[n_pk]);
   const int pk = find_packet(blk_start, n_pk, bid);
   const int local = bid - blk_start[pk];
   const PkDesc d = pks[pk];
@@ -585,7 +598,8 @@ __device__ __forceinline__ void angr_blk(const double* __restrict__ u_all,
                                          const typename Fmt<P>::E* __restrict__ Pf, int ngr,
                                          int psf, const typename Fmt<P>::E* __restrict__ PcT,
                                          int ngk, int psp, const double* __restrict__ Br,
-                                         const double* __restrict__ BR, double rot_cut, int bid) {
+                                         const double* __restrict__ BR, double rot_cut, int bid,
+                                         int xcd) {
   using M = Mma<P>;
   using F = Fmt<P>;
   using E = typename F::E;
@@ -593,6 +607,7 @@ __device__ __forceinline__ void angr_blk(const double* __restrict__ u_all,
   constexpr int RT = 16 * NT;
   static_assert(TPW * MAXOM <= 16, "accumulators per wave");
   extern __shared__ __align__(16) double lds[];
+  if (xcd) bid = xcd_order(bid, blk_start[n_pk]);
   const int pk = find_packet(blk_start, n_pk, bid);
   const int local = bid - blk_start[pk];
   const PkDesc d = pks[pk];
@@ -770,6 +785,7 @@ struct AngArgs {
   const double* Br;
   const double* BR;
   double rot_cut;
+  int xcd;   // blocks in XCD order (xcd_order)
 };
 struct RadrArgs {
   const double* u;
@@ -786,14 +802,14 @@ __global__ __launch_bounds__(256) void k_ang(AngArgs a) {
   using E = typename Fmt<P>::E;
   ang_blk<P, NT, MAXOM>(a.u_all, (typename HType<P>::T*)a.h_all, a.pks, a.blk_start, a.n_pk, a.ne,
                         a.ng, a.nR, a.nr, (const E*)a.Pfwd, (const E*)a.PcT, a.ngk, a.psp, a.Br,
-                        a.BR, a.rot_cut, blockIdx.x);
+                        a.BR, a.rot_cut, blockIdx.x, a.xcd);
 }
 template <int P, int NT, int MAXOM, int TPW>
 __global__ __launch_bounds__(256) void k_angr(AngArgs a) {
   using E = typename Fmt<P>::E;
   angr_blk<P, NT, MAXOM, TPW>(a.u_all, (typename HType<P>::T*)a.h_all, a.pks, a.blk_start, a.n_pk,
                               a.ne, a.ng, a.nR, a.nr, (const E*)a.Pfwd, a.ngr, a.psf,
-                              (const E*)a.PcT, a.ngk, a.psp, a.Br, a.BR, a.rot_cut, blockIdx.x);
+                              (const E*)a.PcT, a.ngk, a.psp, a.Br, a.BR, a.rot_cut, blockIdx.x, a.xcd);
 }
 // The angular pass (blocks 0 .. n_ang-1) and the r pass (the rest) in one launch:
 // neither reads what the other writes, so their memory latencies overlap.  With one
@@ -810,7 +826,7 @@ void k_ang_radr(AngArgs a, RadrArgs r, int n_ang) {
   if ((int)blockIdx.x < n_ang)
     ang_blk<P, NT, MAXOM>(a.u_all, (HT*)a.h_all, a.pks, a.blk_start, a.n_pk, a.ne, a.ng, a.nR,
                           a.nr, (const E*)a.Pfwd, (const E*)a.PcT, a.ngk, a.psp, a.Br, a.BR,
-                          a.rot_cut, blockIdx.x);
+                          a.rot_cut, blockIdx.x, a.xcd);
   else
     radr_blk<P, false>(r.u, (HT*)r.h2, (const E*)r.Ts, (const E*)r.Td, r.ldt, r.pst, r.nr,
                        r.nlines, r.sa, (long)blockIdx.x - n_ang, (long)gridDim.x - n_ang);
@@ -823,7 +839,7 @@ void k_angr_radr(AngArgs a, RadrArgs r, int n_ang) {
   if ((int)blockIdx.x < n_ang)
     angr_blk<P, NT, MAXOM, TPW>(a.u_all, (HT*)a.h_all, a.pks, a.blk_start, a.n_pk, a.ne, a.ng,
                                 a.nR, a.nr, (const E*)a.Pfwd, a.ngr, a.psf, (const E*)a.PcT, a.ngk,
-                                a.psp, a.Br, a.BR, a.rot_cut, blockIdx.x);
+                                a.psp, a.Br, a.BR, a.rot_cut, blockIdx.x, a.xcd);
   else
     radr_blk<P, false>(r.u, (HT*)r.h2, (const E*)r.Ts, (const E*)r.Td, r.ldt, r.pst, r.nr,
                        r.nlines, r.sa, (long)blockIdx.x - n_ang, (long)gridDim.x - n_ang);
@@ -894,8 +910,9 @@ void k_radR_epi(
   // a workgroup takes blocks blockIdx.x, blockIdx.x + gridDim.x, ...
   for (int blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
   __syncthreads();   // the previous block's tile and partials have been read
-  const int pk = find_packet(blk_start, n_pk, blk);
-  const int local = blk - blk_start[pk];
+  const int bx = xcd_order(blk, nblk);
+  const int pk = find_packet(blk_start, n_pk, bx);
+  const int local = bx - blk_start[pk];
   const PkDesc dsc = pks[pk];
   const double* __restrict__ uk = uk_all + dsc.off;
   double* __restrict__ uprev = uprev_all + dsc.off;

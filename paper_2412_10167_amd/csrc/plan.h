@@ -93,6 +93,7 @@ struct tdwp_plan_s {
   long radial_grid = 0;      // workgroups of the two radial passes (0: one per block)
   int ang_pref = 0;          // angular kernel: 0 automatic, 1 k_ang, 2 k_angr
   bool fuse_r = true;        // angular and r passes in one launch (T_r u into d_h2)
+  bool ang_xcd = false;      // angular blocks in XCD order
   int nrhk = 0, nRhk = 0, ngk = 0, ngr = 0;
   size_t lds_radr = 0, lds_ang = 0, lds_radR = 0;
   std::vector<double> Trs, Trd, TRs, TRd, Pc;

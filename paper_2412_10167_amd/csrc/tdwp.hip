@@ -1000,7 +1000,8 @@ int enqueue_step(Plan* P, int cur, int first, int rec, Timing* T) {
   TRY(timed_begin(P, T));
   {
     AngArgs aa{uk, h, pkd, P->d_blk_ang, np, ne, ng, nR, nr, nullptr, P->ngr, (int)P->Pf.size(),
-               P->d_PcTF, P->ngk, (int)P->Pc.size(), P->d_Br, P->d_BR, P->cfg.rot_cut};
+               P->d_PcTF, P->ngk, (int)P->Pc.size(), P->d_Br, P->d_BR, P->cfg.rot_cut,
+               P->ang_xcd ? 1 : 0};
     RadrArgs ra{uk, h2, P->d_TrsF, P->d_TrdF, P->nrhk, P->nrhk * P->nrhk, nr, nlines, sa};
     auto plain = [&](auto kern) {
       hipLaunchKernelGGL(kern, dim3(P->blocks_ang), dim3(256), P->lds_ang_max, P->stream, aa);
@@ -1336,12 +1337,13 @@ int tdwp_plan(const tdwp_config* cfg, tdwp_plan_t* out) {
     return st;
   }
   if (P->fast) {
-    // cached choice: 100 * (r pass fused) + 10 * kernel + tile (kernel 1: LDS
-    // mixing, 2: register mixing)
+    // cached choice: 1000 * (angular blocks in XCD order) + 100 * (r pass fused) +
+    // 10 * kernel + tile (kernel 1: LDS mixing, 2: register mixing)
     const int c = cached_tile(P);
-    const int nt = c % 10, kern = (c / 10) % 10, fz = c / 100;
-    if ((nt == 1 || nt == 2 || nt == 4) && kern <= 2 && fz <= 1) {
+    const int nt = c % 10, kern = (c / 10) % 10, fz = (c / 100) % 10, xo = c / 1000;
+    if ((nt == 1 || nt == 2 || nt == 4) && kern <= 2 && fz <= 1 && xo <= 1) {
       P->fuse_r = fz == 1;
+      P->ang_xcd = xo == 1;
       const int keep = P->ang_pref;
       P->ang_pref = kern;
       if (set_ang_tiles(P, nt) != TDWP_OK) {
@@ -1676,14 +1678,16 @@ int tdwp_autotune(tdwp_plan_t p, int steps, char* report, size_t report_len) {
   HIP_TRY(hipMemsetAsync(p->d_u[1], 0, p->n_total * sizeof(double), p->stream));
   std::string rep;
   const int keep_pref = p->ang_pref, keep_nt = p->nta;
-  const bool keep_fuse = p->fuse_r;
-  int best_k = -1, best_nt = keep_nt, best_f = keep_fuse ? 1 : 0;
+  const bool keep_fuse = p->fuse_r, keep_xcd = p->ang_xcd;
+  int best_k = -1, best_nt = keep_nt, best_f = keep_fuse ? 1 : 0, best_x = keep_xcd ? 1 : 0;
   double best_us = 1e300;
   // r pass beside the angular pass or after it x angular kernel (2: helicity mixing
   // in registers, 1: through LDS) x tile width; the angular and r passes are timed
+  for (int xo : {0, 1})
   for (int fz : {1, 0})
   for (int kern : {2, 1})
     for (int nt : {4, 2, 1}) {
+      p->ang_xcd = xo == 1;
       p->fuse_r = fz == 1;
       p->ang_pref = kern;
       if (set_ang_tiles(p, nt) != TDWP_OK) continue;
@@ -1703,19 +1707,21 @@ int tdwp_autotune(tdwp_plan_t p, int steps, char* report, size_t report_len) {
         (void)hipEventDestroy(T.ev[1]);
         p->ang_pref = keep_pref;
         p->fuse_r = keep_fuse;
+        p->ang_xcd = keep_xcd;
         (void)set_ang_tiles(p, keep_nt);
         return st;
       }
       const double us = 1000.0 * (T.ms[0] + T.ms[4]) / std::max<long>(T.calls[0], 1);
       char buf[64];
-      std::snprintf(buf, sizeof buf, "%sf%d_k%d_nt%d:%.1fus", rep.empty() ? "" : ";", fz, kern, nt,
-                    us);
+      std::snprintf(buf, sizeof buf, "%sx%d_f%d_k%d_nt%d:%.1fus", rep.empty() ? "" : ";", xo, fz,
+                    kern, nt, us);
       rep += buf;
       if (us < best_us) {
         best_us = us;
         best_k = kern;
         best_nt = nt;
         best_f = fz;
+        best_x = xo;
       }
     }
   (void)hipEventDestroy(T.ev[0]);
@@ -1723,18 +1729,20 @@ int tdwp_autotune(tdwp_plan_t p, int steps, char* report, size_t report_len) {
   if (best_k < 0) {   // no variant fits: keep the plan's choice
     p->ang_pref = keep_pref;
     p->fuse_r = keep_fuse;
+    p->ang_xcd = keep_xcd;
     TRY(set_ang_tiles(p, keep_nt));
   } else {
     p->ang_pref = best_k;
     p->fuse_r = best_f == 1;
+    p->ang_xcd = best_x == 1;
     TRY(set_ang_tiles(p, best_nt));
-    store_tile(p, 100 * best_f + 10 * best_k + best_nt);
+    store_tile(p, 1000 * best_x + 100 * best_f + 10 * best_k + best_nt);
   }
   drop_graphs(p);
   reset_propagation(p);
   if (report && report_len) {
-    rep += ";chosen=f" + std::to_string(p->fuse_r ? 1 : 0) + "_k" + std::to_string(p->ang_regs ? 2 : 1) +
-           "_nt" + std::to_string(p->nta);
+    rep += ";chosen=x" + std::to_string(p->ang_xcd ? 1 : 0) + "_f" + std::to_string(p->fuse_r ? 1 : 0) +
+           "_k" + std::to_string(p->ang_regs ? 2 : 1) + "_nt" + std::to_string(p->nta);
     std::strncpy(report, rep.c_str(), report_len - 1);
     report[report_len - 1] = 0;
   }
@@ -1767,6 +1775,11 @@ int tdwp_set_option(tdwp_plan_t p, int option, long value) {
       drop_graphs(p);
       return TDWP_OK;
     }
+    case TDWP_OPT_ANG_XCD:
+      if (value != 0 && value != 1) return TDWP_EINVAL;
+      p->ang_xcd = value != 0;
+      drop_graphs(p);
+      return TDWP_OK;
     case TDWP_OPT_FUSE_R:
       if (value != 0 && value != 1) return TDWP_EINVAL;
       p->fuse_r = value != 0;

@@ -19,7 +19,8 @@ EXPORTED_SYMBOLS = (
     "tdwp_mlp_gradient", "tdwp_mlp_eval", "tdwp_mlp_grid", "tdwp_autotune",
     "tdwp_set_option", "tdwp_get_stat",
 )
-OPTIONS = {"graphs": 0, "ang_tile": 1, "radial_grid": 2, "ang_kernel": 3, "fuse_r": 4}
+OPTIONS = {"graphs": 0, "ang_tile": 1, "radial_grid": 2, "ang_kernel": 3, "fuse_r": 4,
+           "ang_xcd": 5}
 STATS = {"graph_steps": 0, "ang_tile": 1, "matrix_core_path": 2, "ang_kernel": 3, "fuse_r": 4}
 
 
@@ -326,8 +327,8 @@ class Plan:
     def autotune(self, steps=5):
         """Times the tile variants of the step kernels and keeps the fastest (call
         before setting packets).  Returns the report text."""
-        buf = ctypes.create_string_buffer(512)
-        _check(self.lib.tdwp_autotune(self.handle, steps, buf, 512), "tdwp_autotune")
+        buf = ctypes.create_string_buffer(4096)
+        _check(self.lib.tdwp_autotune(self.handle, steps, buf, 4096), "tdwp_autotune")
         return buf.value.decode()
 
     def mlp_grid(self):

@@ -368,6 +368,7 @@ def test_angular_kernels(kernel, fuse):
         plan, _ = problem.build(spec)
         plan.set_option("ang_kernel", kernel)
         plan.set_option("fuse_r", fuse)
+        plan.set_option("ang_xcd", fuse)   # both block orders of the angular pass
         assert plan.stat("ang_kernel") == kernel and plan.stat("fuse_r") == fuse
         K = 40
         plan.propagate(K)
