@@ -51,9 +51,9 @@ def kernel_model(spec, name, precision, fused=False):
     hb = 8 if precision == "fp64" else 4
     fp64 = precision == "fp64"
     if name == "radial_R_epilogue":
-        # T_R split: nR flops per value; bytes: u_k, h, u_{k-1}, V (shared by the
-        # helicity blocks of a point), u_{k+1}
-        flops, byts = values * nR, values * (8 + hb + 8 + 8 * ne * (ne + 1) / 2 / (n_blk * ne) + 8)
+        # T_R split: nR flops per value; bytes: u_k, h, u_{k-1}, V (in h's
+        # precision, shared by the helicity blocks of a point), u_{k+1}
+        flops, byts = values * nR, values * (8 + hb + 8 + hb * ne * (ne + 1) / 2 / (n_blk * ne) + 8)
         if fused:
             byts += values * hb
     elif name == "radial_r" and not fused:
