@@ -251,7 +251,7 @@ def main():
                     help="skip timing the plain FP64 form beside a mixed form")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-steps", type=int, default=50)
-    ap.add_argument("--autotune", type=int, default=3,
+    ap.add_argument("--autotune", type=int, default=5,
                     help="steps per tile variant timed by the library's autotuner (0: off)")
     ap.add_argument("--workload", type=int, default=2,
                     help="workload number 1..5 (default 2: J=0 256x192x80)")

@@ -230,8 +230,10 @@ int tdwp_get_packet(tdwp_plan_t p, int unit, int slot, int which, double* out);
 int tdwp_state_to_state(tdwp_plan_t p, int unit, int slot, int n_ch, const tdwp_channel* ch,
                         const double* chi, double* p_inel, double* p_reac);
 
-/* Chooses tile shapes of the step kernels by timing each feasible variant for
- * `steps` steps on this plan's shapes, and keeps the fastest.  Call after the
+/* Chooses the kernel variants of a step (angular and r passes in one launch or
+ * two, angular kernel, its tile width, its block order) by timing the kernels
+ * of `steps` whole steps for each feasible combination on this plan's shapes,
+ * and keeps the fastest.  Call after the
  * potential and before any initial packet (the packet buffers are used as
  * scratch).  With TDWP_TUNE_CACHE naming a file, the choice is appended to it
  * and later plans of the same shapes start from it.  report (may be NULL)

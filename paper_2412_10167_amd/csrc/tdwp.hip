@@ -1682,7 +1682,7 @@ int tdwp_autotune(tdwp_plan_t p, int steps, char* report, size_t report_len) {
   int best_k = -1, best_nt = keep_nt, best_f = keep_fuse ? 1 : 0, best_x = keep_xcd ? 1 : 0;
   double best_us = 1e300;
   // r pass beside the angular pass or after it x angular kernel (2: helicity mixing
-  // in registers, 1: through LDS) x tile width; the angular and r passes are timed
+  // in registers, 1: through LDS) x tile width; the kernels of whole steps are timed
   for (int xo : {0, 1})
   for (int fz : {1, 0})
   for (int kern : {2, 1})
@@ -1695,7 +1695,7 @@ int tdwp_autotune(tdwp_plan_t p, int steps, char* report, size_t report_len) {
       int st = sync_counters(p);
       for (int s2 = 0; s2 < steps + 1 && st == TDWP_OK; ++s2) {   // the first step warms up
         if (s2 <= 1)
-          for (int q : {0, 4}) {
+          for (int q : {0, 1, 4}) {
             T.ms[q] = 0.0;
             T.calls[q] = 0;
           }
@@ -1711,7 +1711,8 @@ int tdwp_autotune(tdwp_plan_t p, int steps, char* report, size_t report_len) {
         (void)set_ang_tiles(p, keep_nt);
         return st;
       }
-      const double us = 1000.0 * (T.ms[0] + T.ms[4]) / std::max<long>(T.calls[0], 1);
+      // the whole step: the shared launch also changes what the R pass reads
+      const double us = 1000.0 * (T.ms[0] + T.ms[1] + T.ms[4]) / std::max<long>(T.calls[0], 1);
       char buf[64];
       std::snprintf(buf, sizeof buf, "%sx%d_f%d_k%d_nt%d:%.1fus", rep.empty() ? "" : ";", xo, fz,
                     kern, nt, us);
