@@ -406,3 +406,18 @@ def test_autotune_then_parity():
     op, ref = oracle_packets(spec, K, keep=(K,))
     assert rel_err(plan.get_packet(0, 0, 0), ref[(0, 0)][0]["vectors"][K]) < PKT_TOL
     plan.close()
+
+
+def test_step_variant_options_are_checked():
+    banner("launch-form and block-order options: values checked, state reported")
+    from paper_2412_10167_amd.tdwp import TdwpError
+    problem = _problem()
+    plan, _ = problem.build(small_variant(1, n_R=24, n_r=20, n_gamma=10))
+    for name in ("fuse_r", "ang_xcd"):
+        for bad in (-1, 2):
+            with pytest.raises(TdwpError):
+                plan.set_option(name, bad)
+    for fuse in (0, 1):
+        plan.set_option("fuse_r", fuse)
+        assert plan.stat("fuse_r") == fuse
+    plan.close()
