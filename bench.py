@@ -197,7 +197,7 @@ def mlp_bench(args, torch, problem, config):
         "data": "synthetic",
         "config": {"workload": WORKLOAD_NAMES.get(wl, spec["name"]), "grid_values": values,
                    "table_steps_per_s": round(r_table, 2),
-                   "table_bytes_per_step": int(vtab.size * 8),
+                   "table_bytes_per_step": int(vtab.size * (8 if args.precision == "fp64" else 4)),   # the R pass reads the table at h's width
                    "network_flops_per_step": int(n_pts * 2 * (3 * 128 + 2 * 128 * 128 + 128 * n_pair)),
                    "training": {"samples": int(idx.size), "epochs": args.mlp_epochs,
                                 "batch": args.mlp_batch, "lr": args.mlp_lr,
