@@ -849,7 +849,7 @@ void k_angr_radr(AngArgs a, RadrArgs r, int n_ang) {
 // (SPLIT: only y = T_R u + h is formed and stored in h's place; the learned-potential
 // pass k_mlp_epi adds the potential and finishes the step.)
 // One workgroup per (r tile of 16 columns, slab (omega, gamma)) of one packet, all
-// NE electronic states.  The raw FP64 tile X[elec][R][t] stays in LDS for the
+// NE electronic states.  The raw tile X[elec][R][t] of u_k stays in LDS for the
 // epilogue; per elec the sum/difference operand (rows t, contraction over R) is
 // built in compute format, and each M-tile work item finishes rows a and n_R-1-a
 // from its accumulators.  Global loads are issued in independent batches (the
@@ -869,7 +869,7 @@ __device__ __forceinline__ void advance_if_last(int* counters, int recorded) {
     counters[2] = 0;
   }
 }
-// Row stride (doubles) of the FP64 tile (padding it to 18, 20 or 24 measured no
+// Row stride (entries) of the u_k tile (padding it to 18, 20 or 24 measured no
 // faster while it costs occupancy).
 constexpr int kXLd = 16;
 
