@@ -66,15 +66,18 @@ def test_config1_probabilities_per_precision(precision, config1_oracle):
     assert dr < tol and di < tol
 
 
+@pytest.mark.parametrize("fuse", [1, 0])
 @pytest.mark.parametrize("precision", ["fp32", "bf16x3", "fp16x3"])
-def test_coriolis_two_state_packet_per_precision(precision):
+def test_coriolis_two_state_packet_per_precision(precision, fuse):
     from paper_2412_10167_amd import problem
     s = small_variant(3, n_R=22, n_r=18, n_gamma=14)
     s["units"] = [dict(J=5, parity=1, omega_max=3, n_packets=1)]
     s["packets"] = [dict(s["packets"][0], omega0=1, j0=1)]
     K = 60
-    print(f"\n[case] J=5 Omega 1..3 2 states, {precision}", flush=True)
+    print(f"\n[case] J=5 Omega 1..3 2 states, {precision}, r pass "
+          f"{'in the angular launch' if fuse else 'after it'}", flush=True)
     plan, _ = problem.build(s, precision=precision)
+    plan.set_option("fuse_r", fuse)
     plan.propagate(K)
     op, run, _ = _oracle(s, K)
     du = np.max(np.abs(plan.get_packet(0, 0, 0) - run["vectors"][K])) / np.max(np.abs(run["vectors"][K]))
