@@ -240,6 +240,76 @@ def cpu_baseline(spec, budget_s=15.0):
                        f"(H application, recursion and damping; no slices) in {dt:.1f} s")
 
 
+def partial_waves_bench(args):
+    """Partial-wave sums on the batched workload's output shape (host functions of
+    the library): a fitted B per computed J, the cumulative probability over
+    J = 0..40 from the 21 computed J, and the cross section.  The probabilities
+    are seeded synthetic curves of that shape; the oracle runs the same sums."""
+    import numpy as np
+    from paper_2412_10167_amd import cross_section, cumulative_probability, fit_jshift_b
+    from workloads import ev
+    from workloads.partial_waves import batch_shape, probability_curves
+
+    s = batch_shape(n_f=args.pw_final_states)
+    J, e, jmin = s["J_calc"], s["energies"], s["fam_jmin"]
+    p = probability_curves(len(J), s["n_fam"], s["n_f"], e, 2024, fam_jmin=jmin, J_calc=J)
+    mA, mB, mC = s["masses"]
+    mu = mA * (mB + mC) / (mA + mB + mC)
+    B_max = ev(5e-3)
+    fam_total = p[:, 0].sum(axis=1)            # Omega0 = 0 family, summed over final states
+
+    def fits():
+        B = [fit_jshift_b(fam_total[c], fam_total[c + 1], e, J[c], J[c + 1], B_max)
+             for c in range(len(J) - 1)]
+        return np.array(B + [B[-1]])
+
+    def sums(B):
+        C = cumulative_probability(J, B, p, e, s["J_max"], fam_jmin=jmin)
+        return cross_section(C, e, mu, 2)
+
+    def rate(fn, budget):
+        fn()
+        t0, n = time.perf_counter(), 0
+        while time.perf_counter() - t0 < budget:
+            out = fn()
+            n += 1
+        return (time.perf_counter() - t0) / n, out
+
+    t_fit, B = rate(fits, 1.0)
+    t_sum, sigma = rate(lambda: sums(B), 2.0)
+    terms = sum(1 for Jv in range(s["J_max"] + 1) for jm in jmin if Jv >= jm) * s["n_f"] * e.size
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import xsection_oracle as X
+        t_or, ref = rate(lambda: X.cross_section(
+            X.cumulative_probability(J, B, p, e, s["J_max"], fam_jmin=jmin), e, mu, 2), 10.0)
+        err = float(np.max(np.abs(sigma - ref)) / np.max(np.abs(ref)))
+        cpu = dict(value=round(terms / t_or, 1), unit="terms/s", cores=1, kind="oracle",
+                   sample=f"the same sums (numpy oracle) repeated for about 10 s; "
+                          f"max relative difference of sigma {err:.1e}")
+    out = {
+        "metric": "partial-wave sum terms/s (Eq. cumulative-probability + cross section)",
+        "value": round(terms / t_sum, 1),
+        "unit": "terms/s",
+        "n_gpus": 0,
+        "steps": 1,
+        "warmup": 1,
+        "ms_per_step": round(t_sum * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"J=0..40 from 21 computed J, {s['n_fam']} (Omega0, p) families "
+                               f"(j0=2), {s['n_f']} final states, {e.size} energies",
+                   "terms": terms, "fit_ms_per_interval": round(t_fit * 1e3 / (len(J) - 1), 4),
+                   "host_threads": 1},
+        "roofline": None,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -272,6 +342,10 @@ def main():
     ap.add_argument("--mlp-pe-steps", type=int, default=0,
                     help="also propagate both plans from k = 0 for this many steps and report "
                          "the largest P(E) difference between the network and the table")
+    ap.add_argument("--partial-waves", action="store_true",
+                    help="time the host partial-wave sums (J-shifting interpolation, cumulative "
+                         "probability, cross section) on the batched workload's output shape")
+    ap.add_argument("--pw-final-states", type=int, default=64)
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="also run one device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -280,6 +354,8 @@ def main():
               "(independent partial waves would shard across GPUs with no per-step traffic)",
               file=sys.stderr)
         sys.exit(2)
+    if args.partial_waves:
+        return partial_waves_bench(args)
 
     import torch
     from paper_2412_10167_amd import problem

@@ -230,6 +230,65 @@ int tdwp_get_packet(tdwp_plan_t p, int unit, int slot, int which, double* out);
 int tdwp_state_to_state(tdwp_plan_t p, int unit, int slot, int n_ch, const tdwp_channel* ch,
                         const double* chi, double* p_inel, double* p_reac);
 
+/* ---- Partial-wave sums (Sec. "Cross sections") ------------------------------
+ * Host functions on host FP64 arrays; no plan, no device.  They combine the
+ * probabilities that tdwp_state_to_state returns for the computed partial waves.
+ * Energy grids are strictly ascending; a probability curve sampled on a grid is
+ * read between grid points by linear interpolation and keeps its end values
+ * outside the grid.  B (rotational constants) and energies in hartree.
+ * Errors: TDWP_EINVAL for a NULL pointer, a size < 1, a grid that does not
+ * ascend, a negative J or B, or J outside the allowed range; nothing is
+ * written then. */
+
+/* J-shifting from one computed total angular momentum J_ref (the J-shifting
+ * approach cited in Sec. "Cross sections"): the threshold moves up with the
+ * rotational energy, out[i] = p_ref(e[i] - B [J(J+1) - J_ref(J_ref+1)]).
+ * p_ref, e, out: [n_e].  Any J >= 0. */
+int tdwp_jshift(const double* p_ref, const double* e, int n_e, int J_ref, double B, int J,
+                double* out);
+
+/* J-shifting interpolation (Eq. J-shifting-interpolation) between computed
+ * J1 < J2, for J1 <= J <= J2:
+ *   out(E) = (J2-J)/(J2-J1) p1(E - B [J(J+1) - J1(J1+1)])
+ *          + (J-J1)/(J2-J1) p2(E + B [J2(J2+1) - J(J+1)]),
+ * so that J = J1 returns p1 and J = J2 returns p2.  p1, p2, e, out: [n_e]. */
+int tdwp_jshift_interpolate(const double* p1, const double* p2, const double* e, int n_e, int J1,
+                            int J2, double B, int J, double* out);
+
+/* Cumulative probability (Eq. cumulative-probability) on the grid e[n_e]:
+ *   c_out[f][i] = sum_{J=0..J_max} sum_fam (2J+1) P^J_{fam,f}(e[i]),
+ * fam running over the initial-helicity/parity families (Omega0, p) of the
+ * computed waves and f over the final states the caller resolves (a sum over
+ * final helicities can be taken before or after: the result is linear in P).
+ *  J_calc[n_calc]: computed total angular momenta, strictly ascending.
+ *  B[n_calc]: B[c] is the constant of the interval [J_calc[c], J_calc[c+1]];
+ *    the last entry is used for J above the last computed J, B[0] for J below
+ *    the first (plain J-shifting there).
+ *  p[n_calc][n_fam][n_f][n_e]: computed probabilities; a family with no state
+ *    at a computed J (Omega0 > J) has zeros there.
+ *  fam_jmin[n_fam] (may be NULL: all 0): the family contributes for J >= fam_jmin.
+ *  P^J is the computed curve at a computed J, the interpolation of
+ *  tdwp_jshift_interpolate between neighbouring computed J, and tdwp_jshift
+ *  from the nearest computed J outside their range.  c_out: [n_f][n_e]. */
+int tdwp_cumulative_probability(const int* J_calc, const double* B, int n_calc, const double* p,
+                                int n_fam, const int* fam_jmin, int n_f, const double* e, int n_e,
+                                int J_max, double* c_out);
+
+/* Integral cross section (Eq. collisional-xsection), bohr^2:
+ *   sigma[f][i] = pi / (K0^2 (2 j0 + 1)) c[f][i],  K0^2 = 2 mu e_col[i],
+ * mu the reduced mass of A + BC (electron masses), e_col > 0 the collision
+ * energies of c's grid.  c, sigma: [n_f][n_e]. */
+int tdwp_cross_section(const double* c, int n_f, const double* e_col, int n_e, double mu, int j0,
+                       double* sigma);
+
+/* Rotational constant for the interval [J1, J2] of Eq. J-shifting-interpolation,
+ * fitted as the B in [0, B_max] that minimises sum_i (p1(e[i] - B [J2(J2+1) -
+ * J1(J1+1)]) - p2(e[i]))^2: the J1 curve J-shifted onto the computed J2 curve.
+ * The search scans 512 equal cells and refines the best one to 1e-13 B_max.
+ * p1, p2, e: [n_e], n_e >= 2, J2 > J1. */
+int tdwp_fit_jshift_b(const double* p1, const double* p2, const double* e, int n_e, int J1, int J2,
+                      double B_max, double* B_out);
+
 /* Chooses the kernel variants of a step (angular and r passes in one launch or
  * two, angular kernel, its tile width, its block order) by timing the kernels
  * of `steps` whole steps for each feasible combination on this plan's shapes,

@@ -17,7 +17,8 @@ EXPORTED_SYMBOLS = (
     "tdwp_get_packet", "tdwp_state_to_state", "tdwp_time_kernels", "tdwp_destroy",
     "tdwp_strerror", "tdwp_mlp_n_params", "tdwp_set_potential_mlp", "tdwp_mlp_params",
     "tdwp_mlp_gradient", "tdwp_mlp_eval", "tdwp_mlp_grid", "tdwp_autotune",
-    "tdwp_set_option", "tdwp_get_stat",
+    "tdwp_set_option", "tdwp_get_stat", "tdwp_jshift", "tdwp_jshift_interpolate",
+    "tdwp_cumulative_probability", "tdwp_cross_section", "tdwp_fit_jshift_b",
 )
 OPTIONS = {"graphs": 0, "ang_tile": 1, "radial_grid": 2, "ang_kernel": 3, "fuse_r": 4,
            "ang_xcd": 5}
@@ -124,6 +125,13 @@ def load_library():
     lib.tdwp_set_option.argtypes = [P, ctypes.c_int, ctypes.c_long]
     lib.tdwp_get_stat.argtypes = [P, ctypes.c_int, ctypes.POINTER(ctypes.c_long)]
     lib.tdwp_destroy.argtypes = [P]
+    ip = ctypes.POINTER(ctypes.c_int)
+    ci, cd = ctypes.c_int, ctypes.c_double
+    lib.tdwp_jshift.argtypes = [dp, dp, ci, ci, cd, ci, dp]
+    lib.tdwp_jshift_interpolate.argtypes = [dp, dp, dp, ci, ci, ci, cd, ci, dp]
+    lib.tdwp_cumulative_probability.argtypes = [ip, dp, ci, dp, ci, ip, ci, dp, ci, ci, dp]
+    lib.tdwp_cross_section.argtypes = [dp, ci, dp, ci, cd, ci, dp]
+    lib.tdwp_fit_jshift_b.argtypes = [dp, dp, dp, ci, ci, ci, cd, dp]
     lib.tdwp_destroy.restype = None
     lib.tdwp_strerror.argtypes = [ctypes.c_int]
     lib.tdwp_strerror.restype = ctypes.c_char_p
@@ -362,3 +370,73 @@ class Plan:
 
     def __exit__(self, *exc):
         self.close()
+
+
+# ---- partial-wave sums (host functions of the library; no plan, no device) ----
+
+def _i32(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.int32))
+
+
+def _iptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+
+
+def jshift(p_ref, energies, J_ref, B, J):
+    """p_ref J-shifted from J_ref to J (tdwp_jshift)."""
+    p, e = _f64(p_ref), _f64(energies)
+    out = np.empty_like(e)
+    _check(load_library().tdwp_jshift(_ptr(p), _ptr(e), e.size, J_ref, B, J, _ptr(out)),
+           "tdwp_jshift")
+    return out
+
+
+def jshift_interpolate(p1, p2, energies, J1, J2, B, J):
+    """Probability at J from the computed J1 and J2 curves (tdwp_jshift_interpolate)."""
+    a, b, e = _f64(p1), _f64(p2), _f64(energies)
+    out = np.empty_like(e)
+    _check(load_library().tdwp_jshift_interpolate(_ptr(a), _ptr(b), _ptr(e), e.size, J1, J2, B, J,
+                                                  _ptr(out)), "tdwp_jshift_interpolate")
+    return out
+
+
+def cumulative_probability(J_calc, B, p, energies, J_max, fam_jmin=None):
+    """Cumulative probability c[n_f][n_e] from p[n_calc][n_fam][n_f][n_e]
+    (tdwp_cumulative_probability)."""
+    jc, bb, pp, e = _i32(J_calc), _f64(B), _f64(p), _f64(energies)
+    if pp.ndim != 4 or pp.shape[0] != jc.size or pp.shape[3] != e.size or bb.size != jc.size:
+        raise ValueError("p must be [n_calc][n_fam][n_f][n_e] with n_calc = len(J_calc) = len(B)")
+    n_fam, n_f = pp.shape[1], pp.shape[2]
+    jm = None
+    if fam_jmin is not None:
+        jm = _i32(fam_jmin)
+        if jm.size != n_fam:
+            raise ValueError("fam_jmin needs one entry per family")
+    out = np.empty((n_f, e.size))
+    _check(load_library().tdwp_cumulative_probability(
+        _iptr(jc), _ptr(bb), jc.size, _ptr(pp), n_fam, None if jm is None else _iptr(jm), n_f,
+        _ptr(e), e.size, J_max, _ptr(out)), "tdwp_cumulative_probability")
+    return out
+
+
+def cross_section(c, e_col, mu, j0):
+    """Integral cross section [n_f][n_e] in bohr^2 from cumulative probabilities
+    (tdwp_cross_section)."""
+    cc, e = _f64(c), _f64(e_col)
+    if cc.ndim == 1:
+        cc = cc[None, :]
+    if cc.shape[1] != e.size:
+        raise ValueError("c must be [n_f][n_e]")
+    out = np.empty_like(cc)
+    _check(load_library().tdwp_cross_section(_ptr(cc), cc.shape[0], _ptr(e), e.size, mu, j0,
+                                             _ptr(out)), "tdwp_cross_section")
+    return out
+
+
+def fit_jshift_b(p1, p2, energies, J1, J2, B_max):
+    """Fitted rotational constant of the interval [J1, J2] (tdwp_fit_jshift_b)."""
+    a, b, e = _f64(p1), _f64(p2), _f64(energies)
+    out = ctypes.c_double()
+    _check(load_library().tdwp_fit_jshift_b(_ptr(a), _ptr(b), _ptr(e), e.size, J1, J2, B_max,
+                                            ctypes.byref(out)), "tdwp_fit_jshift_b")
+    return out.value
