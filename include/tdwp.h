@@ -230,6 +230,46 @@ int tdwp_get_packet(tdwp_plan_t p, int unit, int slot, int which, double* out);
 int tdwp_state_to_state(tdwp_plan_t p, int unit, int slot, int n_ch, const tdwp_channel* ch,
                         const double* chi, double* p_inel, double* p_reac);
 
+/* ---- Photodissociation packets (Sec. "Initial wave packet in photodissociation")
+ * A photodissociation packet is the transition dipole applied to an initial bound
+ * state, projected on the unit's helicity blocks (Eq. initial-photo-wvp); the
+ * caller builds it.  Its energy content is not known in advance and follows from
+ * the autocorrelation C_k = <u_0|u_k> of the propagated packet (Eqs.
+ * fourier-transform, chebyshev-transform), which the library forms on the
+ * device after every step (one extra read of u_0 and u_k per step; HIP-graph
+ * replay of steps is off while a plan holds such a packet). */
+
+/* Installs packet (unit, slot) from caller values u0 (host, the layout of
+ * tdwp_get_packet: DVR-weighted coefficients, not normalised by the library)
+ * and resets it to k = 0, as tdwp_set_initial_packet does for a collision
+ * packet (every packet of a plan restarts together).  The packet then records
+ * its autocorrelation; tdwp_state_to_state refuses it (TDWP_ESTATE).
+ * Errors: EINVAL (no such packet, u0 zero or not finite), ESTATE (no potential). */
+int tdwp_set_packet_values(tdwp_plan_t p, int unit, int slot, const double* u0);
+
+/* Copies C_0 .. C_{n-1} of photodissociation packet (unit, slot), C_k = <u_0|u_k>
+ * in FP64 over the whole packet; n <= k + 1 with k the plan's step index.
+ * Errors: EINVAL (no such packet, n out of range), ESTATE (not a
+ * photodissociation packet, or not set). */
+int tdwp_autocorrelation(tdwp_plan_t p, int unit, int slot, long n, double* out);
+
+/* Energy content of a packet from its autocorrelation (Eq. chebyshev-transform):
+ *   a0[i] = (1/pi) sum_{k<n_k} (2 - delta_k0) cos(k theta) / (dE sin theta) C[k],
+ *   theta = arccos((E[i] - E0)/dE), E0 = (e_min + e_max)/2, dE = (e_max - e_min)/2,
+ * with (e_min, e_max) the plan's spectral bounds (tdwp_spectral_bounds).  Host
+ * function.  Errors: EINVAL (NULL, n_k or n_e < 1, e_max <= e_min, an energy
+ * not strictly inside (e_min, e_max); nothing is written then). */
+int tdwp_energy_content(const double* C, long n_k, double e_min, double e_max, const double* E,
+                        int n_e, double* a0);
+
+/* Total photodissociation cross section (Eq. spectrum), bohr^2:
+ *   sigma[i] = A hnu[i] / (2 pi) sum_k 2 Re[c_k(H_s, E_i + hnu[i]) C[k]],
+ * A = 1/(hbar^2 eps0 c) = 4 pi / c in atomic units, E_i the initial bound-state
+ * energy on the energy scale of H, hnu > 0 the photon energies.  Host function.
+ * Errors: as tdwp_energy_content, also for hnu <= 0. */
+int tdwp_photo_cross_section(const double* C, long n_k, double e_min, double e_max, double E_i,
+                             const double* hnu, int n_e, double* sigma);
+
 /* ---- Partial-wave sums (Sec. "Cross sections") ------------------------------
  * Host functions on host FP64 arrays; no plan, no device.  They combine the
  * probabilities that tdwp_state_to_state returns for the computed partial waves.

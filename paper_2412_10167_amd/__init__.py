@@ -5,4 +5,5 @@ The compute path is the HIP library libtdwp.so (C ABI in include/tdwp.h);
 """
 from .tdwp import (Plan, TdwpError, library_path, load_library,  # noqa: F401
                    PRECISIONS, EXPORTED_SYMBOLS, jshift, jshift_interpolate,
-                   cumulative_probability, cross_section, fit_jshift_b)
+                   cumulative_probability, cross_section, fit_jshift_b, energy_content,
+                   photo_cross_section)

@@ -5,7 +5,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libtdwp.so")
-SOURCES = ["tdwp.hip", "host_tables.cpp", "partial_waves.cpp"]
+SOURCES = ["tdwp.hip", "host_tables.cpp", "partial_waves.cpp", "spectra.cpp"]
 HEADERS = ["plan.h", "host_tables.h", "step_kernels.hpp"]
 
 FLAGS = [

@@ -58,6 +58,12 @@ struct PacketInfo {
   bool snap_taken = false;
   tdwp_packet pk{};
   std::vector<double> g;   // DVR-weighted unit-normalised g_m
+  // photodissociation packets (installed from caller values): autocorrelation
+  bool photo = false;
+  int acf_nb = 0;            // workgroups of its partial sums
+  size_t acf_part_off = 0;   // offset of its partials within a row of d_acfpart
+  int acf_idx = -1;          // its row block in d_acf
+  std::vector<double> acf;   // C_0 .. C_k
 };
 
 }  // namespace tdwp
@@ -147,6 +153,14 @@ struct tdwp_plan_s {
   size_t chan_cap = 0;
   double* d_out = nullptr;        // staging for analysis outputs
   size_t out_cap = 0;
+  double* d_u0 = nullptr;         // initial photodissociation packets, packet layout
+  size_t u0_cap = 0;
+  double* d_acfpart = nullptr;    // [kNormChunk][acf_nb_total] autocorrelation partials
+  size_t acfpart_cap = 0;
+  double* d_acf = nullptr;        // [n_photo][kNormChunk] summed autocorrelation rows
+  size_t acf_cap = 0;
+  size_t acf_nb_total = 0;
+  int n_photo = 0;
   double* d_g = nullptr;          // [n_packets][n_R]
   // batched-launch index maps (one launch per pass covers every packet)
   void* d_pkdesc = nullptr;       // PkDesc[n_packets]

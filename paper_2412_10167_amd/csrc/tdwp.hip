@@ -16,6 +16,7 @@
 #include "plan.h"
 #include "fast_kernels.hpp"
 #include "mlp_kernels.hpp"
+#include "photo_kernels.hpp"
 #include "step_kernels.hpp"
 
 using namespace tdwp;
@@ -796,8 +797,8 @@ void store_tile(Plan* P, int nt) {
 
 struct Timing {
   hipEvent_t ev[2];
-  double ms[5] = {0, 0, 0, 0, 0};
-  long calls[5] = {0, 0, 0, 0, 0};
+  double ms[6] = {0, 0, 0, 0, 0, 0};
+  long calls[6] = {0, 0, 0, 0, 0, 0};
 };
 
 int timed_begin(Plan* P, Timing* T) {
@@ -1227,11 +1228,67 @@ int finish_slices(Plan* P, Timing* T) {
 // Whether the next two steps are steady state: matrix-core path, not the first
 // step, slices recorded in both, no ring flush or elastic snapshot in between.
 bool graph_ready(Plan* P, int left, Timing* T) {
-  if (!P->use_graphs || !P->fast || T || left < 2 || P->k < 1) return false;
+  if (!P->use_graphs || !P->fast || T || left < 2 || P->k < 1 || P->n_photo) return false;
   if (P->rec_k >= P->k || P->ring_count + 2 > P->ring_len) return false;
   for (auto& pk : P->packets)
     if (!pk.snap_taken && (pk.pk.k_min_elastic == P->k || pk.pk.k_min_elastic == P->k + 1)) return false;
   return true;
+}
+
+// ---- autocorrelation of photodissociation packets -------------------------------
+
+int acf_blocks(size_t n) {
+  const size_t nb = (n + kAcfPerBlock - 1) / kAcfPerBlock;
+  return (int)std::min<size_t>(std::max<size_t>(nb, 1), kAcfMaxBlocks);
+}
+
+// Partial-sum layout of every photodissociation packet: rows of acf_nb_total.
+int acf_layout(Plan* P) {
+  size_t tot = 0;
+  int idx = 0;
+  for (auto& pk : P->packets) {
+    if (!pk.photo) continue;
+    pk.acf_nb = acf_blocks(pk.n_values);
+    pk.acf_part_off = tot;
+    pk.acf_idx = idx++;
+    tot += pk.acf_nb;
+  }
+  P->acf_nb_total = tot;
+  P->n_photo = idx;
+  if (!idx) return TDWP_OK;
+  TRY(ensure_staging(P, &P->d_acfpart, &P->acfpart_cap, (size_t)kNormChunk * tot));
+  TRY(ensure_staging(P, &P->d_acf, &P->acf_cap, (size_t)kNormChunk * idx));
+  return TDWP_OK;
+}
+
+// Row `row` of the partials: <u_0|u_k> of packet pk with u_k the current buffer.
+void acf_dot(Plan* P, const PacketInfo& pk, int row) {
+  hipLaunchKernelGGL(k_dot_partial, dim3(pk.acf_nb), dim3(kAcfThreads), 0, P->stream,
+                     P->d_u0 + pk.off, P->d_u[P->cur] + pk.off, pk.n_values,
+                     P->d_acfpart + (size_t)row * P->acf_nb_total + pk.acf_part_off);
+}
+
+int acf_enqueue(Plan* P, int row, Timing* T) {
+  TRY(timed_begin(P, T));
+  for (auto& pk : P->packets)
+    if (pk.photo) acf_dot(P, pk, row);
+  HIP_TRY(hipGetLastError());
+  TRY(timed_end(P, T, 5));
+  return TDWP_OK;
+}
+
+// Sums rows [0, rows) of packet pk and appends them to its series (synchronises).
+int acf_collect(Plan* P, PacketInfo& pk, int rows) {
+  double* out = P->d_acf + (size_t)pk.acf_idx * kNormChunk;
+  hipLaunchKernelGGL(k_rows_sum, dim3((rows + 255) / 256), dim3(256), 0, P->stream,
+                     P->d_acfpart + pk.acf_part_off, P->acf_nb_total, pk.acf_nb, rows, out);
+  HIP_TRY(hipGetLastError());
+  const size_t n0 = pk.acf.size();
+  pk.acf.resize(n0 + rows);
+  HIP_TRY(hipMemcpyAsync(pk.acf.data() + n0, out, rows * sizeof(double), hipMemcpyDeviceToHost,
+                         P->stream));
+  HIP_TRY(hipStreamSynchronize(P->stream));
+  return TDWP_OK;
 }
 
 int run_steps(Plan* P, long n_steps, double* norms_out, Timing* T) {
@@ -1256,6 +1313,7 @@ int run_steps(Plan* P, long n_steps, double* norms_out, Timing* T) {
         s += 2;
       } else {
         TRY(one_step(P, s, T));
+        if (P->n_photo) TRY(acf_enqueue(P, s, T));
         s += 1;
       }
     }
@@ -1277,6 +1335,8 @@ int run_steps(Plan* P, long n_steps, double* norms_out, Timing* T) {
         if (!std::isfinite(v) || v > 1e6) bad = true;
         if (norms_out) norms_out[(size_t)p * n_steps + done + s] = v;
       }
+    for (auto& pk : P->packets)
+      if (pk.photo) TRY(acf_collect(P, pk, chunk));
     done += chunk;
     if (bad) return TDWP_ERANGE;
   }
@@ -1293,7 +1353,11 @@ void reset_propagation(Plan* P) {
   for (auto& pk : P->packets) {
     pk.set = false;
     pk.snap_taken = false;
+    pk.photo = false;
+    pk.acf.clear();
   }
+  P->n_photo = 0;
+  P->acf_nb_total = 0;
 }
 
 }  // namespace
@@ -1487,6 +1551,11 @@ int tdwp_set_initial_packet(tdwp_plan_t p, const tdwp_packet* pk, const double* 
     if (p->packets[i].unit == pk->unit && p->packets[i].slot == pk->slot) ip = (int)i;
   PacketInfo& P = p->packets[ip];
   P.pk = *pk;
+  if (P.photo) {
+    P.photo = false;
+    P.acf.clear();
+    TRY(acf_layout(p));
+  }
   const int nr = p->nr, nR = p->nR, ng = p->ng;
   // factor vectors: Legendre row, DVR-weighted Gaussian, channel function
   std::vector<double> pj(ng), g(nR), chi(nr);
@@ -1556,6 +1625,65 @@ int tdwp_propagate(tdwp_plan_t p, long n_steps, double* norms) {
   return run_steps(p, n_steps, norms, nullptr);
 }
 
+int tdwp_set_packet_values(tdwp_plan_t p, int unit, int slot, const double* u0) {
+  if (!p || !u0) return TDWP_EINVAL;
+  if (!p->have_potential) return TDWP_ESTATE;
+  int ip = -1;
+  for (size_t i = 0; i < p->packets.size(); ++i)
+    if (p->packets[i].unit == unit && p->packets[i].slot == slot) ip = (int)i;
+  if (ip < 0) return TDWP_EINVAL;
+  const size_t n = p->packets[ip].n_values;
+  double s = 0.0;
+  for (size_t q = 0; q < n; ++q) s += u0[q] * u0[q];
+  if (!(s > 0) || !std::isfinite(s)) return TDWP_EINVAL;
+  if (p->k > 0) reset_propagation(p);
+  PacketInfo& P = p->packets[ip];
+  P.pk = tdwp_packet{};
+  P.pk.unit = unit;
+  P.pk.slot = slot;
+  TRY(ensure_staging(p, &p->d_u0, &p->u0_cap, p->n_total));
+  HIP_TRY(hipMemcpyAsync(p->d_u0 + P.off, u0, n * sizeof(double), hipMemcpyHostToDevice, p->stream));
+  HIP_TRY(hipMemcpyAsync(p->d_u[p->cur] + P.off, p->d_u0 + P.off, n * sizeof(double),
+                         hipMemcpyDeviceToDevice, p->stream));
+  HIP_TRY(hipMemsetAsync(p->d_u[1 - p->cur] + P.off, 0, n * sizeof(double), p->stream));
+  HIP_TRY(hipMemsetAsync(p->d_acc + P.acc_off, 0, (size_t)2 * p->cfg.n_energy * P.n_slice * sizeof(double), p->stream));
+  HIP_TRY(hipMemsetAsync(p->d_snap + P.snap_off, 0, (size_t)2 * p->cfg.n_energy * P.n_w * sizeof(double), p->stream));
+  P.snap_taken = true;   // no elastic-channel window
+  const double zero = 0.0;
+  HIP_TRY(hipMemcpyAsync(p->d_E + ip, &zero, sizeof(double), hipMemcpyHostToDevice, p->stream));
+  p->ring_count = 0;
+  p->norm_row = 0;
+  p->ring_k0 = 0;
+  if (p->fast) {
+    TRY(sync_counters(p));
+    p->rec_k = -1;
+  } else {
+    TRY(record_slices(p, 0));
+    p->ring_count = 1;
+    p->rec_k = 0;
+  }
+  P.photo = true;
+  P.acf.clear();
+  TRY(acf_layout(p));
+  acf_dot(p, P, 0);   // C_0 = <u_0|u_0>
+  HIP_TRY(hipGetLastError());
+  TRY(acf_collect(p, P, 1));
+  P.set = true;
+  return TDWP_OK;
+}
+
+int tdwp_autocorrelation(tdwp_plan_t p, int unit, int slot, long n, double* out) {
+  if (!p || n < 0 || (n > 0 && !out)) return TDWP_EINVAL;
+  for (auto& pk : p->packets)
+    if (pk.unit == unit && pk.slot == slot) {
+      if (!pk.set || !pk.photo) return TDWP_ESTATE;
+      if ((size_t)n > pk.acf.size()) return TDWP_EINVAL;
+      std::copy(pk.acf.begin(), pk.acf.begin() + n, out);
+      return TDWP_OK;
+    }
+  return TDWP_EINVAL;
+}
+
 int tdwp_step_index(tdwp_plan_t p, long* k) {
   if (!p || !k) return TDWP_EINVAL;
   *k = p->k;
@@ -1583,7 +1711,7 @@ int tdwp_state_to_state(tdwp_plan_t p, int unit, int slot, int n_ch, const tdwp_
     if (p->packets[i].unit == unit && p->packets[i].slot == slot) ip = (int)i;
   if (ip < 0) return TDWP_EINVAL;
   PacketInfo& P = p->packets[ip];
-  if (!P.set) return TDWP_ESTATE;
+  if (!P.set || P.photo) return TDWP_ESTATE;
   const UnitInfo& U = p->units[unit];
   const tdwp_config& c = p->cfg;
   const int nE = c.n_energy;
@@ -1650,9 +1778,10 @@ int tdwp_time_kernels(tdwp_plan_t p, long n_steps, int n_max, double* avg_us, ch
   (void)hipEventDestroy(T.ev[0]);
   (void)hipEventDestroy(T.ev[1]);
   if (st != TDWP_OK) return st;
-  static const char* kinds[5] = {"angular", "radial_R_epilogue", "slices", "accumulate", "radial_r"};
+  static const char* kinds[6] = {"angular", "radial_R_epilogue", "slices", "accumulate", "radial_r",
+                                 "autocorrelation"};
   std::string joined;
-  for (int i = 0; i < 5; ++i) {
+  for (int i = 0; i < 6; ++i) {
     if (i < n_max && avg_us) avg_us[i] = T.calls[i] ? 1000.0 * T.ms[i] / T.calls[i] : 0.0;
     if (i) joined += ";";
     joined += kinds[i];
@@ -1661,7 +1790,7 @@ int tdwp_time_kernels(tdwp_plan_t p, long n_steps, int n_max, double* avg_us, ch
     std::strncpy(names, joined.c_str(), names_len - 1);
     names[names_len - 1] = 0;
   }
-  return 5;
+  return 6;
 }
 
 int tdwp_autotune(tdwp_plan_t p, int steps, char* report, size_t report_len) {

@@ -19,6 +19,8 @@ EXPORTED_SYMBOLS = (
     "tdwp_mlp_gradient", "tdwp_mlp_eval", "tdwp_mlp_grid", "tdwp_autotune",
     "tdwp_set_option", "tdwp_get_stat", "tdwp_jshift", "tdwp_jshift_interpolate",
     "tdwp_cumulative_probability", "tdwp_cross_section", "tdwp_fit_jshift_b",
+    "tdwp_set_packet_values", "tdwp_autocorrelation", "tdwp_energy_content",
+    "tdwp_photo_cross_section",
 )
 OPTIONS = {"graphs": 0, "ang_tile": 1, "radial_grid": 2, "ang_kernel": 3, "fuse_r": 4,
            "ang_xcd": 5}
@@ -132,6 +134,11 @@ def load_library():
     lib.tdwp_cumulative_probability.argtypes = [ip, dp, ci, dp, ci, ip, ci, dp, ci, ci, dp]
     lib.tdwp_cross_section.argtypes = [dp, ci, dp, ci, cd, ci, dp]
     lib.tdwp_fit_jshift_b.argtypes = [dp, dp, dp, ci, ci, ci, cd, dp]
+    cl = ctypes.c_long
+    lib.tdwp_set_packet_values.argtypes = [P, ci, ci, dp]
+    lib.tdwp_autocorrelation.argtypes = [P, ci, ci, cl, dp]
+    lib.tdwp_energy_content.argtypes = [dp, cl, cd, cd, dp, ci, dp]
+    lib.tdwp_photo_cross_section.argtypes = [dp, cl, cd, cd, cd, dp, ci, dp]
     lib.tdwp_destroy.restype = None
     lib.tdwp_strerror.argtypes = [ctypes.c_int]
     lib.tdwp_strerror.restype = ctypes.c_char_p
@@ -279,6 +286,26 @@ class Plan:
         return p_inel, (p_reac if reactive else None)
 
     # -- learned potential ---------------------------------------------------
+    def set_packet_values(self, unit, slot, u0):
+        """Installs a photodissociation packet from values in the packet layout."""
+        u = _f64(u0).ravel()
+        n = self.n_omega(unit) * self.spec["n_elec"] * self.spec["n_gamma"] * self.spec["n_R"] \
+            * self.spec["n_r"]
+        if u.size != n:
+            raise ValueError(f"packet of unit {unit} has {n} values, got {u.size}")
+        _check(self.lib.tdwp_set_packet_values(self.handle, unit, slot, _ptr(u)),
+               "tdwp_set_packet_values")
+
+    def autocorrelation(self, unit=0, slot=0, n=None):
+        """C_0 .. C_{n-1} = <u_0|u_k> of a photodissociation packet (default: up to the
+        current step)."""
+        if n is None:
+            n = self.step_index() + 1
+        out = np.empty(n)
+        _check(self.lib.tdwp_autocorrelation(self.handle, unit, slot, n, _ptr(out)),
+               "tdwp_autocorrelation")
+        return out
+
     def mlp_n_params(self):
         return _check(self.lib.tdwp_mlp_n_params(self.handle), "tdwp_mlp_n_params")
 
@@ -440,3 +467,24 @@ def fit_jshift_b(p1, p2, energies, J1, J2, B_max):
     _check(load_library().tdwp_fit_jshift_b(_ptr(a), _ptr(b), _ptr(e), e.size, J1, J2, B_max,
                                             ctypes.byref(out)), "tdwp_fit_jshift_b")
     return out.value
+
+
+# ---- photodissociation spectra (host functions of the library) ----
+
+def energy_content(C, e_min, e_max, energies):
+    """a_0(E) from an autocorrelation series (tdwp_energy_content)."""
+    c, e = _f64(C), _f64(energies)
+    out = np.empty_like(e)
+    _check(load_library().tdwp_energy_content(_ptr(c), c.size, e_min, e_max, _ptr(e), e.size,
+                                              _ptr(out)), "tdwp_energy_content")
+    return out
+
+
+def photo_cross_section(C, e_min, e_max, E_i, hnu):
+    """sigma(h nu) in bohr^2 from an autocorrelation series (tdwp_photo_cross_section)."""
+    c, h = _f64(C), _f64(hnu)
+    out = np.empty_like(h)
+    _check(load_library().tdwp_photo_cross_section(_ptr(c), c.size, e_min, e_max, E_i, _ptr(h),
+                                                   h.size, _ptr(out)),
+           "tdwp_photo_cross_section")
+    return out

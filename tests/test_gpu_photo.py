@@ -1,0 +1,155 @@
+"""Photodissociation packets on the HIP path (through the C ABI) against the
+oracle: the autocorrelation C_k = <u_0|u_k> formed on the device after every
+step (Eqs. fourier-transform, chebyshev-transform), and the energy content
+a_0(E) from it.
+
+Bar: FP64 forms within 1e-10 C_0 at every k (the packet bar, 1e-10 of the
+largest value, bounds the overlap far below that); the mixed forms within 1e-4
+C_0.  a_0(E) within the bound those differences imply through Eq.
+chebyshev-transform.  Each case prints its name first.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import photo_oracle as PH
+from oracle import tdwp_oracle as O
+from workloads import asymptotic_potential, small_variant
+from workloads.photo import photo_packet
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    from paper_2412_10167_amd import load_library
+    load_library()
+
+
+def banner(name):
+    print(f"\n[case] {name}", flush=True)
+
+
+def _photo_plan(spec, precision="fp64"):
+    from paper_2412_10167_amd import problem
+    from paper_2412_10167_amd.tdwp import Plan
+    plan = Plan(spec, precision=precision)
+    plan.set_potential(problem.potential_table(plan, spec))
+    return plan
+
+
+def _device_packet(plan, spec, unit, seed=0):
+    r, R, x, w = plan.grid()
+    return photo_packet(spec, unit, r, R, x, w, seed=seed)
+
+
+def _oracle_series(spec, unit, K, seed=0):
+    op = O.Operator(spec)
+    u0 = photo_packet(spec, unit, op.r, op.R, op.x, op.w, seed=seed)
+    return op, PH.autocorrelation(op, unit, u0, K)
+
+
+def _spec_2state_J1():
+    s = small_variant(3, n_R=21, n_r=17, n_gamma=9)
+    s["units"] = [dict(J=1, parity=-1, omega_max=1, n_packets=1)]
+    s["packets"] = []
+    return s
+
+
+CASES = [
+    ("J=0 24x20x10 fp64 (matrix-core kernels)", lambda: small_variant(1, n_R=24, n_r=20, n_gamma=10),
+     "fp64", 150, 1e-10),
+    ("J=1 Omega 0..1, 2 states, 21x17x9 fp64 (general kernels)", _spec_2state_J1, "fp64", 80, 1e-10),
+    ("J=0 24x20x10 fp16x3", lambda: small_variant(1, n_R=24, n_r=20, n_gamma=10), "fp16x3", 150, 1e-4),
+]
+
+
+@pytest.mark.parametrize("name, spec_fn, precision, K, tol", CASES)
+def test_autocorrelation_matches_oracle(name, spec_fn, precision, K, tol):
+    banner(f"photodissociation autocorrelation: {name}, {K} steps")
+    spec = spec_fn()
+    spec["units"] = [dict(u, n_packets=1) for u in spec["units"]][:1]
+    plan = _photo_plan(spec, precision)
+    plan.set_packet_values(0, 0, _device_packet(plan, spec, 0))
+    plan.propagate(K // 2, norms=False)      # two calls: the series continues across them
+    plan.propagate(K - K // 2, norms=False)
+    C = plan.autocorrelation(0, 0)
+    e_min, e_max = plan.spectral_bounds()
+    plan.close()
+    op, ref = _oracle_series(spec, 0, K)
+    assert C.shape == (K + 1,)
+    assert abs(C[0] - ref[0]) <= 1e-13 * ref[0]
+    err = float(np.max(np.abs(C - ref)))
+    assert err <= tol * ref[0], err
+    # energy content from both series
+    E = np.linspace(op.Emin + 0.05 * (op.Emax - op.Emin), op.Emin + 0.5 * (op.Emax - op.Emin), 41)
+    from paper_2412_10167_amd import energy_content
+    a_dev = energy_content(C, e_min, e_max, E)
+    a_ref = PH.energy_content(ref, op.Emin, op.Emax, E)
+    th = np.arccos((E - op.E0) / op.dE)
+    bound = (2 * K + 1) * max(err, 1e-300) / (math.pi * op.dE * np.sin(th)) \
+        + 1e-12 * np.max(np.abs(a_ref))
+    assert np.all(np.abs(a_dev - a_ref) <= bound)
+
+
+def test_photo_and_collision_packets_share_a_plan():
+    banner("batch: collision packet (slot 0) and photodissociation packet (slot 1), J=0 24x20x10")
+    from paper_2412_10167_amd import problem
+    from paper_2412_10167_amd.tdwp import TdwpError
+    spec = small_variant(1, n_R=24, n_r=20, n_gamma=10)
+    spec["units"] = [dict(spec["units"][0], n_packets=2)]
+    spec["packets"] = [dict(spec["packets"][0], k_min_elastic=30)]
+    plan, info = problem.build(spec)                  # installs the collision packet, slot 0
+    plan.set_packet_values(0, 1, _device_packet(plan, spec, 0))
+    K = 60
+    plan.propagate(K, norms=False)
+    C = plan.autocorrelation(0, 1)
+    with pytest.raises(TdwpError):
+        plan.autocorrelation(0, 0)                    # not a photodissociation packet
+    chans = problem.channels(plan, spec, 0, 2, 0)
+    with pytest.raises(TdwpError):
+        plan.state_to_state(0, 1, chans)              # no collision analysis for it
+    p_inel, p_reac = plan.state_to_state(0, 0, chans)
+    plan.close()
+    op, ref = _oracle_series(spec, 0, K)
+    assert float(np.max(np.abs(C - ref))) <= 1e-10 * ref[0]
+    # the collision packet is unaffected by its neighbour
+    pk = spec["packets"][0]
+    va = asymptotic_potential(spec, op.r, pk["elec0"])
+    e0, chi0 = O.diatomic_states(op, va, pk["j0"], 1)
+    run = O.propagate(op, 0, O.initial_packet(op, 0, pk, chi0[0]), K)
+    och = []
+    for c in chans:
+        vc = asymptotic_potential(spec, op.r, c["elec"])
+        ec, chic = O.diatomic_states(op, vc, c["j"], c["v"] + 1)
+        och.append(dict(c, energy=ec[c["v"]], chi=chic[c["v"]]))
+    res = O.analyse(op, 0, pk, run, e0[0], och)
+    assert np.max(np.abs(p_reac - res["p_reac"])) < 1e-8
+    assert np.max(np.abs(p_inel - res["p_inel"])) < 1e-8
+
+
+def test_photo_packet_errors():
+    banner("photodissociation entry points: invalid values and order")
+    from paper_2412_10167_amd.tdwp import TdwpError
+    spec = small_variant(1, n_R=16, n_r=12, n_gamma=6)
+    plan = _photo_plan(spec)
+    u = _device_packet(plan, spec, 0)
+    with pytest.raises(TdwpError):
+        plan.set_packet_values(0, 0, np.zeros_like(u))      # zero packet
+    bad = u.copy()
+    bad.flat[3] = np.nan
+    with pytest.raises(TdwpError):
+        plan.set_packet_values(0, 0, bad)                     # not finite
+    with pytest.raises(TdwpError):
+        plan.set_packet_values(0, 5, u)                       # no such slot
+    plan.set_packet_values(0, 0, u)
+    plan.propagate(3, norms=False)
+    assert plan.autocorrelation(0, 0).shape == (4,)
+    with pytest.raises(TdwpError):
+        plan.autocorrelation(0, 0, n=5)                       # beyond the current step
+    plan.close()
