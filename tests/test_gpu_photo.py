@@ -15,7 +15,7 @@ import pytest
 
 from oracle import photo_oracle as PH
 from oracle import tdwp_oracle as O
-from workloads import asymptotic_potential, small_variant
+from workloads import asymptotic_potential, config, small_variant
 from workloads.photo import photo_packet
 
 pytestmark = pytest.mark.gpu
@@ -95,6 +95,25 @@ def test_autocorrelation_matches_oracle(name, spec_fn, precision, K, tol):
     bound = (2 * K + 1) * max(err, 1e-300) / (math.pi * op.dE * np.sin(th)) \
         + 1e-12 * np.max(np.abs(a_ref))
     assert np.all(np.abs(a_dev - a_ref) <= bound)
+
+
+@pytest.mark.parametrize("precision, tol", [("fp64", 1e-10), ("fp16x3", 1e-4)])
+def test_full_size_workload2_photo_first_steps(precision, tol):
+    banner(f"photodissociation at full size 256x192x80, {precision}, autotuned launch form: 6 steps")
+    spec = config(2)
+    plan = _photo_plan(spec, precision)
+    plan.autotune(2)                          # the benchmark's launch configuration
+    plan.set_packet_values(0, 0, _device_packet(plan, spec, 0))
+    K = 6
+    plan.propagate(K, norms=False)
+    C = plan.autocorrelation(0, 0)
+    lo, hi = plan.spectral_bounds()
+    plan.close()
+    op = O.Operator(spec, bounds=(lo, hi))
+    ref = PH.autocorrelation(op, 0, photo_packet(spec, 0, op.r, op.R, op.x, op.w), K)
+    err = float(np.max(np.abs(C - ref)))
+    print(f"[result] max |C_k - oracle| / C_0 = {err / ref[0]:.2e}", flush=True)
+    assert err <= tol * ref[0]
 
 
 def test_photo_and_collision_packets_share_a_plan():
