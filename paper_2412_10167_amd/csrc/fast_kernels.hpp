@@ -134,9 +134,12 @@ __device__ __forceinline__ void radr_blk(const double* __restrict__ u,
   __syncthreads();   // the previous block's operands have been read
   const long line0 = blk * kRadrLines;
   // wave w loads lines w, w+4, ...; lanes run along the half line; the loads of
-  // a group of G lines are issued before any of them is used
+  // a group of G lines are issued before any of them is used.  Beside the angular
+  // pass (few r blocks per CU) a wave's eight lines go in one group, so twice the
+  // bytes are in flight; the standalone pass keeps groups of four (eight would
+  // take it past 128 VGPRs, to three waves per SIMD).
   constexpr int LPW = kRadrLines / 4;
-  constexpr int G = 4;
+  constexpr int G = ACC ? 4 : 8;
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
   // packet of the block's first line and its bounds (block-uniform loads); a
