@@ -116,6 +116,23 @@ def test_full_size_workload2_photo_first_steps(precision, tol):
     assert err <= tol * ref[0]
 
 
+def test_autocorrelation_across_readback_chunks():
+    # 4,100 steps in one call: the partial sums are read back every 4,096 steps
+    banner("photodissociation autocorrelation over 4100 steps in one call, J=0 15x12x6 fp64 "
+           "(general kernels)")
+    spec = small_variant(1, n_R=15, n_r=12, n_gamma=6)
+    plan = _photo_plan(spec)
+    plan.set_packet_values(0, 0, _device_packet(plan, spec, 0))
+    K = 4100
+    plan.propagate(K, norms=False)
+    C = plan.autocorrelation(0, 0)
+    assert plan.autocorrelation(0, 0, n=0).shape == (0,)
+    plan.close()
+    _, ref = _oracle_series(spec, 0, K)
+    assert C.shape == (K + 1,)
+    assert float(np.max(np.abs(C - ref))) <= 1e-10 * ref[0]
+
+
 def test_photo_and_collision_packets_share_a_plan():
     banner("batch: collision packet (slot 0) and photodissociation packet (slot 1), J=0 24x20x10")
     from paper_2412_10167_amd import problem
