@@ -1243,9 +1243,21 @@ int acf_blocks(size_t n) {
 }
 
 // Partial-sum layout of every photodissociation packet: rows of acf_nb_total.
+// The buffers are sized first; on an allocation failure nothing is changed.
 int acf_layout(Plan* P) {
   size_t tot = 0;
   int idx = 0;
+  for (auto& pk : P->packets)
+    if (pk.photo) {
+      tot += acf_blocks(pk.n_values);
+      ++idx;
+    }
+  if (idx) {
+    TRY(ensure_staging(P, &P->d_acfpart, &P->acfpart_cap, (size_t)kNormChunk * tot));
+    TRY(ensure_staging(P, &P->d_acf, &P->acf_cap, (size_t)kNormChunk * idx));
+  }
+  tot = 0;
+  idx = 0;
   for (auto& pk : P->packets) {
     if (!pk.photo) continue;
     pk.acf_nb = acf_blocks(pk.n_values);
@@ -1255,9 +1267,6 @@ int acf_layout(Plan* P) {
   }
   P->acf_nb_total = tot;
   P->n_photo = idx;
-  if (!idx) return TDWP_OK;
-  TRY(ensure_staging(P, &P->d_acfpart, &P->acfpart_cap, (size_t)kNormChunk * tot));
-  TRY(ensure_staging(P, &P->d_acf, &P->acf_cap, (size_t)kNormChunk * idx));
   return TDWP_OK;
 }
 
@@ -1636,12 +1645,22 @@ int tdwp_set_packet_values(tdwp_plan_t p, int unit, int slot, const double* u0) 
   double s = 0.0;
   for (size_t q = 0; q < n; ++q) s += u0[q] * u0[q];
   if (!(s > 0) || !std::isfinite(s)) return TDWP_EINVAL;
+  TRY(ensure_staging(p, &p->d_u0, &p->u0_cap, p->n_total));
+  {   // the autocorrelation buffers for this packet besides the others (no-op if they fit)
+    const bool was = p->packets[ip].photo;
+    p->packets[ip].photo = true;
+    const int st = acf_layout(p);
+    p->packets[ip].photo = was;
+    if (st != TDWP_OK) {
+      (void)acf_layout(p);   // the previous layout fits the existing buffers
+      return st;
+    }
+  }
   if (p->k > 0) reset_propagation(p);
   PacketInfo& P = p->packets[ip];
   P.pk = tdwp_packet{};
   P.pk.unit = unit;
   P.pk.slot = slot;
-  TRY(ensure_staging(p, &p->d_u0, &p->u0_cap, p->n_total));
   HIP_TRY(hipMemcpyAsync(p->d_u0 + P.off, u0, n * sizeof(double), hipMemcpyHostToDevice, p->stream));
   HIP_TRY(hipMemcpyAsync(p->d_u[p->cur] + P.off, p->d_u0 + P.off, n * sizeof(double),
                          hipMemcpyDeviceToDevice, p->stream));
