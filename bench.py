@@ -243,6 +243,27 @@ def cpu_baseline(spec, budget_s=15.0):
                        f"(H application, recursion and damping; no slices) in {dt:.1f} s")
 
 
+def spectrum_timing(plan, skip_oracle):
+    """Energy content a_0(E) (host function of the library) from the packet's whole
+    autocorrelation series on 2,000 energies, with the oracle's time beside it."""
+    import numpy as np
+    from paper_2412_10167_amd import energy_content
+    C = plan.autocorrelation(0, 0)
+    lo, hi = plan.spectral_bounds()
+    E = np.linspace(lo, hi, 2002)[1:-1]
+    t0 = time.perf_counter()
+    a0 = energy_content(C, lo, hi, E)
+    t_lib = time.perf_counter() - t0
+    out = dict(components=int(C.size), energies=int(E.size), library_ms=round(t_lib * 1e3, 3))
+    if not skip_oracle:
+        from oracle import photo_oracle as PH
+        t0 = time.perf_counter()
+        ref = PH.energy_content(C, lo, hi, E)
+        out["oracle_ms"] = round((time.perf_counter() - t0) * 1e3, 3)
+        out["max_rel_diff"] = float(np.max(np.abs(a0 - ref)) / np.max(np.abs(ref)))
+    return out
+
+
 def partial_waves_bench(args):
     """Partial-wave sums on the batched workload's output shape (host functions of
     the library): a fitted B per computed J, the cumulative probability over
@@ -435,6 +456,7 @@ def main():
         a_bw = gb / (per_step["autocorrelation"] * 1e-6)
         acf = dict(kernel_avg_us=round(per_step["autocorrelation"], 2), achieved_GBps=round(a_bw, 1),
                    frac=round(a_bw / pk_bw, 4))
+        acf["spectrum"] = spectrum_timing(plan, args.no_cpu_baseline)
     plan.close()
     fp64_rate = None
     if args.precision != "fp64" and not args.no_fp64_reference:

@@ -885,7 +885,10 @@ constexpr int kXLd = 16;
 template <int P, int NE>
 constexpr int radR_waves() { return (P == kP64 || NE > 1) ? 1 : 4; }
 
-template <int P, int NE, bool SPLIT = false, bool TWO = false>
+// ACF: also the partial sums of <u_0|u_{k+1}> of every packet (u_0 in u0_all, packet
+// layout; the photodissociation autocorrelation), one per workgroup beside the
+// norm partial, in acfpart with the norm partials' layout.
+template <int P, int NE, bool SPLIT = false, bool TWO = false, bool ACF = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(radR_waves<P, NE>())))
 void k_radR_epi(
     const double* __restrict__ uk_all, double* __restrict__ uprev_all,
@@ -896,11 +899,13 @@ void k_radR_epi(
     const typename HType<P>::T* __restrict__ V,
     const double* __restrict__ Dsep, int ng, int nR, int nr, double E0, double inv_dE,
     int first, double* __restrict__ normpart, size_t n_wg_total, int* __restrict__ counters,
-    int norm_rows, int recorded) {
+    int norm_rows, int recorded, const double* __restrict__ u0_all,
+    double* __restrict__ acfpart) {
   using M = Mma<P>;
   using F = Fmt<P>;
   using E = typename F::E;
   using HT = typename HType<P>::T;
+  static_assert(!(ACF && SPLIT), "the overlap needs u_{k+1}, formed only by the full epilogue");
   constexpr int CH = (M::KS == 4) ? Chunk<P>::CH : 1;
   using XT = typename HType<P>::T;
   constexpr int RT = 16;
@@ -909,6 +914,7 @@ void k_radR_epi(
   double* __restrict__ normpart_row =
       (nrow_ix >= 0 && nrow_ix < norm_rows) ? normpart + (size_t)nrow_ix * n_wg_total : nullptr;
   __shared__ double red[4];
+  __shared__ double red_acf[ACF ? 4 : 1];
   const int nblk = blk_start[n_pk];
   // a workgroup takes blocks blockIdx.x, blockIdx.x + gridDim.x, ...
   for (int blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
@@ -963,7 +969,7 @@ void k_radR_epi(
   const int t = l & 15;
   const int i = i0 + t;
   const double dr_i = Dsep[i < nr ? i : nr - 1];   // damping exp(-phi_r(r_i))
-  double nsum = 0.0;
+  double nsum = 0.0, asum = 0.0;
 #pragma unroll 1
   for (int le = 0; le < NE; ++le) {
     __syncthreads();
@@ -1056,6 +1062,7 @@ void k_radR_epi(
           const double un = first ? dmp * wv : dmp * (2.0 * wv - dmp * pv[q]);
           uprev[idx] = un;
           nsum += un * un;
+          if constexpr (ACF) asum += u0_all[dsc.off + idx] * un;
         }
       }
     }
@@ -1063,8 +1070,17 @@ void k_radR_epi(
   if constexpr (!SPLIT) {
     for (int off = 32; off > 0; off >>= 1) nsum += __shfl_down(nsum, off, 64);
     if (l == 0) red[w] = nsum;
+    if constexpr (ACF) {
+      for (int off = 32; off > 0; off >>= 1) asum += __shfl_down(asum, off, 64);
+      if (l == 0) red_acf[w] = asum;
+    }
     __syncthreads();
     if (threadIdx.x == 0 && normpart_row) normpart_row[dsc.wg_off + local] = red[0] + red[1] + red[2] + red[3];
+    if constexpr (ACF) {
+      if (threadIdx.x == 0 && normpart_row)
+        acfpart[(size_t)nrow_ix * n_wg_total + dsc.wg_off + local] =
+            red_acf[0] + red_acf[1] + red_acf[2] + red_acf[3];
+    }
   }
   }
   if constexpr (!SPLIT) {

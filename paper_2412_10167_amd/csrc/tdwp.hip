@@ -467,6 +467,14 @@ void set_lds_limits() {
                          (const void*)k_radR_epi<PR, 4, false, true>};
   std::vector<const void*> all(fns, fns + 13);
   auto add = [&](auto kern) { all.push_back((const void*)kern); };
+  add(k_radR_epi<PR, 1, false, false, true>);
+  add(k_radR_epi<PR, 2, false, false, true>);
+  add(k_radR_epi<PR, 3, false, false, true>);
+  add(k_radR_epi<PR, 4, false, false, true>);
+  add(k_radR_epi<PR, 1, false, true, true>);
+  add(k_radR_epi<PR, 2, false, true, true>);
+  add(k_radR_epi<PR, 3, false, true, true>);
+  add(k_radR_epi<PR, 4, false, true, true>);
   for (int nt : {1, 2, 4}) {
     for (bool single : {true, false}) {
       with_ang<PR>(nt, single, PlainAng{}, add);
@@ -1046,7 +1054,7 @@ int enqueue_step(Plan* P, int cur, int first, int rec, Timing* T) {
                          (const E*)P->d_TRsF,
                          (const E*)P->d_TRdF, P->nRhk, P->nRhk * P->nRhk, vtab, P->d_Dsep, ng, nR,
                          nr, P->E0, 1.0 / P->dE, first, P->d_normpart, P->n_wg_total,
-                         P->d_counters, kNormChunk, rec);
+                         P->d_counters, kNormChunk, rec, (const double*)nullptr, (double*)nullptr);
     };
     const double mbc = P->cfg.mass_B + P->cfg.mass_C;
     auto epi = [&](auto kern) {
@@ -1063,6 +1071,8 @@ int enqueue_step(Plan* P, int cur, int first, int rec, Timing* T) {
       default: fuse ? split(k_radR_epi<PR, 4, true, true>) : split(k_radR_epi<PR, 4, true>); epi(k_mlp_epi<PR, 4>); break;
     }
   } else {
+    // photodissociation packets: the R pass also forms <u_0|u_{k+1}>
+    const bool acf = P->acf_in_pass;
     auto launch = [&](auto kern) {
       hipLaunchKernelGGL(kern, dim3(radial_blocks(P, P->blocks_radR)), dim3(256), P->lds_radR,
                          P->stream, uk, uo,
@@ -1070,14 +1080,22 @@ int enqueue_step(Plan* P, int cur, int first, int rec, Timing* T) {
                          (const E*)P->d_TRdF,
                          P->nRhk, P->nRhk * P->nRhk, vtab, P->d_Dsep, ng, nR, nr, P->E0,
                          1.0 / P->dE, first, P->d_normpart, P->n_wg_total, P->d_counters,
-                         kNormChunk, rec);
+                         kNormChunk, rec, acf ? (const double*)P->d_u0 : nullptr,
+                         acf ? P->d_acfwg : nullptr);
     };
-    switch (ne) {
-      case 1: fuse ? launch(k_radR_epi<PR, 1, false, true>) : launch(k_radR_epi<PR, 1>); break;
-      case 2: fuse ? launch(k_radR_epi<PR, 2, false, true>) : launch(k_radR_epi<PR, 2>); break;
-      case 3: fuse ? launch(k_radR_epi<PR, 3, false, true>) : launch(k_radR_epi<PR, 3>); break;
-      default: fuse ? launch(k_radR_epi<PR, 4, false, true>) : launch(k_radR_epi<PR, 4>); break;
-    }
+    auto by_ne = [&](auto two, auto withacf) {
+      constexpr bool TW = decltype(two)::value, AC = decltype(withacf)::value;
+      switch (ne) {
+        case 1: launch(k_radR_epi<PR, 1, false, TW, AC>); break;
+        case 2: launch(k_radR_epi<PR, 2, false, TW, AC>); break;
+        case 3: launch(k_radR_epi<PR, 3, false, TW, AC>); break;
+        default: launch(k_radR_epi<PR, 4, false, TW, AC>); break;
+      }
+    };
+    using T_ = std::true_type;
+    using F_ = std::false_type;
+    if (fuse) acf ? by_ne(T_{}, T_{}) : by_ne(T_{}, F_{});
+    else acf ? by_ne(F_{}, T_{}) : by_ne(F_{}, F_{});
   }
   HIP_TRY(hipGetLastError());   // the pass's last workgroup has advanced the counters
   TRY(timed_end(P, T, 1));
@@ -1228,7 +1246,8 @@ int finish_slices(Plan* P, Timing* T) {
 // Whether the next two steps are steady state: matrix-core path, not the first
 // step, slices recorded in both, no ring flush or elastic snapshot in between.
 bool graph_ready(Plan* P, int left, Timing* T) {
-  if (!P->use_graphs || !P->fast || T || left < 2 || P->k < 1 || P->n_photo) return false;
+  if (!P->use_graphs || !P->fast || T || left < 2 || P->k < 1 || (P->n_photo && !P->acf_in_pass))
+    return false;
   if (P->rec_k >= P->k || P->ring_count + 2 > P->ring_len) return false;
   for (auto& pk : P->packets)
     if (!pk.snap_taken && (pk.pk.k_min_elastic == P->k || pk.pk.k_min_elastic == P->k + 1)) return false;
@@ -1252,10 +1271,14 @@ int acf_layout(Plan* P) {
       tot += acf_blocks(pk.n_values);
       ++idx;
     }
+  const bool in_pass = idx > 0 && P->fast && P->pot_mode != TDWP_POT_MLP;
   if (idx) {
     TRY(ensure_staging(P, &P->d_acfpart, &P->acfpart_cap, (size_t)kNormChunk * tot));
-    TRY(ensure_staging(P, &P->d_acf, &P->acf_cap, (size_t)kNormChunk * idx));
+    TRY(ensure_staging(P, &P->d_acf, &P->acf_cap, (size_t)kNormChunk * P->packets.size()));
   }
+  if (in_pass) TRY(ensure_staging(P, &P->d_acfwg, &P->acfwg_cap, (size_t)kNormChunk * P->n_wg_total));
+  if (in_pass != P->acf_in_pass) drop_graphs(P);   // captured steps launch the other R pass
+  P->acf_in_pass = in_pass;
   tot = 0;
   idx = 0;
   for (auto& pk : P->packets) {
@@ -1300,6 +1323,25 @@ int acf_collect(Plan* P, PacketInfo& pk, int rows) {
   return TDWP_OK;
 }
 
+// The R pass's overlap partials of rows [0, rows), summed per packet in the norm
+// partials' fixed order, appended to each photodissociation packet's series.
+int acf_collect_pass(Plan* P, int rows) {
+  const int np = (int)P->packets.size();
+  hipLaunchKernelGGL(k_norm_reduce, dim3((np * rows + 255) / 256), dim3(256), 0, P->stream,
+                     P->d_acf, P->d_acfwg, P->n_wg_total, P->d_wg_off, P->d_n_wg, np, rows);
+  HIP_TRY(hipGetLastError());
+  for (int ip = 0; ip < np; ++ip) {
+    PacketInfo& pk = P->packets[ip];
+    if (!pk.photo) continue;
+    const size_t n0 = pk.acf.size();
+    pk.acf.resize(n0 + rows);
+    HIP_TRY(hipMemcpyAsync(pk.acf.data() + n0, P->d_acf + (size_t)ip * kNormChunk,
+                           rows * sizeof(double), hipMemcpyDeviceToHost, P->stream));
+  }
+  HIP_TRY(hipStreamSynchronize(P->stream));
+  return TDWP_OK;
+}
+
 int run_steps(Plan* P, long n_steps, double* norms_out, Timing* T) {
   if (!P->have_potential) return TDWP_ESTATE;
   for (auto& pk : P->packets)
@@ -1322,7 +1364,7 @@ int run_steps(Plan* P, long n_steps, double* norms_out, Timing* T) {
         s += 2;
       } else {
         TRY(one_step(P, s, T));
-        if (P->n_photo) TRY(acf_enqueue(P, s, T));
+        if (P->n_photo && !P->acf_in_pass) TRY(acf_enqueue(P, s, T));
         s += 1;
       }
     }
@@ -1344,8 +1386,10 @@ int run_steps(Plan* P, long n_steps, double* norms_out, Timing* T) {
         if (!std::isfinite(v) || v > 1e6) bad = true;
         if (norms_out) norms_out[(size_t)p * n_steps + done + s] = v;
       }
-    for (auto& pk : P->packets)
-      if (pk.photo) TRY(acf_collect(P, pk, chunk));
+    if (P->acf_in_pass) TRY(acf_collect_pass(P, chunk));
+    else
+      for (auto& pk : P->packets)
+        if (pk.photo) TRY(acf_collect(P, pk, chunk));
     done += chunk;
     if (bad) return TDWP_ERANGE;
   }
@@ -1367,6 +1411,8 @@ void reset_propagation(Plan* P) {
   }
   P->n_photo = 0;
   P->acf_nb_total = 0;
+  if (P->acf_in_pass) drop_graphs(P);
+  P->acf_in_pass = false;
 }
 
 }  // namespace
@@ -1645,7 +1691,10 @@ int tdwp_set_packet_values(tdwp_plan_t p, int unit, int slot, const double* u0) 
   double s = 0.0;
   for (size_t q = 0; q < n; ++q) s += u0[q] * u0[q];
   if (!(s > 0) || !std::isfinite(s)) return TDWP_EINVAL;
-  TRY(ensure_staging(p, &p->d_u0, &p->u0_cap, p->n_total));
+  if (!p->d_u0) {   // zeros for every packet that is not a photodissociation packet
+    TRY(ensure_staging(p, &p->d_u0, &p->u0_cap, p->n_total));
+    HIP_TRY(hipMemsetAsync(p->d_u0, 0, p->n_total * sizeof(double), p->stream));
+  }
   {   // the autocorrelation buffers for this packet besides the others (no-op if they fit)
     const bool was = p->packets[ip].photo;
     p->packets[ip].photo = true;
