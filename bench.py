@@ -37,13 +37,14 @@ PEAKS = {  # MI355X published dense peaks
 }
 
 
-def kernel_model(spec, name, precision, fused=False):
+def kernel_model(spec, name, precision, fused=False, photo=False):
     """Algorithmic work of one launch of kernel `name` on this single-unit workload:
     (bound, amount, unit, peak).  Flops count the executed multiply-adds of the
     even/odd-split contractions (2 per MAC); bytes count each HBM array the
     kernel must touch once (packet FP64, H-partials FP64 or FP32, potential FP64).
     fused: the r pass shares the angular launch and writes T_r u to a buffer of
-    its own, which the R pass reads."""
+    its own, which the R pass reads.  photo: the R pass also reads u_0 to form the
+    photodissociation overlaps."""
     nr, nR, ng, ne = spec["n_r"], spec["n_R"], spec["n_gamma"], spec["n_elec"]
     n_blk = sum((u["omega_max"] - (0 if u["parity"] * (-1) ** u["J"] == 1 else 1) + 1) * u["n_packets"]
                 for u in spec["units"])
@@ -56,6 +57,8 @@ def kernel_model(spec, name, precision, fused=False):
         flops, byts = values * nR, values * (8 + hb + 8 + hb * ne * (ne + 1) / 2 / (n_blk * ne) + 8)
         if fused:
             byts += values * hb
+        if photo:
+            byts += values * 8
     elif name == "radial_r" and not fused:
         # T_r split: nr flops per value; bytes: u_k, h read and written
         flops, byts = values * nr, values * (8 + 2 * hb)
@@ -441,21 +444,26 @@ def main():
     fused = bool(plan.stat("fuse_r"))
     per_step = {k: v for k, v in kt.items()
                 if not (fused and k == "radial_r") and not (k == "autocorrelation" and v == 0.0)}
+    in_pass = args.photo and not per_step.get("autocorrelation")
     dom = max((k for k in per_step if kernel_model(spec, k, args.precision, fused)),
               key=lambda k: per_step[k])
-    traffic = measured_traffic(dom, args.workload, args.precision)
-    bound, amount, unit, peak, _ = kernel_model(spec, dom, args.precision, fused)
+    traffic = measured_traffic(dom, args.workload, args.precision) if not args.photo else None
+    bound, amount, unit, peak, _ = kernel_model(spec, dom, args.precision, fused, in_pass)
     achieved = amount / (per_step[dom] * 1e-6)
     roofline = dict(bound=bound, achieved=round(achieved, 3), peak=peak, unit=unit,
                     frac=round(achieved / peak, 4), traffic=traffic, kernel=dom,
                     kernel_avg_us=round(per_step[dom], 2),
                     kernels_avg_us={k: round(v, 2) for k, v in per_step.items()})
     acf = None
-    if args.photo and per_step.get("autocorrelation"):
-        _, gb, _, pk_bw, _ = kernel_model(spec, "autocorrelation", args.precision, fused)
-        a_bw = gb / (per_step["autocorrelation"] * 1e-6)
-        acf = dict(kernel_avg_us=round(per_step["autocorrelation"], 2), achieved_GBps=round(a_bw, 1),
-                   frac=round(a_bw / pk_bw, 4))
+    if args.photo:
+        if in_pass:   # formed by the R pass (u_0 read there, 8 bytes per value)
+            acf = dict(formed_in="radial_R_epilogue")
+        else:
+            _, gb, _, pk_bw, _ = kernel_model(spec, "autocorrelation", args.precision, fused)
+            a_bw = gb / (per_step["autocorrelation"] * 1e-6)
+            acf = dict(formed_in="autocorrelation kernel",
+                       kernel_avg_us=round(per_step["autocorrelation"], 2),
+                       achieved_GBps=round(a_bw, 1), frac=round(a_bw / pk_bw, 4))
         acf["spectrum"] = spectrum_timing(plan, args.no_cpu_baseline)
     plan.close()
     fp64_rate = None
