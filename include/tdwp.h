@@ -236,8 +236,9 @@ int tdwp_state_to_state(tdwp_plan_t p, int unit, int slot, int n_ch, const tdwp_
  * caller builds it.  Its energy content is not known in advance and follows from
  * the autocorrelation C_k = <u_0|u_k> of the propagated packet (Eqs.
  * fourier-transform, chebyshev-transform), which the library forms on the
- * device after every step (one extra read of u_0 and u_k per step; HIP-graph
- * replay of steps is off while a plan holds such a packet). */
+ * device after every step: in the R pass on the matrix-core path with a
+ * tabulated potential (one more read of u_0 per step), else in a kernel of its
+ * own (u_0 and u_k read; HIP-graph replay of steps is then off). */
 
 /* Installs packet (unit, slot) from caller values u0 (host, the layout of
  * tdwp_get_packet: DVR-weighted coefficients, not normalised by the library)

@@ -1,7 +1,9 @@
 // Autocorrelation of photodissociation packets: C_k = <u_0|u_k> of every step
-// (the overlap of Eqs. fourier-transform and chebyshev-transform).  One launch
-// per packet and step writes per-workgroup partial sums; the rows of a chunk of
-// steps are summed in a fixed order when the chunk's norms are read back.
+// (the overlap of Eqs. fourier-transform and chebyshev-transform), where the R
+// pass does not form it (general kernels, learned-potential pass) and for C_0.
+// One launch per packet and step writes per-workgroup partial sums; the rows of
+// a chunk of steps are summed in a fixed order when the chunk's norms are read
+// back.
 #pragma once
 #include <hip/hip_runtime.h>
 
