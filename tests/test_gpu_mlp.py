@@ -107,6 +107,18 @@ def test_mlp_training_and_on_the_fly_step():
     reltab = np.max(np.abs(um - ut)) / np.max(np.abs(ut))
     print(f"[result] on-the-fly vs table-of-network packet rel {rel:.2e}; vs true table {reltab:.2e}",
           flush=True)
+    # photodissociation packets: the learned-potential plan forms the overlaps in a
+    # kernel of its own, the tabulated plan in its R pass; the series agree
+    from workloads.photo import photo_packet
+    u0 = photo_packet(spec, 0, *plan_m.grid())
+    for p in (plan_m, plan_n):
+        p.set_packet_values(0, 0, u0)
+        p.propagate(K, norms=False)
+    cm, cn = plan_m.autocorrelation(0, 0), plan_n.autocorrelation(0, 0)
+    relc = float(np.max(np.abs(cm - cn)) / cn[0])
+    print(f"[result] photodissociation overlaps, network pass vs tabulated R pass: rel {relc:.2e}",
+          flush=True)
     for p in (plan_m, plan_n, plan_t):
         p.close()
     assert rel < 1e-12
+    assert cm.shape == (K + 1,) and relc < 1e-12
