@@ -248,6 +248,17 @@ int tdwp_state_to_state(tdwp_plan_t p, int unit, int slot, int n_ch, const tdwp_
  * Errors: EINVAL (no such packet, u0 zero or not finite), ESTATE (no potential). */
 int tdwp_set_packet_values(tdwp_plan_t p, int unit, int slot, const double* u0);
 
+/* out = H in for packet (unit, slot): the plan's Hamiltonian (Eq. hamiltonian,
+ * with its radial and rotational caps, the potential installed, no damping)
+ * applied by the step kernels in the plan's precision.  in, out: host arrays in
+ * the packet layout.  This is the H u of the preparatory stage's bound-state
+ * calculation (an iterative Lanczos method on the same grid, Sec. "Initial wave
+ * packet in photodissociation"), which callers build on this call.  The packet
+ * buffers are its scratch: no packet may be installed (TDWP_ESTATE otherwise),
+ * and none is after it.  Errors: EINVAL (no such packet), ESTATE (no potential,
+ * or a packet installed). */
+int tdwp_apply_hamiltonian(tdwp_plan_t p, int unit, int slot, const double* in, double* out);
+
 /* Copies C_0 .. C_{n-1} of photodissociation packet (unit, slot), C_k = <u_0|u_k>
  * in FP64 over the whole packet; n <= k + 1 with k the plan's step index.
  * Errors: EINVAL (no such packet, n out of range), ESTATE (not a

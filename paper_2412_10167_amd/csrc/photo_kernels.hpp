@@ -52,4 +52,12 @@ __global__ void k_rows_sum(const double* __restrict__ part, size_t stride, int n
   out[r] = s;
 }
 
+// out[i] = a out[i] + b in[i]: H u = dE (H_s u) + E0 u from a step's H_s u.
+__global__ void k_affine(double* __restrict__ out, const double* __restrict__ in, double a,
+                         double b, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    out[i] = a * out[i] + b * in[i];
+}
+
 }  // namespace tdwp

@@ -164,6 +164,8 @@ struct tdwp_plan_s {
   double* d_acfwg = nullptr;      // [kNormChunk][n_wg_total] overlaps formed by the R pass
   size_t acfwg_cap = 0;
   bool acf_in_pass = false;       // the R pass forms the overlaps (else a kernel of its own)
+  double* d_ones = nullptr;       // ones in place of the damping factors (H applied alone)
+  size_t ones_cap = 0;
   double* d_g = nullptr;          // [n_packets][n_R]
   // batched-launch index maps (one launch per pass covers every packet)
   void* d_pkdesc = nullptr;       // PkDesc[n_packets]

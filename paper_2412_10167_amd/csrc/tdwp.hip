@@ -1740,6 +1740,51 @@ int tdwp_set_packet_values(tdwp_plan_t p, int unit, int slot, const double* u0) 
   return TDWP_OK;
 }
 
+int tdwp_apply_hamiltonian(tdwp_plan_t p, int unit, int slot, const double* in, double* out) {
+  if (!p || !in || !out) return TDWP_EINVAL;
+  if (!p->have_potential) return TDWP_ESTATE;
+  int ip = -1;
+  for (size_t i = 0; i < p->packets.size(); ++i)
+    if (p->packets[i].unit == unit && p->packets[i].slot == slot) ip = (int)i;
+  if (ip < 0) return TDWP_EINVAL;
+  for (auto& pk : p->packets)
+    if (pk.set) return TDWP_ESTATE;   // the packet buffers are the scratch of this call
+  if (!p->d_ones) {
+    const std::vector<double> ones((size_t)p->nR * p->nr + p->nR + p->nr, 1.0);
+    TRY(alloc_copy(p, &p->d_ones, ones));
+    p->ones_cap = ones.size();
+  }
+  const PacketInfo& P = p->packets[ip];
+  const size_t n = P.n_values;
+  reset_propagation(p);
+  HIP_TRY(hipMemsetAsync(p->d_u[0], 0, p->n_total * sizeof(double), p->stream));
+  HIP_TRY(hipMemsetAsync(p->d_u[1], 0, p->n_total * sizeof(double), p->stream));
+  HIP_TRY(hipMemcpyAsync(p->d_u[p->cur] + P.off, in, n * sizeof(double), hipMemcpyHostToDevice,
+                         p->stream));
+  // the first step with the damping factors set to one leaves H_s u in the new buffer
+  double* const keep_D = p->d_D;
+  double* const keep_Dsep = p->d_Dsep;
+  p->d_D = p->d_ones;
+  p->d_Dsep = p->d_ones;
+  int st = p->fast ? sync_counters(p) : TDWP_OK;
+  if (st == TDWP_OK) st = one_step(p, 0, nullptr);
+  p->d_D = keep_D;
+  p->d_Dsep = keep_Dsep;
+  if (st == TDWP_OK) {
+    hipLaunchKernelGGL(k_affine, dim3((unsigned)std::min<size_t>((n + 255) / 256, 4096)), dim3(256),
+                       0, p->stream, p->d_u[p->cur] + P.off, p->d_u[1 - p->cur] + P.off, p->dE,
+                       p->E0, n);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(out, p->d_u[p->cur] + P.off, n * sizeof(double), hipMemcpyDeviceToHost,
+                         p->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+    if (e != hipSuccess) st = hip_fail(e, "tdwp_apply_hamiltonian", __LINE__);
+  }
+  reset_propagation(p);
+  return st;
+}
+
 int tdwp_autocorrelation(tdwp_plan_t p, int unit, int slot, long n, double* out) {
   if (!p || n < 0 || (n > 0 && !out)) return TDWP_EINVAL;
   for (auto& pk : p->packets)

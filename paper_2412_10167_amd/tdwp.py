@@ -20,7 +20,7 @@ EXPORTED_SYMBOLS = (
     "tdwp_set_option", "tdwp_get_stat", "tdwp_jshift", "tdwp_jshift_interpolate",
     "tdwp_cumulative_probability", "tdwp_cross_section", "tdwp_fit_jshift_b",
     "tdwp_set_packet_values", "tdwp_autocorrelation", "tdwp_energy_content",
-    "tdwp_photo_cross_section",
+    "tdwp_photo_cross_section", "tdwp_apply_hamiltonian",
 )
 OPTIONS = {"graphs": 0, "ang_tile": 1, "radial_grid": 2, "ang_kernel": 3, "fuse_r": 4,
            "ang_xcd": 5}
@@ -137,6 +137,7 @@ def load_library():
     cl = ctypes.c_long
     lib.tdwp_set_packet_values.argtypes = [P, ci, ci, dp]
     lib.tdwp_autocorrelation.argtypes = [P, ci, ci, cl, dp]
+    lib.tdwp_apply_hamiltonian.argtypes = [P, ci, ci, dp, dp]
     lib.tdwp_energy_content.argtypes = [dp, cl, cd, cd, dp, ci, dp]
     lib.tdwp_photo_cross_section.argtypes = [dp, cl, cd, cd, cd, dp, ci, dp]
     lib.tdwp_destroy.restype = None
@@ -295,6 +296,19 @@ class Plan:
             raise ValueError(f"packet of unit {unit} has {n} values, got {u.size}")
         _check(self.lib.tdwp_set_packet_values(self.handle, unit, slot, _ptr(u)),
                "tdwp_set_packet_values")
+
+    def apply_hamiltonian(self, u, unit=0, slot=0):
+        """H u (undamped) for a vector in the layout of packet (unit, slot); no packet
+        may be installed."""
+        x = _f64(u).ravel()
+        n = self.n_omega(unit) * self.spec["n_elec"] * self.spec["n_gamma"] * self.spec["n_R"] \
+            * self.spec["n_r"]
+        if x.size != n:
+            raise ValueError(f"packet of unit {unit} has {n} values, got {x.size}")
+        out = np.empty_like(x)
+        _check(self.lib.tdwp_apply_hamiltonian(self.handle, unit, slot, _ptr(x), _ptr(out)),
+               "tdwp_apply_hamiltonian")
+        return out.reshape(np.shape(u))
 
     def autocorrelation(self, unit=0, slot=0, n=None):
         """C_0 .. C_{n-1} = <u_0|u_k> of a photodissociation packet (default: up to the
