@@ -259,6 +259,21 @@ int tdwp_set_packet_values(tdwp_plan_t p, int unit, int slot, const double* u0);
  * or a packet installed). */
 int tdwp_apply_hamiltonian(tdwp_plan_t p, int unit, int slot, const double* in, double* out);
 
+/* Lowest eigenstate of the plan's H in the space of packet (unit, slot), by a
+ * Lanczos iteration without reorthogonalisation (the method of the preparatory
+ * stage's bound-state program, Sec. "Initial wave packet in photodissociation")
+ * of n_iter >= 2 steps from the host vector guess (packet layout, not zero),
+ * with a second pass that rebuilds the Lanczos vectors for the Ritz vector;
+ * H u as in tdwp_apply_hamiltonian, three device vectors besides the packet
+ * buffers.  energy: the Rayleigh quotient of the normalised Ritz vector; psi
+ * (may be NULL): that vector, DVR-normalised (sum psi^2 = 1); residual (may be
+ * NULL): |H psi - energy psi|.  The packet buffers are its scratch, as for
+ * tdwp_apply_hamiltonian.  Errors: EINVAL (no such packet, n_iter < 2, zero or
+ * non-finite guess), ESTATE (no potential, or a packet installed), ERANGE (the
+ * Ritz vector vanished). */
+int tdwp_lowest_state(tdwp_plan_t p, int unit, int slot, const double* guess, int n_iter,
+                      double* energy, double* psi, double* residual);
+
 /* Copies C_0 .. C_{n-1} of photodissociation packet (unit, slot), C_k = <u_0|u_k>
  * in FP64 over the whole packet; n <= k + 1 with k the plan's step index.
  * Errors: EINVAL (no such packet, n out of range), ESTATE (not a

@@ -14,6 +14,8 @@ oracle/tdwp_oracle.py (Sec. 2.2, Eq. wvp-k).
                    chebyshev-transform.
   cross_section    sigma(h nu) = A h nu / (2 pi) sum_k 2 Re[c_k(H_s, E) C_k],
                    E = E_i + h nu (Eq. spectrum).
+  lowest_state     the lowest eigenpair of the dense H (the initial bound state's
+                   definition; the paper finds it with a Lanczos method).
 
 Readings (each also listed in the design notes):
   * The components C_k of a real packet under the real recursion are real, so
@@ -63,6 +65,16 @@ def autocorrelation(op, unit_index, u0, K, undamped=False, damping=None):
         u_prev, u = u, u_next
         C[k + 1] = float(np.sum(u0 * u))
     return C
+
+
+def lowest_state(op, unit_index):
+    """Lowest eigenpair of the dense H of one unit (the bound state the preparatory
+    stage finds iteratively), by a library symmetric eigensolver: (E, psi) with psi
+    DVR-normalised and its largest component positive."""
+    lam, V = np.linalg.eigh(O.dense_H(op, unit_index))
+    psi = V[:, 0]
+    psi = psi * np.sign(psi[np.argmax(np.abs(psi))])
+    return float(lam[0]), psi.reshape(op.unit_shape(unit_index))
 
 
 def _re_ck(E, e_min, e_max, K):

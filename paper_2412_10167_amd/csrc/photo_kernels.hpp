@@ -60,4 +60,17 @@ __global__ void k_affine(double* __restrict__ out, const double* __restrict__ in
     out[i] = a * out[i] + b * in[i];
 }
 
+// y = a y + b x + c z (y may alias x; y is not read when a = 0, z not when c = 0):
+// the vector updates of the bound-state Lanczos iteration.
+__global__ void k_lincomb(double* y, double a, const double* x, double b, const double* z,
+                          double c, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x) {
+    double v = b * x[i];
+    if (a != 0.0) v += a * y[i];
+    if (c != 0.0) v += c * z[i];
+    y[i] = v;
+  }
+}
+
 }  // namespace tdwp

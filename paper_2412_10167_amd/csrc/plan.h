@@ -166,6 +166,10 @@ struct tdwp_plan_s {
   bool acf_in_pass = false;       // the R pass forms the overlaps (else a kernel of its own)
   double* d_ones = nullptr;       // ones in place of the damping factors (H applied alone)
   size_t ones_cap = 0;
+  double* d_lz = nullptr;         // vectors of H u and of the bound-state Lanczos iteration
+  size_t lz_cap = 0;
+  double* d_dotpart = nullptr;    // partial sums of a dot product, then its sum
+  size_t dotpart_cap = 0;
   double* d_g = nullptr;          // [n_packets][n_R]
   // batched-launch index maps (one launch per pass covers every packet)
   void* d_pkdesc = nullptr;       // PkDesc[n_packets]

@@ -1323,6 +1323,165 @@ int acf_collect(Plan* P, PacketInfo& pk, int rows) {
   return TDWP_OK;
 }
 
+// Sum of a[i] b[i] over n values (device arrays), to the host.
+int dev_dot(Plan* P, const double* a, const double* b, size_t n, double* out) {
+  const int nb = acf_blocks(n);
+  TRY(ensure_staging(P, &P->d_dotpart, &P->dotpart_cap, (size_t)nb + 1));
+  hipLaunchKernelGGL(k_dot_partial, dim3(nb), dim3(kAcfThreads), 0, P->stream, a, b, n,
+                     P->d_dotpart);
+  hipLaunchKernelGGL(k_rows_sum, dim3(1), dim3(256), 0, P->stream, P->d_dotpart, (size_t)nb, nb, 1,
+                     P->d_dotpart + nb);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(out, P->d_dotpart + nb, sizeof(double), hipMemcpyDeviceToHost, P->stream));
+  HIP_TRY(hipStreamSynchronize(P->stream));
+  return TDWP_OK;
+}
+
+// y = a y + b x + c z on the device (z may be null when c = 0).
+int dev_axpbypcz(Plan* P, double* y, double a, const double* x, double b, const double* z,
+                 double c, size_t n) {
+  hipLaunchKernelGGL(k_lincomb, dim3((unsigned)std::min<size_t>((n + 255) / 256, 4096)), dim3(256),
+                     0, P->stream, y, a, x, b, z, c, n);
+  HIP_TRY(hipGetLastError());
+  return TDWP_OK;
+}
+
+// Lowest eigenvalue of the symmetric tridiagonal matrix (diagonal al[0..m-1],
+// off-diagonal be[1..m-1]) by bisection on the Sturm count.
+double tridiag_lowest(const std::vector<double>& al, const std::vector<double>& be, int m) {
+  double lo = al[0], hi = al[0];
+  for (int i = 0; i < m; ++i) {
+    const double r = (i ? std::fabs(be[i]) : 0.0) + (i + 1 < m ? std::fabs(be[i + 1]) : 0.0);
+    lo = std::min(lo, al[i] - r);
+    hi = std::max(hi, al[i] + r);
+  }
+  auto below = [&](double x) {   // eigenvalues < x
+    int cnt = 0;
+    double d = 1.0;
+    for (int i = 0; i < m; ++i) {
+      const double b2 = i ? be[i] * be[i] : 0.0;
+      d = (al[i] - x) - (i ? b2 / d : 0.0);
+      if (d == 0.0) d = -1e-300;
+      if (d < 0) ++cnt;
+    }
+    return cnt;
+  };
+  for (int it = 0; it < 200 && hi - lo > 1e-15 * std::max(std::fabs(lo), std::fabs(hi)); ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (below(mid) >= 1) hi = mid;
+    else lo = mid;
+  }
+  return 0.5 * (lo + hi);
+}
+
+// Eigenvector of the tridiagonal matrix for eigenvalue lam: inverse iteration with
+// Gaussian elimination and row pivoting on (T - lam I), normalised.
+std::vector<double> tridiag_vector(const std::vector<double>& al, const std::vector<double>& be,
+                                   int m, double lam) {
+  double scale = 0.0;
+  for (int i = 0; i < m; ++i) scale = std::max(scale, std::fabs(al[i]) + (i ? std::fabs(be[i]) : 0));
+  const double shift = lam - 1e-13 * std::max(scale, 1e-300);
+  std::vector<double> y(m, 1.0), dl(m), d(m), du(m), du2(m);
+  std::vector<int> piv(m);
+  // LU with partial pivoting of the tridiagonal (T - shift I), as in a banded solver
+  for (int i = 0; i < m; ++i) {
+    d[i] = al[i] - shift;
+    du[i] = i + 1 < m ? be[i + 1] : 0.0;
+    dl[i] = i + 1 < m ? be[i + 1] : 0.0;
+    du2[i] = 0.0;
+  }
+  for (int i = 0; i + 1 < m; ++i) {
+    if (std::fabs(d[i]) >= std::fabs(dl[i])) {   // no interchange
+      piv[i] = 0;
+      const double f = d[i] != 0.0 ? dl[i] / d[i] : 0.0;
+      dl[i] = f;
+      d[i + 1] -= f * du[i];
+    } else {   // interchange rows i and i+1
+      piv[i] = 1;
+      const double f = d[i] / dl[i];
+      d[i] = dl[i];
+      dl[i] = f;
+      const double t = du[i];
+      du[i] = d[i + 1];
+      d[i + 1] = t - f * d[i + 1];
+      du2[i] = i + 2 < m ? du[i + 1] : 0.0;
+      if (i + 2 < m) du[i + 1] = -f * du[i + 1];
+    }
+  }
+  if (d[m - 1] == 0.0) d[m - 1] = 1e-300;
+  for (int it = 0; it < 4; ++it) {
+    for (int i = 0; i + 1 < m; ++i) {   // forward: apply L^-1 with the interchanges
+      if (piv[i]) std::swap(y[i], y[i + 1]);
+      y[i + 1] -= dl[i] * y[i];
+    }
+    for (int i = m - 1; i >= 0; --i) {   // back: U^-1 (diagonal, two superdiagonals)
+      double v = y[i];
+      if (i + 1 < m) v -= du[i] * y[i + 1];
+      if (i + 2 < m) v -= du2[i] * y[i + 2];
+      y[i] = v / (d[i] != 0.0 ? d[i] : 1e-300);
+    }
+    double nrm = 0.0;
+    for (double v : y) nrm += v * v;
+    nrm = std::sqrt(nrm);
+    for (double& v : y) v /= nrm;
+  }
+  return y;
+}
+
+// Checks for the calls that use the packet buffers as scratch (H applied alone):
+// potential installed, packet (unit, slot) exists (its index in *ip), none set.
+int h_scratch_ready(Plan* P, int unit, int slot, int* ip) {
+  if (!P->have_potential) return TDWP_ESTATE;
+  *ip = -1;
+  for (size_t i = 0; i < P->packets.size(); ++i)
+    if (P->packets[i].unit == unit && P->packets[i].slot == slot) *ip = (int)i;
+  if (*ip < 0) return TDWP_EINVAL;
+  for (auto& pk : P->packets)
+    if (pk.set) return TDWP_ESTATE;
+  if (!P->d_ones) {
+    const std::vector<double> ones((size_t)P->nR * P->nr + P->nR + P->nr, 1.0);
+    TRY(alloc_copy(P, &P->d_ones, ones));
+    P->ones_cap = ones.size();
+  }
+  return TDWP_OK;
+}
+
+int one_step(Plan* P, int chunk_row, Timing* T);
+void reset_propagation(Plan* P);
+
+// out = H in for packet ip (device arrays of its size, outside the packet
+// buffers): the first step of the plan with the damping factors set to one
+// leaves H_s in in the new buffer, and H in = dE H_s in + E0 in.
+int apply_h_dev(Plan* p, int ip, const double* in, double* out) {
+  const PacketInfo& P = p->packets[ip];
+  const size_t n = P.n_values;
+  reset_propagation(p);
+  HIP_TRY(hipMemsetAsync(p->d_u[0], 0, p->n_total * sizeof(double), p->stream));
+  HIP_TRY(hipMemsetAsync(p->d_u[1], 0, p->n_total * sizeof(double), p->stream));
+  HIP_TRY(hipMemcpyAsync(p->d_u[p->cur] + P.off, in, n * sizeof(double), hipMemcpyDeviceToDevice,
+                         p->stream));
+  double* const keep_D = p->d_D;
+  double* const keep_Dsep = p->d_Dsep;
+  p->d_D = p->d_ones;
+  p->d_Dsep = p->d_ones;
+  int st = p->fast ? sync_counters(p) : TDWP_OK;
+  if (st == TDWP_OK) st = one_step(p, 0, nullptr);
+  p->d_D = keep_D;
+  p->d_Dsep = keep_Dsep;
+  if (st == TDWP_OK) {
+    hipLaunchKernelGGL(k_affine, dim3((unsigned)std::min<size_t>((n + 255) / 256, 4096)), dim3(256),
+                       0, p->stream, p->d_u[p->cur] + P.off, p->d_u[1 - p->cur] + P.off, p->dE,
+                       p->E0, n);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(out, p->d_u[p->cur] + P.off, n * sizeof(double), hipMemcpyDeviceToDevice,
+                         p->stream);
+    if (e != hipSuccess) st = hip_fail(e, "apply_h_dev", __LINE__);
+  }
+  reset_propagation(p);
+  return st;
+}
+
 // The R pass's overlap partials of rows [0, rows), summed per packet in the norm
 // partials' fixed order, appended to each photodissociation packet's series.
 int acf_collect_pass(Plan* P, int rows) {
@@ -1742,47 +1901,96 @@ int tdwp_set_packet_values(tdwp_plan_t p, int unit, int slot, const double* u0) 
 
 int tdwp_apply_hamiltonian(tdwp_plan_t p, int unit, int slot, const double* in, double* out) {
   if (!p || !in || !out) return TDWP_EINVAL;
-  if (!p->have_potential) return TDWP_ESTATE;
   int ip = -1;
-  for (size_t i = 0; i < p->packets.size(); ++i)
-    if (p->packets[i].unit == unit && p->packets[i].slot == slot) ip = (int)i;
-  if (ip < 0) return TDWP_EINVAL;
-  for (auto& pk : p->packets)
-    if (pk.set) return TDWP_ESTATE;   // the packet buffers are the scratch of this call
-  if (!p->d_ones) {
-    const std::vector<double> ones((size_t)p->nR * p->nr + p->nR + p->nr, 1.0);
-    TRY(alloc_copy(p, &p->d_ones, ones));
-    p->ones_cap = ones.size();
-  }
+  TRY(h_scratch_ready(p, unit, slot, &ip));
   const PacketInfo& P = p->packets[ip];
   const size_t n = P.n_values;
-  reset_propagation(p);
-  HIP_TRY(hipMemsetAsync(p->d_u[0], 0, p->n_total * sizeof(double), p->stream));
-  HIP_TRY(hipMemsetAsync(p->d_u[1], 0, p->n_total * sizeof(double), p->stream));
-  HIP_TRY(hipMemcpyAsync(p->d_u[p->cur] + P.off, in, n * sizeof(double), hipMemcpyHostToDevice,
-                         p->stream));
-  // the first step with the damping factors set to one leaves H_s u in the new buffer
-  double* const keep_D = p->d_D;
-  double* const keep_Dsep = p->d_Dsep;
-  p->d_D = p->d_ones;
-  p->d_Dsep = p->d_ones;
-  int st = p->fast ? sync_counters(p) : TDWP_OK;
-  if (st == TDWP_OK) st = one_step(p, 0, nullptr);
-  p->d_D = keep_D;
-  p->d_Dsep = keep_Dsep;
+  TRY(ensure_staging(p, &p->d_lz, &p->lz_cap, 4 * n));
+  HIP_TRY(hipMemcpyAsync(p->d_lz, in, n * sizeof(double), hipMemcpyHostToDevice, p->stream));
+  int st = apply_h_dev(p, ip, p->d_lz, p->d_lz + n);
   if (st == TDWP_OK) {
-    hipLaunchKernelGGL(k_affine, dim3((unsigned)std::min<size_t>((n + 255) / 256, 4096)), dim3(256),
-                       0, p->stream, p->d_u[p->cur] + P.off, p->d_u[1 - p->cur] + P.off, p->dE,
-                       p->E0, n);
-    hipError_t e = hipGetLastError();
-    if (e == hipSuccess)
-      e = hipMemcpyAsync(out, p->d_u[p->cur] + P.off, n * sizeof(double), hipMemcpyDeviceToHost,
-                         p->stream);
+    hipError_t e = hipMemcpyAsync(out, p->d_lz + n, n * sizeof(double), hipMemcpyDeviceToHost,
+                                  p->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
     if (e != hipSuccess) st = hip_fail(e, "tdwp_apply_hamiltonian", __LINE__);
   }
-  reset_propagation(p);
   return st;
+}
+
+int tdwp_lowest_state(tdwp_plan_t p, int unit, int slot, const double* guess, int n_iter,
+                      double* energy, double* psi, double* residual) {
+  if (!p || !guess || !energy || n_iter < 2) return TDWP_EINVAL;
+  int ip = -1;
+  TRY(h_scratch_ready(p, unit, slot, &ip));
+  const size_t n = p->packets[ip].n_values;
+  TRY(ensure_staging(p, &p->d_lz, &p->lz_cap, 4 * n));
+  double* q = p->d_lz;          // q_j
+  double* w = p->d_lz + n;      // H q_j, then the next residual
+  double* qp = p->d_lz + 2 * n; // q_{j-1}
+  double* x = p->d_lz + 3 * n;  // Ritz vector
+  // Lanczos without reorthogonalisation (as the preparatory stage's bound-state
+  // program does), from the normalised guess; a second pass rebuilds the q_j for
+  // the Ritz vector, so only three vectors are kept.
+  auto restart = [&](double* nrm_out) -> int {
+    HIP_TRY(hipMemcpyAsync(q, guess, n * sizeof(double), hipMemcpyHostToDevice, p->stream));
+    HIP_TRY(hipMemsetAsync(qp, 0, n * sizeof(double), p->stream));
+    double s = 0.0;
+    TRY(dev_dot(p, q, q, n, &s));
+    if (!(s > 0) || !std::isfinite(s)) return TDWP_EINVAL;
+    TRY(dev_axpbypcz(p, q, 1.0 / std::sqrt(s), q, 0.0, nullptr, 0.0, n));
+    if (nrm_out) *nrm_out = s;
+    return TDWP_OK;
+  };
+  std::vector<double> al, be(1, 0.0);
+  TRY(restart(nullptr));
+  for (int j = 0; j < n_iter; ++j) {
+    TRY(apply_h_dev(p, ip, q, w));
+    double a = 0.0;
+    TRY(dev_dot(p, w, q, n, &a));
+    TRY(dev_axpbypcz(p, w, 1.0, q, -a, qp, -be[j], n));   // w = H q - a q - b qp
+    double b2 = 0.0;
+    TRY(dev_dot(p, w, w, n, &b2));
+    al.push_back(a);
+    const double b = std::sqrt(b2);
+    if (j + 1 == n_iter || !(b > 1e-14 * std::fabs(a))) break;   // invariant subspace found
+    be.push_back(b);
+    TRY(dev_axpbypcz(p, qp, 0.0, q, 1.0, nullptr, 0.0, n));      // qp = q
+    TRY(dev_axpbypcz(p, q, 0.0, w, 1.0 / b, nullptr, 0.0, n));   // q = w / b
+  }
+  const int m = (int)al.size();
+  const double lam = tridiag_lowest(al, be, m);
+  const std::vector<double> y = tridiag_vector(al, be, m, lam);
+  // second pass: x = sum_j y_j q_j with the same recursion coefficients
+  TRY(restart(nullptr));
+  HIP_TRY(hipMemsetAsync(x, 0, n * sizeof(double), p->stream));
+  for (int j = 0; j < m; ++j) {
+    TRY(dev_axpbypcz(p, x, 1.0, q, y[j], nullptr, 0.0, n));
+    if (j + 1 == m) break;
+    TRY(apply_h_dev(p, ip, q, w));
+    TRY(dev_axpbypcz(p, w, 1.0, q, -al[j], qp, -be[j], n));
+    TRY(dev_axpbypcz(p, qp, 0.0, q, 1.0, nullptr, 0.0, n));
+    TRY(dev_axpbypcz(p, q, 0.0, w, 1.0 / be[j + 1], nullptr, 0.0, n));
+  }
+  double xx = 0.0;
+  TRY(dev_dot(p, x, x, n, &xx));
+  if (!(xx > 0) || !std::isfinite(xx)) return TDWP_ERANGE;
+  TRY(dev_axpbypcz(p, x, 1.0 / std::sqrt(xx), x, 0.0, nullptr, 0.0, n));
+  // Rayleigh quotient and residual of the normalised Ritz vector
+  TRY(apply_h_dev(p, ip, x, w));
+  double e = 0.0;
+  TRY(dev_dot(p, x, w, n, &e));
+  *energy = e;
+  if (residual) {
+    TRY(dev_axpbypcz(p, w, 1.0, x, -e, nullptr, 0.0, n));
+    double r2 = 0.0;
+    TRY(dev_dot(p, w, w, n, &r2));
+    *residual = std::sqrt(r2);
+  }
+  if (psi) {
+    HIP_TRY(hipMemcpyAsync(psi, x, n * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+    HIP_TRY(hipStreamSynchronize(p->stream));
+  }
+  return TDWP_OK;
 }
 
 int tdwp_autocorrelation(tdwp_plan_t p, int unit, int slot, long n, double* out) {

@@ -20,7 +20,7 @@ EXPORTED_SYMBOLS = (
     "tdwp_set_option", "tdwp_get_stat", "tdwp_jshift", "tdwp_jshift_interpolate",
     "tdwp_cumulative_probability", "tdwp_cross_section", "tdwp_fit_jshift_b",
     "tdwp_set_packet_values", "tdwp_autocorrelation", "tdwp_energy_content",
-    "tdwp_photo_cross_section", "tdwp_apply_hamiltonian",
+    "tdwp_photo_cross_section", "tdwp_apply_hamiltonian", "tdwp_lowest_state",
 )
 OPTIONS = {"graphs": 0, "ang_tile": 1, "radial_grid": 2, "ang_kernel": 3, "fuse_r": 4,
            "ang_xcd": 5}
@@ -138,6 +138,7 @@ def load_library():
     lib.tdwp_set_packet_values.argtypes = [P, ci, ci, dp]
     lib.tdwp_autocorrelation.argtypes = [P, ci, ci, cl, dp]
     lib.tdwp_apply_hamiltonian.argtypes = [P, ci, ci, dp, dp]
+    lib.tdwp_lowest_state.argtypes = [P, ci, ci, dp, ci, dp, dp, dp]
     lib.tdwp_energy_content.argtypes = [dp, cl, cd, cd, dp, ci, dp]
     lib.tdwp_photo_cross_section.argtypes = [dp, cl, cd, cd, cd, dp, ci, dp]
     lib.tdwp_destroy.restype = None
@@ -309,6 +310,17 @@ class Plan:
         _check(self.lib.tdwp_apply_hamiltonian(self.handle, unit, slot, _ptr(x), _ptr(out)),
                "tdwp_apply_hamiltonian")
         return out.reshape(np.shape(u))
+
+    def lowest_state(self, guess, n_iter=300, unit=0, slot=0):
+        """(energy, psi, residual) of the lowest eigenstate of H in the space of packet
+        (unit, slot), by the library's Lanczos iteration from `guess`."""
+        g = _f64(guess).ravel()
+        psi = np.empty_like(g)
+        e, r = ctypes.c_double(), ctypes.c_double()
+        _check(self.lib.tdwp_lowest_state(self.handle, unit, slot, _ptr(g), n_iter,
+                                          ctypes.byref(e), _ptr(psi), ctypes.byref(r)),
+               "tdwp_lowest_state")
+        return e.value, psi.reshape(np.shape(guess)), r.value
 
     def autocorrelation(self, unit=0, slot=0, n=None):
         """C_0 .. C_{n-1} = <u_0|u_k> of a photodissociation packet (default: up to the

@@ -101,3 +101,27 @@ def test_apply_hamiltonian_order_and_propagation_after_it():
     run = O.propagate(op, 0, O.initial_packet(op, 0, pk, chi[0]), K, keep_vectors=(K,))
     ref = run["vectors"][K]
     assert float(np.max(np.abs(got - ref)) / np.max(np.abs(ref))) < 1e-10
+
+
+@pytest.mark.parametrize("name, spec_fn, n_iter", [
+    ("J=0 16x12x6 (matrix-core kernels)", lambda: small_variant(1, n_R=16, n_r=12, n_gamma=6), 400),
+    ("J=1 Omega 0..1, 2 states, 13x11x5 (general kernels)",
+     lambda: _coriolis_spec(1, -1, 1, 2, 13, 11, 5), 400),
+])
+def test_lowest_state_matches_dense_eigensolver(name, spec_fn, n_iter):
+    banner(f"bound state by the library's Lanczos iteration: {name}, {n_iter} steps")
+    from oracle import photo_oracle as PH
+    spec = spec_fn()
+    plan = _bare_plan(spec, "fp64")
+    lo, hi = plan.spectral_bounds()
+    op = O.Operator(spec, bounds=(lo, hi))
+    guess = np.random.default_rng(5).standard_normal(op.unit_shape(0))
+    E, psi, res = plan.lowest_state(guess, n_iter=n_iter)
+    plan.close()
+    E_ref, psi_ref = PH.lowest_state(op, 0)
+    ov = abs(float(np.sum(psi * psi_ref)))
+    print(f"[result] E {E:.12f} vs dense {E_ref:.12f} (rel {abs(E - E_ref) / abs(E_ref):.1e}); "
+          f"|<psi|psi_ref>| = {ov:.12f}; residual {res:.1e}", flush=True)
+    assert abs(E - E_ref) <= 1e-9 * abs(E_ref)
+    assert ov > 1 - 1e-8
+    assert res < 1e-5 * abs(E_ref)
