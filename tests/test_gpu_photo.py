@@ -189,3 +189,49 @@ def test_photo_packet_errors():
     with pytest.raises(TdwpError):
         plan.autocorrelation(0, 0, n=5)                       # beyond the current step
     plan.close()
+
+
+def test_photodissociation_from_a_lanczos_bound_state():
+    banner("photodissociation: Lanczos bound state on a ground-state well, times the dipole, "
+           "propagated; J=0 24x20x10 fp64")
+    from paper_2412_10167_amd.tdwp import Plan
+    from workloads.photo import bound_spec, dipole_times, ground_state_table
+    spec = small_variant(1, n_R=24, n_r=20, n_gamma=10)
+    bspec = bound_spec(spec)
+    bplan = Plan(bspec)
+    r, R, x, _ = bplan.grid()
+    bplan.set_potential(ground_state_table(bspec, r, R, x))
+    guess = np.exp(-((R[:, None] - 3.0) / 0.5) ** 2 - ((r[None, :] - 1.4) / 0.3) ** 2)
+    guess = np.broadcast_to(guess, (len(x),) + guess.shape).copy()
+    E_i, psi, res = bplan.lowest_state(guess, n_iter=300)
+    bplan.close()
+    psi = psi * np.sign(psi.flat[np.argmax(np.abs(psi))])
+    opb0 = O.Operator(bspec)
+    opb = O.Operator(bspec, vtable=ground_state_table(bspec, opb0.r, opb0.R, opb0.x))
+    E_ref, psi_ref = PH.lowest_state(opb, 0)
+    ov = abs(float(np.sum(psi * psi_ref.reshape(psi.shape))))
+    print(f"[result] bound state E {E_i:.12f} vs dense {E_ref:.12f}; overlap {ov:.12f}; "
+          f"residual {res:.1e}", flush=True)
+    assert abs(E_i - E_ref) <= 1e-9 * abs(E_ref) and ov > 1 - 1e-8
+    # the photodissociation packet from each side's bound state
+    plan = _photo_plan(spec)
+    rr, RR, xx, _ = plan.grid()
+    u_dev = dipole_times(spec, 0, rr, RR, xx, psi)
+    plan.set_packet_values(0, 0, u_dev)
+    K = 120
+    plan.propagate(K, norms=False)
+    C = plan.autocorrelation(0, 0)
+    lo, hi = plan.spectral_bounds()
+    plan.close()
+    op = O.Operator(spec, bounds=(lo, hi))
+    u_ref = dipole_times(spec, 0, op.r, op.R, op.x, psi_ref)
+    ref = PH.autocorrelation(op, 0, u_ref, K)
+    err = float(np.max(np.abs(C - ref)))
+    # the two bound states agree to an overlap of 1 - O(1e-13), i.e. vectors to
+    # O(1e-7); C_k = <u_0|u_k> is bilinear in the packet and the damped recursion
+    # does not grow it, so |dC_k| <= (2 |u_0| + |du_0|) |du_0|, plus the FP64 step's bar
+    du = float(np.linalg.norm(u_dev - u_ref))
+    bound = (2 * np.sqrt(ref[0]) + du) * du + 1e-10 * ref[0]
+    print(f"[result] autocorrelation max |C - oracle| / C_0 = {err / ref[0]:.2e} "
+          f"(packets differ by {du:.1e}; bound {bound / ref[0]:.1e} C_0)", flush=True)
+    assert err <= bound
