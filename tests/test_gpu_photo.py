@@ -54,8 +54,8 @@ def _oracle_series(spec, unit, K, seed=0):
     return op, PH.autocorrelation(op, unit, u0, K)
 
 
-def _spec_2state_J1():
-    s = small_variant(3, n_R=21, n_r=17, n_gamma=9)
+def _spec_2state_J1(n_R=21, n_r=17, n_gamma=9):
+    s = small_variant(3, n_R=n_R, n_r=n_r, n_gamma=n_gamma)
     s["units"] = [dict(J=1, parity=-1, omega_max=1, n_packets=1)]
     s["packets"] = []
     return s
@@ -66,6 +66,11 @@ CASES = [
      "fp64", 150, 1e-10),
     ("J=1 Omega 0..1, 2 states, 21x17x9 fp64 (general kernels)", _spec_2state_J1, "fp64", 80, 1e-10),
     ("J=0 24x20x10 fp16x3", lambda: small_variant(1, n_R=24, n_r=20, n_gamma=10), "fp16x3", 150, 1e-4),
+    ("J=1 Omega 0..1, 2 states, 22x18x10 fp64 (matrix-core kernels, overlaps in the R pass)",
+     lambda: _spec_2state_J1(22, 18, 10), "fp64", 80, 1e-10),
+    ("J=1 Omega 0..1, 2 states, 22x18x10 bf16x3", lambda: _spec_2state_J1(22, 18, 10), "bf16x3", 80,
+     1e-4),
+    ("J=0 24x20x10 fp32", lambda: small_variant(1, n_R=24, n_r=20, n_gamma=10), "fp32", 150, 1e-4),
 ]
 
 
