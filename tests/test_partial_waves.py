@@ -133,3 +133,18 @@ def test_invalid_arguments_are_rejected():
         with pytest.raises(TdwpError):
             call()
             pytest.fail(f"case {k} accepted")
+
+
+def test_bench_partial_waves_line():
+    # the host leg of bench.py runs without a GPU and prints one JSON line
+    import json
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    out = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--partial-waves",
+                          "--no-cpu-baseline", "--pw-final-states", "8"],
+                         capture_output=True, text=True, timeout=300, check=True).stdout
+    line = json.loads([ln for ln in out.splitlines() if ln.startswith("{")][-1])
+    assert line["unit"] == "terms/s" and line["value"] > 0 and line["dtype"] == "f64"
+    assert line["config"]["terms"] == 41 * 200 * 8 * 5 - 200 * 8 * (1 + 1 + 2 + 2)
