@@ -34,7 +34,9 @@ eigendecomposition of the dense H (and, with a uniform damping d, against
 d^k times it), the normalisation sum rule (the integral of
 a_0 over the spectral range is C_0) and the first moment (<u_0|H|u_0>) by exact
 quadrature, the Dirichlet-kernel closed form of a_0 for an eigenstate packet,
-and the integrated cross section sum rule.
+and the integrated cross section sum rule.  lowest_state is a library
+eigensolver on the dense H, whose construction the tdwp_oracle pins fix
+(symmetry, spectrum, closed-form special cases).
 """
 import math
 
