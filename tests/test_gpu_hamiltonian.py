@@ -125,3 +125,30 @@ def test_lowest_state_matches_dense_eigensolver(name, spec_fn, n_iter):
     assert abs(E - E_ref) <= 1e-9 * abs(E_ref)
     assert ov > 1 - 1e-8
     assert res < 1e-5 * abs(E_ref)
+
+
+def test_lowest_state_mixed_form_and_errors():
+    banner("bound state in the fp16x3 form; invalid iteration counts, guesses and order")
+    from oracle import photo_oracle as PH
+    from paper_2412_10167_amd import problem
+    from paper_2412_10167_amd.tdwp import TdwpError
+    spec = small_variant(1, n_R=16, n_r=12, n_gamma=6)
+    plan = _bare_plan(spec, "fp16x3")
+    lo, hi = plan.spectral_bounds()
+    op = O.Operator(spec, bounds=(lo, hi))
+    guess = np.random.default_rng(5).standard_normal(op.unit_shape(0))
+    E, psi, res = plan.lowest_state(guess, n_iter=300)
+    E_ref, psi_ref = PH.lowest_state(op, 0)
+    ov = abs(float(np.sum(psi * psi_ref)))
+    print(f"[result] fp16x3: E rel {abs(E - E_ref) / abs(E_ref):.1e}, overlap 1 - {1 - ov:.1e}",
+          flush=True)
+    # the split contractions carry 2^-22 of the contraction scale into H u
+    assert abs(E - E_ref) <= 1e-5 * abs(E_ref) and ov > 1 - 1e-6
+    with pytest.raises(TdwpError):
+        plan.lowest_state(guess, n_iter=1)                   # fewer than two steps
+    with pytest.raises(TdwpError):
+        plan.lowest_state(np.zeros_like(guess), n_iter=10)   # zero start vector
+    problem.install_packets(plan, spec)
+    with pytest.raises(TdwpError):
+        plan.lowest_state(guess, n_iter=10)                  # a packet is installed
+    plan.close()
