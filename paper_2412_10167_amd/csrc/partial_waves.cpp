@@ -9,9 +9,11 @@
 // constant, so its linear-interpolation stencil (left index and weight at each
 // grid energy) depends on J and the grid only.  The cumulative sum builds the
 // stencils of a J once and applies them to every final state, after summing the
-// families present at that J (the shifted curve is linear in the computed one).
+// families present at that J (the shifted curve is linear in the computed one);
+// ranges of final states run on host threads.
 #include <algorithm>
 #include <cmath>
+#include <thread>
 #include <vector>
 
 #include "../../include/tdwp.h"
@@ -161,50 +163,68 @@ int tdwp_cumulative_probability(const int* J_calc, const double* B, int n_calc, 
   }
   const int n_lev = (int)level_j.size();
   const size_t row = (size_t)n_e, per_fam = (size_t)n_f * row, per_c = (size_t)n_fam * per_fam;
-  std::vector<double> slot_buf[2];
-  int slot_c[2] = {-1, -1};
-  for (auto& v : slot_buf) v.resize((size_t)n_lev * per_fam);
-  auto levels_of = [&](int c, int keep) -> const double* {
-    for (int k = 0; k < 2; ++k)
-      if (slot_c[k] == c) return slot_buf[k].data();
-    const int k = (slot_c[0] == keep) ? 1 : 0;
-    double* dst = slot_buf[k].data();
-    int fam = 0;
-    for (int q = 0; q < n_lev; ++q) {
-      double* lv = dst + (size_t)q * per_fam;
-      if (q) std::copy(lv - per_fam, lv, lv);
-      else std::fill(lv, lv + per_fam, 0.0);
-      for (; fam < level_end[q]; ++fam) {
-        const double* src = p + (size_t)c * per_c + (size_t)order[fam] * per_fam;
-        for (size_t x = 0; x < per_fam; ++x) lv[x] += src[x];
+  // Final states [f0, f1) of the sum: independent of every other final state,
+  // so ranges of them run on host threads with results identical to one thread.
+  auto run = [&](int f0, int f1) {
+    const size_t nfr = (size_t)(f1 - f0) * row;   // values of one level for the range
+    std::vector<double> slot_buf[2];
+    int slot_c[2] = {-1, -1};
+    for (auto& v : slot_buf) v.resize((size_t)n_lev * nfr);
+    auto levels_of = [&](int c, int keep) -> const double* {
+      for (int k = 0; k < 2; ++k)
+        if (slot_c[k] == c) return slot_buf[k].data();
+      const int k = (slot_c[0] == keep) ? 1 : 0;
+      double* dst = slot_buf[k].data();
+      int fam = 0;
+      for (int q = 0; q < n_lev; ++q) {
+        double* lv = dst + (size_t)q * nfr;
+        if (q) std::copy(lv - nfr, lv, lv);
+        else std::fill(lv, lv + nfr, 0.0);
+        for (; fam < level_end[q]; ++fam) {
+          const double* src = p + (size_t)c * per_c + (size_t)order[fam] * per_fam + (size_t)f0 * row;
+          for (size_t x = 0; x < nfr; ++x) lv[x] += src[x];
+        }
+      }
+      slot_c[k] = c;
+      return dst;
+    };
+    std::fill(c_out + (size_t)f0 * row, c_out + (size_t)f1 * row, 0.0);
+    Stencil a, b;
+    int lev = -1;
+    for (int J = 0; J <= J_max; ++J) {
+      while (lev + 1 < n_lev && level_j[lev + 1] <= J) ++lev;
+      if (lev < 0) continue;   // no family has a state at this J
+      const Source s = source_of(J, J_calc, n_calc, B);
+      const double* S1 = levels_of(s.c1, s.c2) + (size_t)lev * nfr;
+      const double* S2 = levels_of(s.c2, s.c1) + (size_t)lev * nfr;
+      a.build(e, n_e, s.s1);
+      if (s.w2 != 0.0) b.build(e, n_e, -s.s2);
+      const double g = 2.0 * J + 1.0;
+      const double g1 = g * s.w1, g2 = g * s.w2;
+      for (int f = f0; f < f1; ++f) {
+        const double* p1 = S1 + (size_t)(f - f0) * row;
+        const double* p2 = S2 + (size_t)(f - f0) * row;
+        double* out = c_out + (size_t)f * row;
+        if (s.w2 == 0.0) {
+          for (int i = 0; i < n_e; ++i) out[i] += g1 * a.at(p1, i);
+        } else {
+          for (int i = 0; i < n_e; ++i) out[i] += g1 * a.at(p1, i) + g2 * b.at(p2, i);
+        }
       }
     }
-    slot_c[k] = c;
-    return dst;
   };
-  for (size_t q = 0; q < (size_t)n_f * row; ++q) c_out[q] = 0.0;
-  Stencil a, b;
-  int lev = -1;
-  for (int J = 0; J <= J_max; ++J) {
-    while (lev + 1 < n_lev && level_j[lev + 1] <= J) ++lev;
-    if (lev < 0) continue;   // no family has a state at this J
-    const Source s = source_of(J, J_calc, n_calc, B);
-    const double* S1 = levels_of(s.c1, s.c2) + (size_t)lev * per_fam;
-    const double* S2 = levels_of(s.c2, s.c1) + (size_t)lev * per_fam;
-    a.build(e, n_e, s.s1);
-    if (s.w2 != 0.0) b.build(e, n_e, -s.s2);
-    const double g = 2.0 * J + 1.0;
-    const double g1 = g * s.w1, g2 = g * s.w2;
-    for (int f = 0; f < n_f; ++f) {
-      const double* p1 = S1 + (size_t)f * row;
-      const double* p2 = S2 + (size_t)f * row;
-      double* out = c_out + (size_t)f * row;
-      if (s.w2 == 0.0) {
-        for (int i = 0; i < n_e; ++i) out[i] += g1 * a.at(p1, i);
-      } else {
-        for (int i = 0; i < n_e; ++i) out[i] += g1 * a.at(p1, i) + g2 * b.at(p2, i);
-      }
+  // one thread per 16 final states at least, up to the host's cores (at most 16)
+  const unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  const int n_thr = (int)std::min<long>((long)hw, std::max<long>(1, (long)n_f / 16));
+  if (n_thr == 1) {
+    run(0, n_f);
+  } else {
+    std::vector<std::thread> pool;
+    for (int t = 0; t < n_thr; ++t) {
+      const int f0 = (int)((long)n_f * t / n_thr), f1 = (int)((long)n_f * (t + 1) / n_thr);
+      pool.emplace_back(run, f0, f1);
     }
+    for (auto& th : pool) th.join();
   }
   return TDWP_OK;
 }
