@@ -337,7 +337,7 @@ def partial_waves_bench(args):
         "config": {"workload": f"J=0..40 from 21 computed J, {s['n_fam']} (Omega0, p) families "
                                f"(j0=2), {s['n_f']} final states, {e.size} energies",
                    "terms": terms, "fit_ms_per_interval": round(t_fit * 1e3 / (len(J) - 1), 4),
-                   "host_threads": 1},
+                   "host_threads": min(16, os.cpu_count() or 1, max(1, s["n_f"] // 16))},
         "roofline": None,
         "cpu_baseline": cpu,
     }
