@@ -240,3 +240,28 @@ def test_photodissociation_from_a_lanczos_bound_state():
     print(f"[result] autocorrelation max |C - oracle| / C_0 = {err / ref[0]:.2e} "
           f"(packets differ by {du:.1e}; bound {bound / ref[0]:.1e} C_0)", flush=True)
     assert err <= bound
+
+
+def test_photo_packet_replaced_by_a_collision_packet():
+    banner("slot switched from a photodissociation packet to a collision packet, J=0 24x20x10 fp64")
+    from paper_2412_10167_amd import problem
+    from paper_2412_10167_amd.tdwp import TdwpError
+    spec = small_variant(1, n_R=24, n_r=20, n_gamma=10)
+    plan = _photo_plan(spec)
+    plan.set_packet_values(0, 0, _device_packet(plan, spec, 0))
+    plan.propagate(30, norms=False)                 # overlaps in the R pass, graphs captured
+    problem.install_packets(plan, spec)             # the same slot as a collision packet
+    with pytest.raises(TdwpError):
+        plan.autocorrelation(0, 0)
+    K = 60
+    plan.propagate(K)
+    got = plan.get_packet(0, 0, 0)
+    lo, hi = plan.spectral_bounds()
+    plan.close()
+    op = O.Operator(spec, bounds=(lo, hi))
+    pk = spec["packets"][0]
+    va = asymptotic_potential(spec, op.r, pk["elec0"])
+    e, chi = O.diatomic_states(op, va, pk["j0"], 1)
+    run = O.propagate(op, 0, O.initial_packet(op, 0, pk, chi[0]), K, keep_vectors=(K,))
+    ref = run["vectors"][K]
+    assert float(np.max(np.abs(got - ref)) / np.max(np.abs(ref))) < 1e-10
