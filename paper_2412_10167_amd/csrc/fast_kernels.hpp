@@ -523,7 +523,9 @@ __device__ __forceinline__ void ang_blk(const double* __restrict__ u_all,
   }
   __syncthreads();
   // C[o][class][t][jj], jj < kpa (rows past the class size come out zero:
-  // the table rows there are zero)
+  // the table rows there are zero).  With one helicity the mixing is the factor
+  // min(B_r j(j+1) + B_R ell, rot_cut) of each coefficient, applied here.
+  const double bR = BR[m];
 #pragma unroll
   for (int r = 0; r < RES; ++r) {
     const int it = w + 4 * r;
@@ -534,14 +536,23 @@ __device__ __forceinline__ void ang_blk(const double* __restrict__ u_all,
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int jj = mt * 16 + M::row(l, v);
-        if (jj < kpa)
-          F::put(X, ps, (o * 2 + c) * tile + (nt * 16 + (l & 15)) * ld + jj,
-                 (double)res[r][nt][v] * M::kUnscale);
+        if (jj >= kpa) continue;
+        const int t = nt * 16 + (l & 15);
+        double val = (double)res[r][nt][v] * M::kUnscale;
+        if constexpr (MAXOM == 1) {
+          const int j = 2 * jj + om_lo + c;   // FBR index of row jj of class c
+          if (j < ng && i0 + t < nr && d.n_om_j[j] > 0) {
+            double e = Br[i0 + t] * (double)j * (double)(j + 1) + bR * elll[d.ell_off[j]];
+            if (rot_cut > 0.0) e = fmin(e, rot_cut);
+            val *= e;
+          }
+        }
+        F::put(X, ps, (o * 2 + c) * tile + t * ld + jj, val);
       }
   }
   __syncthreads();
   // Omega mixing at fixed j: U diag(min(B_r j(j+1) + B_R ell_a, rot_cut)) U^T
-  const double bR = BR[m];
+  if constexpr (MAXOM > 1)
   for (int q = threadIdx.x; q < ng * RT; q += blockDim.x) {
     const int t = q % RT, j = q / RT;
     const int nj = d.n_om_j[j];
@@ -576,7 +587,7 @@ __device__ __forceinline__ void ang_blk(const double* __restrict__ u_all,
       }
     }
   }
-  __syncthreads();
+  if constexpr (MAXOM > 1) __syncthreads();
   ang_back<P, NT>(X, h, PcT, tab, ngk, psp, n_om, om_lo, ne, le, ng, ld, tile, ps, m, i0, nr,
                   plane);
 }
