@@ -300,3 +300,123 @@ def test_uncoupled_second_state_stays_empty_and_first_matches_single_state():
     r1 = O.propagate(op1, 0, u1, 30, keep_vectors=(30,))
     assert np.max(np.abs(r2["vectors"][30][:, 1])) == 0.0
     assert np.max(np.abs(r2["vectors"][30][:, 0] - r1["vectors"][30][:, 0])) < 1e-13
+
+
+# P4 continued -- the capped branch of the angular term (several helicities) ------------------
+
+def _angular_part(op, u):
+    """Angular + Coriolis part of H u (H u minus the radial kinetic and potential terms)."""
+    h = O.apply_H(op, 0, u) - (u @ op.Tr) - np.matmul(op.TR, u)
+    for p, (la, lb) in enumerate(op.pairs):
+        h[:, la] -= op.V[p][None] * u[:, lb]
+        if la != lb:
+            h[:, lb] -= op.V[p][None] * u[:, la]
+    return h
+
+
+def _fbr_block(op, unit, j, m, i):
+    """The matrix of the angular term on the FBR coefficients c[Omega][j] at the grid
+    point (R_m, r_i), over the helicities Omega <= j of the unit: column b is the
+    FBR image of the DVR vector whose only coefficient is (Omega_b, j)."""
+    oms = O.omega_range(unit)
+    om = [o for o in oms if o <= j]
+    A = np.zeros((len(om), len(om)))
+    for b, ob in enumerate(om):
+        u = np.zeros(op.unit_shape(0))
+        u[oms.index(ob), 0, :, m, i] = op.P[ob][j - ob]
+        h = _angular_part(op, u)
+        for a, oa in enumerate(om):
+            A[a, b] = op.P[oa][j - oa] @ h[oms.index(oa), 0, :, m, i]
+    return om, A
+
+
+def test_capped_branch_with_cap_above_spectrum_equals_l2_operator():
+    """rot_cut above every block eigenvalue: the capped branch (eigenvectors of the
+    l^2 block) must reproduce B_r j(j+1) + B_R l^2 built by hand at every point and j;
+    an eigenvector matrix applied transposed fails this."""
+    s = tiny_spec(J=4, omega_max=3, rot_cut=50.0, rad_cut=0.0, n_gamma=6, n_R=5, n_r=4)
+    s["v_cut"] = 0.0
+    op = O.Operator(s)
+    oms = O.omega_range(s["units"][0])
+    assert oms == [0, 1, 2, 3]
+    rng = np.random.default_rng(7)
+    u = rng.standard_normal(op.unit_shape(0))
+    h = _angular_part(op, u)
+    ref = np.zeros_like(u)
+    for m in range(s["n_R"]):
+        for i in range(s["n_r"]):
+            for j in range(op.jmax + 1):
+                om, L = O.ell2_matrix(4, j, oms)
+                for a, oa in enumerate(om):
+                    for b, ob in enumerate(om):
+                        coef = op.BR[m] * L[a, b] + (op.Br[i] * j * (j + 1) if a == b else 0.0)
+                        ref[oms.index(oa), 0, :, m, i] += coef * op.P[oa][j - oa] * (
+                            op.P[ob][j - ob] @ u[oms.index(ob), 0, :, m, i])
+    assert np.max(np.abs(h - ref)) < 1e-13 * np.max(np.abs(ref))
+
+
+def test_biting_cap_clips_closed_form_eigenvalues_of_each_block():
+    """A cap inside the block spectra: each (R_m, r_i, j) block of the angular term has
+    eigenvalues min(B_r j(j+1) + B_R l(l+1), rot_cut) with l(l+1) from the closed form
+    (|J-j| <= l <= J+j, (j + l - J) even for the block holding Omega = 0), and it is a
+    function of the l^2 block (it commutes with it)."""
+    J = 3
+    s = tiny_spec(J=J, omega_max=J, rad_cut=0.0, n_gamma=6, n_R=5, n_r=4)
+    s["v_cut"] = 0.0
+    probe = O.Operator(dict(s, rot_cut=0.0))
+    m, i = 1, 2
+    levels = sorted(probe.Br[i] * j * (j + 1) + probe.BR[m] * l * (l + 1)
+                    for j in range(probe.jmax + 1) for l in range(abs(J - j), J + j + 1))
+    cap = levels[len(levels) // 2]
+    s["rot_cut"] = cap
+    op = O.Operator(s)
+    oms = O.omega_range(s["units"][0])
+    bitten = kept = 0
+    for j in range(op.jmax + 1):
+        om, A = _fbr_block(op, s["units"][0], j, m, i)
+        if not om:
+            continue
+        ls = [l for l in range(abs(J - j), J + j + 1) if (j + l - J) % 2 == 0]
+        assert len(ls) == len(om)
+        exact = np.sort([min(op.Br[i] * j * (j + 1) + op.BR[m] * l * (l + 1), cap) for l in ls])
+        assert np.max(np.abs(np.sort(np.linalg.eigvalsh(0.5 * (A + A.T))) - exact)) < 1e-13 * cap
+        assert np.max(np.abs(A - A.T)) < 1e-14 * cap
+        _, L = O.ell2_matrix(J, j, oms)
+        assert np.max(np.abs(A @ L - L @ A)) < 1e-12 * cap * np.max(np.abs(L))
+        bitten += int(np.sum(exact >= cap))
+        kept += int(np.sum(exact < cap))
+    assert bitten > 0 and kept > 0
+
+
+# P11 -- free spreading of a Gaussian (kinetic terms, time reconstruction) ---------------------
+
+def test_free_gaussian_spreads_analytically():
+    """V = 0, J = 0, caps and absorbers off: a Gaussian amplitude exp(-(x-x0)^2 / 2 G^2)
+    in R and in r keeps its form and its width grows as G sqrt(1 + (t / (M G^2))^2),
+    with M = mu along R and m along r, until it reaches the walls.  Psi(t) comes from
+    the undamped Chebyshev components (Eq. chebyshev-expansion-constants)."""
+    s = config(1)
+    s.update(n_R=72, n_r=60, n_gamma=3, rad_cut=0.0, rot_cut=0.0, v_cut=0.0)
+    s["units"] = [dict(J=0, parity=1, omega_max=0, n_packets=1)]
+    shape = (1, 1, 3, 72, 60)
+    op = O.Operator(s, vtable=np.zeros((1,) + shape[2:]))
+    GR, Gr, R0, r0 = 0.6, 0.55, 6.25, 4.25
+    pk = dict(unit=0, slot=0, v0=0, j0=0, omega0=0, elec0=0, R0=R0, width=GR, ecol_mean=0.0)
+    chi = np.sqrt(op.dr) * np.exp(-((op.r - r0) ** 2) / (2 * Gr * Gr))
+    u0 = O.initial_packet(op, 0, pk, chi)
+    t_max = 700.0
+    K = int(t_max * op.dE * 1.1) + 80
+    run = O.propagate(op, 0, u0, K, keep_vectors="all", undamped=True)
+    vecs = np.array([run["vectors"][k] for k in range(K + 1)])
+    for t in (0.0, 150.0, 400.0, 700.0):
+        psi = O.time_reconstruct(op, vecs, t)
+        dens = np.abs(psi[0, 0]) ** 2                      # (gamma, R, r)
+        assert abs(dens.sum() - 1.0) < 1e-10
+        for axis, x, M, G, t_lim in ((1, op.R, op.mu, GR, 700.0), (2, op.r, op.m, Gr, 400.0)):
+            if t > t_lim:
+                continue
+            p = dens.sum(axis=tuple(a for a in range(3) if a != axis))
+            mean = float(p @ x)
+            var = float(p @ (x - mean) ** 2)
+            want = 0.5 * (G * math.sqrt(1.0 + (t / (M * G * G)) ** 2)) ** 2
+            assert abs(var - want) < 1e-7 * want, (t, axis, var, want)
