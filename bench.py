@@ -1,16 +1,24 @@
 """Throughput of the Chebyshev wave-packet hot path on one MI355X.
 
-Workload: J = 0 A + BC (masses 1.008/2.014/1.008 amu) on the synthetic LEPS
-surface, grid R x r x gamma = 256 x 192 x 80 (3,932,160 values), one diabatic
-state, one packet.  A step is one full Chebyshev iteration: angular + potential,
-both radial kinetic terms, scaling/recursion/damping, norm, flux and analysis
-lines, and the (amortised) Chebyshev-to-energy accumulation.  Inputs are
-resident in HBM before the timed region; the timed region is K calls' worth of
-steps bracketed by device synchronisation and HIP events on the library's
-stream.
+Default workload: the batched one, 21 partial waves J = 0, 2, ..., 40 (helicities
+Omega <= min(J, 6): 135 helicity blocks) x 3 initial states BC(v=0, j=0,1,2) of
+A + BC (masses 1.008/2.014/1.008 amu) on the synthetic LEPS surface, grid
+R x r x gamma = 128 x 128 x 48 (318,504,960 values per step), in the
+mixed-precision form chosen by the library's autotuner, with the plain FP64 form
+timed beside it.  A step is one full Chebyshev iteration of every packet:
+angular + Coriolis, both radial kinetic terms, potential, scaling/recursion/
+damping, norm, flux and analysis lines, and the Chebyshev-to-energy
+accumulation.  The accumulation runs once per ring of buffered steps; its
+HIP-event time for one flush, divided by the ring length, is added to the
+timed per-step time.  Inputs are resident in HBM before the timed region; the
+timed region is K steps bracketed by device synchronisation and HIP events on
+the library's stream.
 
-Prints one JSON line.  Also reports the dominant kernel against its roofline
-(per-kernel device time from HIP events inside the library) and the FP64 oracle
+Prints one JSON line.  Also reports the dominant kernel against the HBM
+roofline (algorithmic bytes: read u_k and u_{k-1}, write u_{k+1}, 24 bytes per
+value, plus the potential once per grid point), the whole step against the
+same bytes, the largest P(E) difference of the timed form from the FP64 form
+after the workload's full step count (per partial wave), and the FP64 oracle
 timed on a bounded sample of the same workload on the host cores.
 """
 import argparse
@@ -111,26 +119,38 @@ def measured_traffic(kernel, workload, precision):
     return table.get(kernel)
 
 
-def pe_difference(problem, spec, precision, steps, jmax=10, vmax=2):
+def pe_difference(problem, spec, precision, steps, autotune, jmax=10, vmax=2):
     """Largest |P(E)| difference between the timed form and the FP64 form after the
-    same number of steps: reactive probability per state and every reactant-channel
-    probability (v <= vmax, j <= jmax, all helicities) of every packet, on all
-    collision energies."""
+    same number of steps, each built as it is timed (the autotuner's variant):
+    reactive probability per state and every reactant-channel probability
+    (v <= vmax, j <= jmax, all helicities) of every packet, on all collision
+    energies; also the largest difference per partial wave J."""
     import numpy as np
-    res = {}
+    res, per_pk, chosen = {}, {}, {}
     for prec in (precision, "fp64"):
-        plan, _ = problem.build(spec, precision=prec, autotune=0)
+        plan, info = problem.build(spec, precision=prec, autotune=autotune)
+        chosen[prec] = (info.get("autotune") or "").split("chosen=")[-1] or None
         plan.propagate(steps, norms=False)
         parts = []
         for pk in spec["packets"]:
             chans = problem.channels(plan, spec, pk["unit"], min(jmax, spec["n_gamma"] - 1), vmax)
             p_inel, p_reac = plan.state_to_state(pk["unit"], pk["slot"], chans)
-            parts += [p_inel.ravel(), p_reac.ravel()]
+            v = np.concatenate([p_inel.ravel(), p_reac.ravel()])
+            per_pk.setdefault(prec, []).append(v)
+            parts.append(v)
         res[prec] = np.concatenate(parts)
         plan.close()
+        print(f"pe_vs_fp64: {prec} propagated {steps} steps", file=sys.stderr, flush=True)
     d = np.abs(res[precision] - res["fp64"])
+    by_J = {}
+    for i, pk in enumerate(spec["packets"]):
+        J = spec["units"][pk["unit"]]["J"]
+        dj = float(np.max(np.abs(per_pk[precision][i] - per_pk["fp64"][i])))
+        by_J[J] = max(by_J.get(J, 0.0), dj)
     return dict(steps=steps, probabilities=int(d.size), max_abs_diff=float(d.max()),
-                max_probability=float(np.max(np.abs(res["fp64"]))))
+                max_probability=float(np.max(np.abs(res["fp64"]))),
+                variants=chosen,
+                max_abs_diff_by_J={str(k): float("%.3g" % v) for k, v in sorted(by_J.items())})
 
 
 def mlp_bench(args, torch, problem, config):
@@ -217,9 +237,18 @@ def mlp_bench(args, torch, problem, config):
     print(json.dumps(out))
 
 
-def cpu_baseline(spec, budget_s=15.0):
-    """The oracle, untuned, on a bounded sample: as many full-size Chebyshev steps
-    as fit in about budget_s seconds after one warm-up step."""
+def n_blocks(spec):
+    """Helicity blocks x packets of a workload (the units of work of one step)."""
+    return sum((u["omega_max"] - (0 if u["parity"] * (-1) ** u["J"] == 1 else 1) + 1) * u["n_packets"]
+               for u in spec["units"])
+
+
+def cpu_baseline(spec, min_steps=100, budget_s=20.0):
+    """The oracle, untuned, on a bounded sample: one packet of the workload's unit
+    with the most helicity blocks, at least min_steps full-size Chebyshev steps
+    (more while within budget_s) after one warm-up step.  The rate is scaled to
+    steps/s of the whole workload by the blocks the sample holds against the
+    workload's total (the oracle's cost per block and step is nearly uniform)."""
     import numpy as np
     from oracle import tdwp_oracle as O
     from workloads import asymptotic_potential
@@ -229,21 +258,31 @@ def cpu_baseline(spec, budget_s=15.0):
         cores = max([i.get("num_threads", 1) for i in info] or [1])
     except Exception:
         cores = os.cpu_count() or 1
-    op = O.Operator(spec)
-    va = asymptotic_potential(spec, op.r, 0)
-    e0, chi0 = O.diatomic_states(op, va, 0, 1)
-    u0 = O.initial_packet(op, 0, spec["packets"][0], chi0[0])
+    ui = max(range(len(spec["units"])), key=lambda i: (spec["units"][i]["omega_max"], spec["units"][i]["J"]))
+    sub = dict(spec)
+    sub["units"] = [dict(spec["units"][ui], n_packets=1)]
+    pk = [dict(p, unit=0) for p in spec["packets"] if p["unit"] == ui][0]
+    sub["packets"] = [pk]
+    op = O.Operator(sub)
+    va = asymptotic_potential(sub, op.r, pk["elec0"])
+    e0, chi0 = O.diatomic_states(op, va, pk["j0"], pk["v0"] + 1)
+    u0 = O.initial_packet(op, 0, pk, chi0[pk["v0"]])
     u_prev, u = u0, op.D * O.apply_Hs(op, 0, u0)
     t0 = time.perf_counter()
     n = 0
-    while time.perf_counter() - t0 < budget_s:
+    while n < min_steps or time.perf_counter() - t0 < budget_s:
         u_prev, u = u, op.D * (2.0 * O.apply_Hs(op, 0, u) - op.D * u_prev)
         n += 1
     dt = time.perf_counter() - t0
     assert np.isfinite(np.sum(u * u))
-    return dict(value=n / dt, unit="Chebyshev steps/s", cores=cores, kind="oracle",
-                sample=f"{n} full-size steps (256x192x80, J=0) of the FP64 numpy oracle "
-                       f"(H application, recursion and damping; no slices) in {dt:.1f} s")
+    blk = n_blocks(sub)
+    total = n_blocks(spec)
+    U = spec["units"][ui]
+    return dict(value=n * blk / dt / total, unit="Chebyshev steps/s", cores=cores, kind="oracle",
+                sample=f"{n} full-size steps of one packet of the J={U['J']} unit ({blk} helicity "
+                       f"blocks of {spec['n_R']}x{spec['n_r']}x{spec['n_gamma']}) of the FP64 numpy "
+                       f"oracle (H application, recursion and damping; no slices) in {dt:.1f} s = "
+                       f"{n * blk / dt:.3f} block-steps/s, scaled to the workload's {total} blocks")
 
 
 def spectrum_timing(plan, skip_oracle, E_i):
@@ -347,23 +386,29 @@ def partial_waves_bench(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=400)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--precision", default="fp16x3",
                     help="contraction precision of the timed form: fp64, fp32, bf16x3, fp16x3")
     ap.add_argument("--no-fp64-reference", action="store_true",
                     help="skip timing the plain FP64 form beside a mixed form")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--kernel-steps", type=int, default=50)
+    ap.add_argument("--kernel-steps", type=int, default=None,
+                    help="steps of the per-kernel HIP-event timing (default: past two ring "
+                         "flushes, so the energy accumulation is timed)")
     ap.add_argument("--autotune", type=int, default=5,
                     help="steps per tile variant timed by the library's autotuner (0: off)")
-    ap.add_argument("--workload", type=int, default=2,
-                    help="workload number 1..5 (default 2: J=0 256x192x80)")
+    ap.add_argument("--workload", type=int, default=4,
+                    help="workload number 1..5 (default 4: 21 partial waves x 3 packets, "
+                         "128x128x48)")
+    ap.add_argument("--no-side-workload", action="store_true",
+                    help="skip timing workload 2 (J=0 256x192x80) beside the batched workload")
     ap.add_argument("--radial-grid", type=int, default=0,
                     help="workgroups of the radial passes (0: one per block)")
     ap.add_argument("--pe-steps", type=int, default=None,
                     help="steps of the P(E) comparison of the timed form with the FP64 form "
-                         "(default: the workload's full step count on workload 2, else 0 = off)")
+                         "(default: the workload's full step count on workloads 2 and 4, else "
+                         "0 = off)")
     ap.add_argument("--mlp", action="store_true",
                     help="learned-potential run: train the network on the device from the "
                          "tabulated surface, then time the step with the network evaluated on "
@@ -449,11 +494,14 @@ def main():
         plan.set_packet_values(0, 0, dipole_times(spec, 0, r, R, x, psi))
         return plan, info
 
-    def timed(precision, steps, warmup):
-        plan, info = build(precision)
+    def timed(precision, steps, warmup, sp=None):
+        if sp is None:
+            plan, info = build(precision)
+        else:
+            plan, info = problem.build(sp, precision=precision, autotune=args.autotune)
         if args.radial_grid:
             plan.set_option("radial_grid", args.radial_grid)
-        if info.get("autotune"):
+        if info.get("autotune") and sp is None:
             tune_reports[precision] = info["autotune"]
         plan.propagate(warmup, norms=False)
         stream = torch.cuda.current_stream()
@@ -466,22 +514,47 @@ def main():
         torch.cuda.synchronize()
         return plan, e0.elapsed_time(e1), time.perf_counter() - t0
 
+    def per_step_kernels(plan):
+        """Kernel averages (us per launch, HIP events on the library's stream) over
+        enough steps to include two energy accumulations (ring flushes)."""
+        ring = plan.stat("ring_len")
+        n = args.kernel_steps or 2 * ring + 8
+        kt = plan.time_kernels(n)
+        fz = bool(plan.stat("fuse_r"))
+        return {k: v for k, v in kt.items()
+                if not (fz and k == "radial_r") and not (k == "autocorrelation" and v == 0.0)}, ring
+
     plan, ms, wall = timed(args.precision, args.steps, args.warmup)
-    steps_per_s = args.steps / (ms / 1e3)
-    kt = plan.time_kernels(args.kernel_steps)
+    per_step, ring = per_step_kernels(plan)
     fused = bool(plan.stat("fuse_r"))
-    per_step = {k: v for k, v in kt.items()
-                if not (fused and k == "radial_r") and not (k == "autocorrelation" and v == 0.0)}
+    # the energy accumulation runs once per ring of buffered steps: its time per
+    # flush over the ring length is added to the timed steps
+    acc_us = per_step.get("accumulate", 0.0)
+    ms_step = ms / args.steps + acc_us * 1e-3 / ring
+    steps_per_s = 1e3 / ms_step
     in_pass = args.photo and not per_step.get("autocorrelation")
-    dom = max((k for k in per_step if kernel_model(spec, k, args.precision, fused)),
-              key=lambda k: per_step[k])
+    step_kernels = {k: v for k, v in per_step.items() if k not in ("accumulate", "slices")}
+    dom = max((k for k in step_kernels if kernel_model(spec, k, args.precision, fused)),
+              key=lambda k: step_kernels[k])
     traffic = measured_traffic(dom, args.workload, args.precision) if not args.photo else None
-    bound, amount, unit, peak, _ = kernel_model(spec, dom, args.precision, fused, in_pass)
-    achieved = amount / (per_step[dom] * 1e-6)
-    roofline = dict(bound=bound, achieved=round(achieved, 3), peak=peak, unit=unit,
+    _, _, _, _, own_bytes = kernel_model(spec, dom, args.precision, fused, in_pass)
+    # algorithmic bytes of a step: u_k and u_{k-1} read, u_{k+1} written (FP64),
+    # the potential once per grid point (8 bytes per stored entry)
+    n_pair = spec["n_elec"] * (spec["n_elec"] + 1) // 2
+    alg_bytes = 24.0 * values + 8.0 * n_pair * spec["n_R"] * spec["n_r"] * spec["n_gamma"]
+    peak = PEAKS["hbm"][0]
+    achieved = alg_bytes / 1e9 / (step_kernels[dom] * 1e-6)
+    step_gbps = alg_bytes / 1e9 / (ms_step * 1e-3)
+    roofline = dict(bound="hbm", achieved=round(achieved, 3), peak=peak, unit="GB/s",
                     frac=round(achieved / peak, 4), traffic=traffic, kernel=dom,
-                    kernel_avg_us=round(per_step[dom], 2),
-                    kernels_avg_us={k: round(v, 2) for k, v in per_step.items()})
+                    kernel_avg_us=round(step_kernels[dom], 2),
+                    algorithmic_bytes_per_step=alg_bytes,
+                    kernel_own_bytes=own_bytes,
+                    kernel_own_frac=round(own_bytes / 1e9 / (step_kernels[dom] * 1e-6) / peak, 4),
+                    step=dict(achieved=round(step_gbps, 3), frac=round(step_gbps / peak, 4),
+                              ms=round(ms_step, 5)),
+                    kernels_avg_us={k: round(v, 2) for k, v in per_step.items()},
+                    ring_len=ring)
     acf = None
     if args.photo:
         if in_pass:   # formed by the R pass (u_0 read there, 8 bytes per value)
@@ -495,11 +568,25 @@ def main():
         acf["bound_state"] = bound_cache.get("info")
         acf["spectrum"] = spectrum_timing(plan, args.no_cpu_baseline, bound_cache["bound"][0])
     plan.close()
+    print(f"timed {args.precision}: {steps_per_s:.2f} steps/s", file=sys.stderr, flush=True)
     fp64_rate = None
     if args.precision != "fp64" and not args.no_fp64_reference:
         p64, ms64, _ = timed("fp64", args.steps, args.warmup)
+        k64, ring64 = per_step_kernels(p64)
         p64.close()
-        fp64_rate = args.steps / (ms64 / 1e3)
+        fp64_rate = 1e3 / (ms64 / args.steps + k64.get("accumulate", 0.0) * 1e-3 / ring64)
+        print(f"timed fp64: {fp64_rate:.2f} steps/s", file=sys.stderr, flush=True)
+    side = None
+    if args.workload != 2 and not args.no_side_workload and not args.photo:
+        s2 = config(2)
+        side = {"workload": WORKLOAD_NAMES[2]}
+        for prec in ([args.precision, "fp64"] if args.precision != "fp64" else ["fp64"]):
+            pp, m2, _ = timed(prec, 400, 20, sp=s2)
+            k2, r2 = per_step_kernels(pp)
+            pp.close()
+            side[prec + "_steps_per_s"] = round(1e3 / (m2 / 400 + k2.get("accumulate", 0.0) * 1e-3 / r2), 2)
+        if "fp64_steps_per_s" in side and args.precision != "fp64":
+            side["speedup_vs_fp64"] = round(side[args.precision + "_steps_per_s"] / side["fp64_steps_per_s"], 3)
     if args.copy_calibration:
         n = args.copy_calibration * (1 << 20) // 4
         src = torch.ones(n, dtype=torch.float32, device="cuda")
@@ -508,15 +595,16 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
 
-    pe_steps = args.pe_steps if args.pe_steps is not None else (spec["steps"] if args.workload == 2 else 0)
+    pe_steps = args.pe_steps if args.pe_steps is not None else (
+        spec["steps"] if args.workload in (2, 4) else 0)
     if args.photo:
         pe_steps = 0
     pe = None
     if pe_steps > 0 and args.precision != "fp64":
-        pe = pe_difference(problem, spec, args.precision, pe_steps)
+        pe = pe_difference(problem, spec, args.precision, pe_steps, args.autotune)
 
     cpu = None
-    if not args.no_cpu_baseline and args.workload == 2:
+    if not args.no_cpu_baseline and not args.photo:
         cpu = cpu_baseline(spec)
 
     out = {
@@ -527,7 +615,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms / args.steps, 5),
+        "ms_per_step": round(ms_step, 5),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -536,12 +624,17 @@ def main():
         "config": {"workload": WORKLOAD_NAMES.get(args.workload, spec["name"]),
                    "precision": args.precision, "grid_values": values,
                    "grid_pt_steps_per_s": round(steps_per_s * values, 1),
+                   "timed_steps_ms": round(ms, 4),
+                   "accumulate_in_step": f"one energy accumulation per {ring} steps: "
+                                         f"{acc_us:.1f} us per flush, {acc_us / ring:.2f} us per step "
+                                         "added to the timed steps",
                    "fp64_steps_per_s": round(fp64_rate, 2) if fp64_rate else None,
                    "speedup_vs_fp64": round(steps_per_s / fp64_rate, 3) if fp64_rate else None,
                    "autotune": tune_reports or None,
                    "fused_r": fused,
                    "autocorrelation": acf,
                    "pe_vs_fp64": pe,
+                   "workload_2": side,
                    "wall_s": round(wall, 3)},
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -205,7 +205,9 @@ int tdwp_set_initial_packet(tdwp_plan_t p, const tdwp_packet* pk, const double* 
 /* Advances every packet by n_steps Chebyshev steps from its current (u_{k-1},
  * u_k, k).  norms: NULL, or host [n_packets_total][n_steps] receiving
  * ||u_{k+1}||^2 .. ||u_{k+n_steps}||^2, packets ordered by (unit, slot).
- * Chunked calls give the same results as one call.  Errors: ESTATE (packets
+ * Chunked calls give the same results as one call (the analysis lines of the
+ * last u_k are recorded by the next step or by tdwp_state_to_state, so a
+ * chunk boundary adds no pass).  Errors: ESTATE (packets
  * missing), ERANGE (a norm exceeded 1e6 or is not finite: E_max too low). */
 int tdwp_propagate(tdwp_plan_t p, long n_steps, double* norms);
 
@@ -386,7 +388,9 @@ enum tdwp_stat {
   TDWP_STAT_MATRIX_CORE_PATH = 2,   /* 1 when the matrix-core kernels are in use */
   TDWP_STAT_ANG_KERNEL = 3,         /* angular kernel in use: 1 LDS mixing, 2 register mixing
                                        (0: general kernels) */
-  TDWP_STAT_FUSE_R = 4              /* 1 when the angular and r passes share a launch */
+  TDWP_STAT_FUSE_R = 4,             /* 1 when the angular and r passes share a launch */
+  TDWP_STAT_RING_LEN = 5            /* steps of slices buffered between two energy
+                                       accumulations (Eq. wvf-chebyshev, blocked)     */
 };
 
 /* Sets a plan option; EINVAL for an unknown option or value. */

@@ -1552,7 +1552,10 @@ int run_steps(Plan* P, long n_steps, double* norms_out, Timing* T) {
     done += chunk;
     if (bad) return TDWP_ERANGE;
   }
-  return finish_slices(P, T);
+  // the slices of the final u_k are recorded by the next step's r pass, or by the
+  // analysis (tdwp_state_to_state) if it comes first: a chunked caller pays no
+  // extra pass per call
+  return TDWP_OK;
 }
 
 void reset_propagation(Plan* P) {
@@ -2254,6 +2257,7 @@ int tdwp_get_stat(tdwp_plan_t p, int stat, long* value) {
     case TDWP_STAT_ANG_KERNEL: *value = p->fast ? (p->ang_regs ? 2 : 1) : 0; return TDWP_OK;
     case TDWP_STAT_MATRIX_CORE_PATH: *value = p->fast ? 1 : 0; return TDWP_OK;
     case TDWP_STAT_FUSE_R: *value = (p->fast && p->fuse_r) ? 1 : 0; return TDWP_OK;
+    case TDWP_STAT_RING_LEN: *value = p->ring_len; return TDWP_OK;
     default: return TDWP_EINVAL;
   }
 }

@@ -24,7 +24,8 @@ EXPORTED_SYMBOLS = (
 )
 OPTIONS = {"graphs": 0, "ang_tile": 1, "radial_grid": 2, "ang_kernel": 3, "fuse_r": 4,
            "ang_xcd": 5}
-STATS = {"graph_steps": 0, "ang_tile": 1, "matrix_core_path": 2, "ang_kernel": 3, "fuse_r": 4}
+STATS = {"graph_steps": 0, "ang_tile": 1, "matrix_core_path": 2, "ang_kernel": 3, "fuse_r": 4,
+         "ring_len": 5}
 
 
 class TdwpError(RuntimeError):
