@@ -379,8 +379,12 @@ enum tdwp_option {
   TDWP_OPT_FUSE_R = 4,      /* 1 (default): the angular pass and the r pass in one launch
                                (T_r u into a buffer of its own); 0: two launches, the r
                                pass adding T_r u to the angular terms                      */
-  TDWP_OPT_ANG_XCD = 5      /* 1: angular blocks dealt to the XCDs in contiguous runs;
+  TDWP_OPT_ANG_XCD = 5,     /* 1: angular blocks dealt to the XCDs in contiguous runs;
                                0 (default): in launch order                                */
+  TDWP_OPT_PLANE_R = 6      /* 1: both radial kinetic terms, the potential and the
+                               recursion in one pass over whole (R, r) planes (one
+                               electronic state, mixed forms, plane within the device's
+                               LDS; EINVAL otherwise); 0 (default): r pass and R pass    */
 };
 enum tdwp_stat {
   TDWP_STAT_GRAPH_STEPS = 0,        /* steps taken so far by graph replay      */
@@ -389,8 +393,9 @@ enum tdwp_stat {
   TDWP_STAT_ANG_KERNEL = 3,         /* angular kernel in use: 1 LDS mixing, 2 register mixing
                                        (0: general kernels) */
   TDWP_STAT_FUSE_R = 4,             /* 1 when the angular and r passes share a launch */
-  TDWP_STAT_RING_LEN = 5            /* steps of slices buffered between two energy
+  TDWP_STAT_RING_LEN = 5,           /* steps of slices buffered between two energy
                                        accumulations (Eq. wvf-chebyshev, blocked)     */
+  TDWP_STAT_PLANE_R = 6             /* 1 when steps run the plane pass               */
 };
 
 /* Sets a plan option; EINVAL for an unknown option or value. */

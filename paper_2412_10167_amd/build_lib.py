@@ -1,6 +1,9 @@
-"""Builds libtdwp.so for gfx950 in-tree with hipcc (no GPU needed)."""
+"""Builds libtdwp.so for gfx950 in-tree with hipcc (no GPU needed): each source
+compiled to an object in parallel, then one link."""
 import os
 import subprocess
+import tempfile
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
@@ -9,19 +12,27 @@ SOURCES = ["tdwp.hip", "host_tables.cpp", "partial_waves.cpp", "spectra.cpp"]
 HEADERS = ["plan.h", "host_tables.h", "step_kernels.hpp"]
 
 FLAGS = [
-    "-O3", "--offload-arch=gfx950", "-fPIC", "-shared", "-std=c++17",
+    "-O3", "--offload-arch=gfx950", "-fPIC", "-std=c++17",
     # packed FP32 instructions are disabled for all device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 ]
 
 
-def build(verbose=False):
-    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    tmp = OUT + ".tmp"
-    cmd = [hipcc, *FLAGS, "-o", tmp] + [os.path.join(CSRC, s) for s in SOURCES]
+def _run(cmd):
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
-        raise RuntimeError("hipcc failed:\n" + res.stdout + res.stderr)
+        raise RuntimeError("hipcc failed:\n" + " ".join(cmd) + "\n" + res.stdout + res.stderr)
+
+
+def build(verbose=False):
+    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    with tempfile.TemporaryDirectory(prefix="tdwp_build_") as tmpdir:
+        objs = [os.path.join(tmpdir, s + ".o") for s in SOURCES]
+        cmds = [[hipcc, *FLAGS, "-c", os.path.join(CSRC, s), "-o", o] for s, o in zip(SOURCES, objs)]
+        with ThreadPoolExecutor(max_workers=len(cmds)) as ex:
+            list(ex.map(_run, cmds))
+        tmp = OUT + ".tmp"
+        _run([hipcc, "--offload-arch=gfx950", "-fPIC", "-shared", "-o", tmp] + objs)
     os.replace(tmp, OUT)
     if verbose:
         print("built", OUT)

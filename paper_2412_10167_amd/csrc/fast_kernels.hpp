@@ -1117,6 +1117,13 @@ __global__ void k_to_format(const double* __restrict__ src, typename Fmt<P>::E* 
 // ---- energy accumulation: acc[c e][s] += sum_b coef[c e][b] ring[b][s] ----------------
 // M = 2 n_E rows (real and imaginary parts), K = buffered steps, N = slice values.
 // One workgroup per 32 slice values; wave w owns M-tiles w, w+4, ...
+// The K loop runs in chunks of eight ring rows (two matrix-core k-steps); within a
+// chunk lane l takes rows 2 (l/16) and 2 (l/16) + 1 for both operands (any pairing
+// of k between the operands' fragments is a valid contraction as long as it is
+// the same for A and B), so its two coefficients are one 16-byte load.  The loads
+// of the next chunk are issued before the current chunk's products (two register
+// buffers), so the ring's HBM latency and the coefficients' L2 latency overlap
+// the matrix-core work instead of preceding each k-step.
 constexpr int kAccMaxMT = 8;   // M-tiles per wave (2 n_E <= 512)
 struct AccDesc {
   unsigned long acc_off;    // accumulators of the packet [2 n_E][n_slice]
@@ -1124,14 +1131,15 @@ struct AccDesc {
   int n_slice;
 };
 
-__global__ __launch_bounds__(256) void k_accum_mfma(double* __restrict__ acc_all,
-                                                    const double* __restrict__ coef_all, int ldc,
-                                                    const double* __restrict__ ring_all,
-                                                    size_t ring_stride,
-                                                    const AccDesc* __restrict__ ads,
-                                                    const int* __restrict__ blk_start, int n_pk,
-                                                    int rows, int count) {
+__global__ __launch_bounds__(256, 2) void k_accum_mfma(double* __restrict__ acc_all,
+                                                       const double* __restrict__ coef_all, int ldc,
+                                                       const double* __restrict__ ring_all,
+                                                       size_t ring_stride,
+                                                       const AccDesc* __restrict__ ads,
+                                                       const int* __restrict__ blk_start, int n_pk,
+                                                       int rows, int count) {
   using M = Mma<kP64>;
+  typedef double v2d __attribute__((ext_vector_type(2)));
   const int l = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int pk = find_packet(blk_start, n_pk, blockIdx.x);
   const AccDesc ad = ads[pk];
@@ -1141,27 +1149,62 @@ __global__ __launch_bounds__(256) void k_accum_mfma(double* __restrict__ acc_all
   const int n_slice = ad.n_slice;
   const int s0 = (blockIdx.x - blk_start[pk]) * 32;
   const int MT = (rows + 15) >> 4;
+  const int kq = 2 * (l >> 4);
   M::acc_t c[kAccMaxMT][2];
 #pragma unroll
   for (int a = 0; a < kAccMaxMT; ++a) c[a][0] = c[a][1] = M::zero();
-  const int kc = round_up(count, 4);
-  for (int k0 = 0; k0 < kc; k0 += 4) {
-    const int kb = k0 + (l >> 4);
-    double b[2];
+  int scol[2];
+  bool sok[2];
 #pragma unroll
-    for (int nt = 0; nt < 2; ++nt) {
-      const int s = s0 + nt * 16 + (l & 15);
-      b[nt] = (kb < count && s < n_slice) ? ring[(size_t)kb * ring_stride + s] : 0.0;
+  for (int nt = 0; nt < 2; ++nt) {
+    const int s = s0 + nt * 16 + (l & 15);
+    sok[nt] = s < n_slice;
+    scol[nt] = sok[nt] ? s : n_slice - 1;   // clamped, in-range address
+  }
+  // fragments of one chunk: A[tile] = (row r, ring rows kb, kb + 1), B[cc][nt]
+  v2d A0[kAccMaxMT], A1[kAccMaxMT];
+  double B0[2][2], B1[2][2];
+  auto load = [&](v2d (&A)[kAccMaxMT], double (&B)[2][2], int ch) {
+    const int kb = 8 * ch + kq;   // even; kb + 1 < 8 * nchunks <= ldc
+#pragma unroll
+    for (int cc = 0; cc < 2; ++cc) {
+      const int k = kb + cc;
+      const int kr = k < count ? k : count - 1;
+#pragma unroll
+      for (int nt = 0; nt < 2; ++nt) {
+        const double x = ring[(size_t)kr * ring_stride + scol[nt]];
+        B[cc][nt] = (k < count && sok[nt]) ? x : 0.0;
+      }
     }
 #pragma unroll
     for (int a = 0; a < kAccMaxMT; ++a) {
       const int mt = w + 4 * a;
       if (mt >= MT) break;
-      const int r = mt * 16 + (l & 15);
-      const double av = (r < rows && kb < count) ? coef[(size_t)r * ldc + kb] : 0.0;
-      M::mma(c[a][0], av, b[0]);
-      M::mma(c[a][1], av, b[1]);
+      int r = mt * 16 + (l & 15);
+      const bool rok = r < rows;
+      r = rok ? r : rows - 1;
+      const v2d x = *reinterpret_cast<const v2d*>(coef + (size_t)r * ldc + kb);
+      A[a] = v2d{(rok && kb < count) ? x[0] : 0.0, (rok && kb + 1 < count) ? x[1] : 0.0};
     }
+  };
+  auto compute = [&](const v2d (&A)[kAccMaxMT], const double (&B)[2][2]) {
+#pragma unroll
+    for (int cc = 0; cc < 2; ++cc)
+#pragma unroll
+      for (int a = 0; a < kAccMaxMT; ++a) {
+        const int mt = w + 4 * a;
+        if (mt >= MT) break;
+        M::mma(c[a][0], A[a][cc], B[cc][0]);
+        M::mma(c[a][1], A[a][cc], B[cc][1]);
+      }
+  };
+  const int nch = (count + 7) >> 3;
+  if (nch > 0) load(A0, B0, 0);
+  for (int ch = 0; ch < nch; ch += 2) {
+    if (ch + 1 < nch) load(A1, B1, ch + 1);
+    compute(A0, B0);
+    if (ch + 2 < nch) load(A0, B0, ch + 2);
+    if (ch + 1 < nch) compute(A1, B1);
   }
 #pragma unroll
   for (int a = 0; a < kAccMaxMT; ++a) {
@@ -1169,8 +1212,8 @@ __global__ __launch_bounds__(256) void k_accum_mfma(double* __restrict__ acc_all
     if (mt >= MT) break;
 #pragma unroll
     for (int nt = 0; nt < 2; ++nt) {
+      if (!sok[nt]) continue;
       const int s = s0 + nt * 16 + (l & 15);
-      if (s >= n_slice) continue;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int r = mt * 16 + M::row(l, v);

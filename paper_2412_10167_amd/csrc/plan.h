@@ -100,6 +100,16 @@ struct tdwp_plan_s {
   int ang_pref = 0;          // angular kernel: 0 automatic, 1 k_ang, 2 k_angr
   bool fuse_r = true;        // angular and r passes in one launch (T_r u into d_h2)
   bool ang_xcd = false;      // angular blocks in XCD order
+  // both radial terms in one pass over whole (R, r) planes (one state, mixed forms)
+  bool plane_ok = false;     // the plane fits the device's LDS and the form allows it
+  bool plane_r = false;      // in use (option / autotuner)
+  int plane_kR = 0, plane_kr = 0;   // padded contraction lengths of the full operator tables
+  size_t lds_plane = 0;
+  void* d_TRfullF = nullptr;  // T_R [rows][plane_kR], compute format
+  void* d_TrfullF = nullptr;  // T_r [rows][plane_kr], compute format
+  int* d_blk_plane = nullptr; // planes per packet, prefix sums
+  int blocks_plane = 0;
+  int* d_n_wg_plane = nullptr;   // norm partials per packet of the plane pass
   int nrhk = 0, nRhk = 0, ngk = 0, ngr = 0;
   size_t lds_radr = 0, lds_ang = 0, lds_radR = 0;
   std::vector<double> Trs, Trd, TRs, TRd, Pc;

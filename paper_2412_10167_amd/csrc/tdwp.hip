@@ -17,6 +17,7 @@
 #include "fast_kernels.hpp"
 #include "mlp_kernels.hpp"
 #include "photo_kernels.hpp"
+#include "plane_kernels.hpp"
 #include "step_kernels.hpp"
 
 using namespace tdwp;
@@ -486,6 +487,7 @@ void set_lds_limits() {
         with_angr<PR>(nt, mom, tpw, FusedAng{}, add);
       }
   }
+  if constexpr (PR != kP64) add(k_plane_epi<PR>);
   for (const void* f : all) {
     // the dynamic share is what the device allows beyond the kernel's static LDS
     hipFuncAttributes fa{};
@@ -514,6 +516,54 @@ void query_lds_limit() {
   if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cu > 0)
     kNumCU = cu;
   (void)hipGetLastError();
+}
+
+// Full-size radial operators padded to the plane pass's tile (rows to 16, the
+// contraction to the matrix-core k-step), in compute format.
+template <int PR>
+int plane_tables(Plan* P) {
+  using M = Mma<PR>;
+  const int nR = P->nR, nr = P->nr;
+  P->plane_kR = plane_pad(nR, M::KS);
+  P->plane_kr = plane_pad(nr, M::KS);
+  auto padded = [](const std::vector<double>& T, int n, int kp) {
+    std::vector<double> out((size_t)round_up(n, 16) * kp, 0.0);
+    for (int a = 0; a < n; ++a)
+      for (int b = 0; b < n; ++b) out[(size_t)a * kp + b] = T[(size_t)a * n + b];
+    return out;
+  };
+  TRY(upload_formatted<PR>(P, &P->d_TRfullF, padded(P->TR, nR, P->plane_kR)));
+  TRY(upload_formatted<PR>(P, &P->d_TrfullF, padded(P->Tr, nr, P->plane_kr)));
+  const int rows_x = plane_pad(nR, M::KS), cols_x = plane_pad(nr, M::KS);
+  P->lds_plane = (size_t)rows_x * plane_ld(cols_x) * sizeof(float);
+  hipFuncAttributes fa{};
+  size_t stat = 0;
+  if (hipFuncGetAttributes(&fa, (const void*)k_plane_epi<PR>) == hipSuccess) stat = fa.sharedSizeBytes;
+  (void)hipGetLastError();
+  P->plane_ok = P->lds_plane + stat <= kLdsMax;
+  return TDWP_OK;
+}
+
+// The plane pass (one electronic state, mixed forms, r lines of at most 256):
+// tables, block map and norm-partial counts.
+int plane_setup(Plan* P) {
+  P->plane_ok = false;
+  if (P->ne != 1 || P->cfg.precision == TDWP_FP64 || P->nr > 64 * kPlaneMaxCols) return TDWP_OK;
+  switch (P->cfg.precision) {
+    case TDWP_FP32: TRY(plane_tables<kP32>(P)); break;
+    case TDWP_BF16X3: TRY(plane_tables<kPBF>(P)); break;
+    default: TRY(plane_tables<kPF16>(P)); break;
+  }
+  std::vector<int> bp(1, 0), nw;
+  for (auto& pk : P->packets) {
+    const int n_planes = P->units[pk.unit].n_om * P->ng;
+    bp.push_back(bp.back() + n_planes);
+    nw.push_back(n_planes);
+  }
+  P->blocks_plane = bp.back();
+  TRY(alloc_copy(P, &P->d_blk_plane, bp));
+  TRY(alloc_copy(P, &P->d_n_wg_plane, nw));
+  return TDWP_OK;
 }
 
 int layout_and_allocate(Plan* P) {
@@ -641,6 +691,7 @@ int layout_and_allocate(Plan* P) {
       case TDWP_BF16X3: set_lds_limits<kPBF>(); TRY(upload_tables<kPBF>(P)); break;
       default: set_lds_limits<kPF16>(); TRY(upload_tables<kPF16>(P)); break;
     }
+    TRY(plane_setup(P));
   }
   TRY(dev_alloc(P, (void**)&P->d_normpart, (size_t)kNormChunk * P->n_wg_total * sizeof(double)));
   TRY(dev_alloc(P, (void**)&P->d_norms, P->packets.size() * kNormChunk * sizeof(double)));
@@ -805,8 +856,8 @@ void store_tile(Plan* P, int nt) {
 
 struct Timing {
   hipEvent_t ev[2];
-  double ms[6] = {0, 0, 0, 0, 0, 0};
-  long calls[6] = {0, 0, 0, 0, 0, 0};
+  double ms[7] = {0, 0, 0, 0, 0, 0, 0};
+  long calls[7] = {0, 0, 0, 0, 0, 0, 0};
 };
 
 int timed_begin(Plan* P, Timing* T) {
@@ -983,6 +1034,13 @@ unsigned radial_blocks(const Plan* P, long n) {
   return (unsigned)((P->radial_grid > 0 && P->radial_grid < n) ? P->radial_grid : n);
 }
 
+// Whether this step runs the plane pass (both radial terms, one launch) after
+// the angular pass: chosen, feasible, a tabulated potential, and no overlaps to
+// form in the R pass.
+bool use_plane(const Plan* P) {
+  return P->fast && P->plane_ok && P->plane_r && P->pot_mode == TDWP_POT_TABLE && !P->acf_in_pass;
+}
+
 // Launches the kernels of one step of the matrix-core path (no host state change):
 // u_k in d_u[cur], u_{k-1} in d_u[1 - cur]; rec: record the slices of u_k.
 template <int PR>
@@ -1002,7 +1060,8 @@ int enqueue_step(Plan* P, int cur, int first, int rec, Timing* T) {
                P->d_flux_split + 3 * nrh, 1.0 / std::sqrt(P->dR), P->d_ring, P->slice_total,
                P->d_counters, P->ring_len, P->d_radr_pk};
   const unsigned nblk_r = radial_blocks(P, (nlines + kRadrLines - 1) / kRadrLines);
-  const bool fuse = P->fuse_r;
+  const bool plane = use_plane(P);
+  const bool fuse = P->fuse_r && !plane;
   HT* h2 = fuse ? reinterpret_cast<HT*>(P->d_h2) : nullptr;
   // the potential table in h's precision (an FP32 copy in the mixed forms)
   const HT* vtab = reinterpret_cast<const HT*>(PR == kP64 ? (const void*)P->d_V : (const void*)P->d_Vf);
@@ -1037,6 +1096,24 @@ int enqueue_step(Plan* P, int cur, int first, int rec, Timing* T) {
   }
   HIP_TRY(hipGetLastError());
   TRY(timed_end(P, T, 0));
+  if constexpr (PR != kP64) {
+    if (plane) {
+      // T_r and T_R over whole planes, potential, recursion, damping, norm, slices
+      TRY(timed_begin(P, T));
+      PlaneArgs pa{uk, uo, reinterpret_cast<const float*>(P->d_h), pkd, P->d_blk_plane, np,
+                   P->d_TRfullF, P->d_TrfullF, P->plane_kR, P->plane_kr,
+                   round_up(nR, 16) * P->plane_kR, round_up(nr, 16) * P->plane_kr,
+                   P->d_Vf, P->d_Dsep, ng, nR, nr, P->E0, 1.0 / P->dE, first, P->d_normpart,
+                   P->n_wg_total, P->d_counters, kNormChunk, rec, P->d_slice_off,
+                   P->d_line_start, P->d_arow, P->d_drow, P->m_inf, 1.0 / std::sqrt(P->dR),
+                   P->d_ring, P->slice_total, P->ring_len};
+      hipLaunchKernelGGL(k_plane_epi<PR>, dim3(radial_blocks(P, P->blocks_plane)),
+                         dim3(kPlaneThreads), P->lds_plane, P->stream, pa);
+      HIP_TRY(hipGetLastError());
+      TRY(timed_end(P, T, 6));
+      return TDWP_OK;
+    }
+  }
   if (!fuse) {
     TRY(timed_begin(P, T));
     hipLaunchKernelGGL(k_radr<PR>, dim3(nblk_r), dim3(256), P->lds_radr, P->stream, uk, h,
@@ -1529,10 +1606,12 @@ int run_steps(Plan* P, long n_steps, double* norms_out, Timing* T) {
     }
     const int nq = np * chunk;
     const bool mlp_layout = P->fast && P->pot_mode == TDWP_POT_MLP;
+    const bool plane_layout = use_plane(P);
     hipLaunchKernelGGL(k_norm_reduce, dim3((nq + 255) / 256), dim3(256), 0, P->stream,
                        P->d_norms, P->d_normpart, P->n_wg_total,
                        mlp_layout ? P->d_wg_off_mlp : P->d_wg_off,
-                       mlp_layout ? P->d_n_wg_mlp : P->d_n_wg, np, chunk);
+                       mlp_layout ? P->d_n_wg_mlp : (plane_layout ? P->d_n_wg_plane : P->d_n_wg),
+                       np, chunk);
     HIP_TRY(hipGetLastError());
     hn.resize((size_t)np * kNormChunk);
     HIP_TRY(hipMemcpyAsync(hn.data(), P->d_norms, hn.size() * sizeof(double),
@@ -1621,10 +1700,12 @@ int tdwp_plan(const tdwp_config* cfg, tdwp_plan_t* out) {
     // cached choice: 1000 * (angular blocks in XCD order) + 100 * (r pass fused) +
     // 10 * kernel + tile (kernel 1: LDS mixing, 2: register mixing)
     const int c = cached_tile(P);
-    const int nt = c % 10, kern = (c / 10) % 10, fz = (c / 100) % 10, xo = c / 1000;
-    if ((nt == 1 || nt == 2 || nt == 4) && kern <= 2 && fz <= 1 && xo <= 1) {
+    const int nt = c % 10, kern = (c / 10) % 10, fz = (c / 100) % 10, xo = (c / 1000) % 10;
+    const int pl = c / 10000;
+    if ((nt == 1 || nt == 2 || nt == 4) && kern <= 2 && fz <= 1 && xo <= 1 && pl <= 1) {
       P->fuse_r = fz == 1;
       P->ang_xcd = xo == 1;
+      P->plane_r = pl == 1 && P->plane_ok;
       const int keep = P->ang_pref;
       P->ang_pref = kern;
       if (set_ang_tiles(P, nt) != TDWP_OK) {
@@ -2102,10 +2183,10 @@ int tdwp_time_kernels(tdwp_plan_t p, long n_steps, int n_max, double* avg_us, ch
   (void)hipEventDestroy(T.ev[0]);
   (void)hipEventDestroy(T.ev[1]);
   if (st != TDWP_OK) return st;
-  static const char* kinds[6] = {"angular", "radial_R_epilogue", "slices", "accumulate", "radial_r",
-                                 "autocorrelation"};
+  static const char* kinds[7] = {"angular", "radial_R_epilogue", "slices", "accumulate", "radial_r",
+                                 "autocorrelation", "radial_rR_epilogue"};
   std::string joined;
-  for (int i = 0; i < 6; ++i) {
+  for (int i = 0; i < 7; ++i) {
     if (i < n_max && avg_us) avg_us[i] = T.calls[i] ? 1000.0 * T.ms[i] / T.calls[i] : 0.0;
     if (i) joined += ";";
     joined += kinds[i];
@@ -2114,7 +2195,7 @@ int tdwp_time_kernels(tdwp_plan_t p, long n_steps, int n_max, double* avg_us, ch
     std::strncpy(names, joined.c_str(), names_len - 1);
     names[names_len - 1] = 0;
   }
-  return 6;
+  return 7;
 }
 
 int tdwp_autotune(tdwp_plan_t p, int steps, char* report, size_t report_len) {
@@ -2131,15 +2212,20 @@ int tdwp_autotune(tdwp_plan_t p, int steps, char* report, size_t report_len) {
   HIP_TRY(hipMemsetAsync(p->d_u[1], 0, p->n_total * sizeof(double), p->stream));
   std::string rep;
   const int keep_pref = p->ang_pref, keep_nt = p->nta;
-  const bool keep_fuse = p->fuse_r, keep_xcd = p->ang_xcd;
+  const bool keep_fuse = p->fuse_r, keep_xcd = p->ang_xcd, keep_plane = p->plane_r;
   int best_k = -1, best_nt = keep_nt, best_f = keep_fuse ? 1 : 0, best_x = keep_xcd ? 1 : 0;
+  int best_p = keep_plane ? 1 : 0;
   double best_us = 1e300;
-  // r pass beside the angular pass or after it x angular kernel (2: helicity mixing
-  // in registers, 1: through LDS) x tile width; the kernels of whole steps are timed
+  // both radial terms in one plane pass, or the r pass beside the angular pass or
+  // after it x angular kernel (2: helicity mixing in registers, 1: through LDS) x
+  // tile width; the kernels of whole steps are timed
+  for (int pl : {1, 0})
   for (int xo : {0, 1})
   for (int fz : {1, 0})
   for (int kern : {2, 1})
     for (int nt : {4, 2, 1}) {
+      if (pl && (!p->plane_ok || fz)) continue;   // the plane pass follows a plain angular pass
+      p->plane_r = pl == 1;
       p->ang_xcd = xo == 1;
       p->fuse_r = fz == 1;
       p->ang_pref = kern;
@@ -2148,7 +2234,7 @@ int tdwp_autotune(tdwp_plan_t p, int steps, char* report, size_t report_len) {
       int st = sync_counters(p);
       for (int s2 = 0; s2 < steps + 1 && st == TDWP_OK; ++s2) {   // the first step warms up
         if (s2 <= 1)
-          for (int q : {0, 1, 4}) {
+          for (int q : {0, 1, 4, 6}) {
             T.ms[q] = 0.0;
             T.calls[q] = 0;
           }
@@ -2161,14 +2247,16 @@ int tdwp_autotune(tdwp_plan_t p, int steps, char* report, size_t report_len) {
         p->ang_pref = keep_pref;
         p->fuse_r = keep_fuse;
         p->ang_xcd = keep_xcd;
+        p->plane_r = keep_plane;
         (void)set_ang_tiles(p, keep_nt);
         return st;
       }
-      // the whole step: the shared launch also changes what the R pass reads
-      const double us = 1000.0 * (T.ms[0] + T.ms[1] + T.ms[4]) / std::max<long>(T.calls[0], 1);
-      char buf[64];
-      std::snprintf(buf, sizeof buf, "%sx%d_f%d_k%d_nt%d:%.1fus", rep.empty() ? "" : ";", xo, fz,
-                    kern, nt, us);
+      // the whole step: the launch form also changes what the later passes read
+      const double us =
+          1000.0 * (T.ms[0] + T.ms[1] + T.ms[4] + T.ms[6]) / std::max<long>(T.calls[0], 1);
+      char buf[80];
+      std::snprintf(buf, sizeof buf, "%sp%d_x%d_f%d_k%d_nt%d:%.1fus", rep.empty() ? "" : ";", pl,
+                    xo, fz, kern, nt, us);
       rep += buf;
       if (us < best_us) {
         best_us = us;
@@ -2176,6 +2264,7 @@ int tdwp_autotune(tdwp_plan_t p, int steps, char* report, size_t report_len) {
         best_nt = nt;
         best_f = fz;
         best_x = xo;
+        best_p = pl;
       }
     }
   (void)hipEventDestroy(T.ev[0]);
@@ -2184,18 +2273,21 @@ int tdwp_autotune(tdwp_plan_t p, int steps, char* report, size_t report_len) {
     p->ang_pref = keep_pref;
     p->fuse_r = keep_fuse;
     p->ang_xcd = keep_xcd;
+    p->plane_r = keep_plane;
     TRY(set_ang_tiles(p, keep_nt));
   } else {
     p->ang_pref = best_k;
     p->fuse_r = best_f == 1;
     p->ang_xcd = best_x == 1;
+    p->plane_r = best_p == 1;
     TRY(set_ang_tiles(p, best_nt));
-    store_tile(p, 1000 * best_x + 100 * best_f + 10 * best_k + best_nt);
+    store_tile(p, 10000 * best_p + 1000 * best_x + 100 * best_f + 10 * best_k + best_nt);
   }
   drop_graphs(p);
   reset_propagation(p);
   if (report && report_len) {
-    rep += ";chosen=x" + std::to_string(p->ang_xcd ? 1 : 0) + "_f" + std::to_string(p->fuse_r ? 1 : 0) +
+    rep += ";chosen=p" + std::to_string(use_plane(p) ? 1 : 0) + "_x" +
+           std::to_string(p->ang_xcd ? 1 : 0) + "_f" + std::to_string(p->fuse_r ? 1 : 0) +
            "_k" + std::to_string(p->ang_regs ? 2 : 1) + "_nt" + std::to_string(p->nta);
     std::strncpy(report, rep.c_str(), report_len - 1);
     report[report_len - 1] = 0;
@@ -2239,6 +2331,12 @@ int tdwp_set_option(tdwp_plan_t p, int option, long value) {
       p->fuse_r = value != 0;
       drop_graphs(p);
       return TDWP_OK;
+    case TDWP_OPT_PLANE_R:
+      if (value != 0 && value != 1) return TDWP_EINVAL;
+      if (value == 1 && !(p->fast && p->plane_ok)) return TDWP_EINVAL;
+      p->plane_r = value != 0;
+      drop_graphs(p);
+      return TDWP_OK;
     case TDWP_OPT_RADIAL_GRID:
       if (value < 0 || value > (1L << 30)) return TDWP_EINVAL;
       p->radial_grid = value;
@@ -2258,6 +2356,7 @@ int tdwp_get_stat(tdwp_plan_t p, int stat, long* value) {
     case TDWP_STAT_MATRIX_CORE_PATH: *value = p->fast ? 1 : 0; return TDWP_OK;
     case TDWP_STAT_FUSE_R: *value = (p->fast && p->fuse_r) ? 1 : 0; return TDWP_OK;
     case TDWP_STAT_RING_LEN: *value = p->ring_len; return TDWP_OK;
+    case TDWP_STAT_PLANE_R: *value = use_plane(p) ? 1 : 0; return TDWP_OK;
     default: return TDWP_EINVAL;
   }
 }

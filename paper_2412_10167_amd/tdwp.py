@@ -23,9 +23,9 @@ EXPORTED_SYMBOLS = (
     "tdwp_photo_cross_section", "tdwp_apply_hamiltonian", "tdwp_lowest_state",
 )
 OPTIONS = {"graphs": 0, "ang_tile": 1, "radial_grid": 2, "ang_kernel": 3, "fuse_r": 4,
-           "ang_xcd": 5}
+           "ang_xcd": 5, "plane_r": 6}
 STATS = {"graph_steps": 0, "ang_tile": 1, "matrix_core_path": 2, "ang_kernel": 3, "fuse_r": 4,
-         "ring_len": 5}
+         "ring_len": 5, "plane_r": 6}
 
 
 class TdwpError(RuntimeError):
