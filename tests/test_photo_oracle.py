@@ -141,3 +141,108 @@ def test_cross_section_sum_rule_and_energy_origin():
     a0 = PH.energy_content(C, e_min, e_max, E_i + hnu)
     ref = 4 * math.pi / 137.035999084 * hnu * a0
     np.testing.assert_allclose(sig, ref, rtol=0, atol=1e-13 * np.max(np.abs(ref)))
+
+
+# ---- initial packet of Eq. initial-photo-wvp -----------------------------------------------
+
+@pytest.mark.parametrize("j", [0, 1, 2, 5, 9])
+def test_clebsch_gordan_closed_forms_for_rank_one(j):
+    """The standard j x 1 tables, <j m 1 0|j m> = m / sqrt(j(j+1)),
+    <j m 1 0|j+1 m> = sqrt((j-m+1)(j+m+1)/((2j+1)(j+1))) and
+    <j m-1 1 1|j+1 m> = sqrt((j+m)(j+m+1)/((2j+1)(2j+2))), read in the order 1 x j
+    through <j1 m1 j2 m2|J M> = (-1)^(j1+j2-J) <j2 m2 j1 m1|J M>."""
+    for m in range(-j, j + 1):
+        if j > 0:
+            assert abs(PH.clebsch_gordan(1, 0, j, m, j, m) + m / math.sqrt(j * (j + 1))) < 1e-14
+        want = math.sqrt((j - m + 1) * (j + m + 1) / ((2 * j + 1) * (j + 1)))
+        assert abs(PH.clebsch_gordan(1, 0, j, m, j + 1, m) - want) < 1e-14
+    for m in range(-j, j + 2):
+        want = math.sqrt((j + m) * (j + m + 1) / ((2 * j + 1) * (2 * j + 2)))
+        assert abs(PH.clebsch_gordan(1, 1, j, m - 1, j + 1, m) - want) < 1e-14
+
+
+@pytest.mark.parametrize("j2", [0, 1, 3, 4])
+def test_clebsch_gordan_orthonormal(j2):
+    """sum_{m1 m2} <1 m1 j2 m2|J M><1 m1 j2 m2|J' M'> = delta_JJ' delta_MM'."""
+    Js = range(abs(j2 - 1), j2 + 2)
+    for J in Js:
+        for Jp in Js:
+            for M in range(-J, J + 1):
+                s = sum(PH.clebsch_gordan(1, m1, j2, M - m1, J, M) * PH.clebsch_gordan(1, m1, j2, M - m1, Jp, M)
+                        for m1 in (-1, 0, 1))
+                assert abs(s - (1.0 if J == Jp else 0.0)) < 1e-13
+
+
+def _wigner_small_d(j, mp, m, beta):
+    """d^j_{m' m}(beta) by Wigner's explicit sum (independent of the coupling route)."""
+    f = math.factorial
+    c, s = np.cos(beta / 2.0), np.sin(beta / 2.0)
+    out = np.zeros_like(beta)
+    for k in range(max(0, m - mp), min(j + m, j - mp) + 1):
+        num = (-1) ** (mp - m + k) * math.sqrt(f(j + mp) * f(j - mp) * f(j + m) * f(j - m))
+        den = f(j + m - k) * f(k) * f(j - k - mp) * f(k - m + mp)
+        out = out + num / den * c ** (2 * j - 2 * k + m - mp) * s ** (2 * k - m + mp)
+    return out
+
+
+def _W(J, M, par, om, phi, th, chi):
+    """W^{JMp}_{Omega, Lambda=0} of Eq. angular-functions (sigma = +1) on Euler-angle grids."""
+    def Dstar(mp, m):
+        return np.exp(1j * mp * phi) * _wigner_small_d(J, mp, m, th) * np.exp(1j * m * chi)
+    norm = math.sqrt((2 * J + 1) / (16 * math.pi ** 2 * (1 + (om == 0))))
+    return norm * (Dstar(M, om) + par * (-1) ** (J + om) * Dstar(M, -om))
+
+
+@pytest.mark.parametrize("J,par,Ji,Mi,pari,pol", [(1, -1, 0, 0, 1, 0), (2, 1, 1, 0, -1, 0),
+                                                  (3, -1, 2, 1, 1, 1), (2, -1, 2, -1, -1, -1),
+                                                  (4, 1, 3, 2, 1, -1)])
+def test_dipole_coupling_equals_euler_angle_quadrature(J, par, Ji, Mi, pari, pol):
+    """<W_Omega|D^{1*}_{pol q}|W_Omega_i> by direct quadrature over (phi, theta, chi)
+    with Wigner's d-function sum equals the oracle's Clebsch-Gordan reduction, for
+    every Omega, Omega_i and q (zero where the selection rules forbid)."""
+    n_ang, n_th = 16, 96
+    phi = 2 * math.pi * np.arange(n_ang) / n_ang
+    xg, wg = np.polynomial.legendre.leggauss(n_th)
+    th = 0.5 * math.pi * (xg + 1.0)
+    wt = 0.5 * math.pi * wg * np.sin(th)
+    P, T, C = np.meshgrid(phi, th, phi, indexing="ij")
+    wts = (2 * math.pi / n_ang) ** 2 * wt[None, :, None]
+    M = Mi + pol
+    if abs(M) > J:
+        pytest.skip("M outside the final J")
+    oms = [o for o in range(0, J + 1) if not (o == 0 and par * (-1) ** J != 1)]
+    omis = [o for o in range(0, Ji + 1) if not (o == 0 and pari * (-1) ** Ji != 1)]
+    checked = 0
+    for om in oms:
+        Wf = np.conj(_W(J, M, par, om, P, T, C))
+        for omi in omis:
+            Wi = _W(Ji, Mi, pari, omi, P, T, C)
+            for q in (-1, 0, 1):
+                D1s = np.exp(1j * pol * P) * _wigner_small_d(1, pol, q, T) * np.exp(1j * q * C)
+                quad = np.sum(wts * Wf * D1s * Wi)
+                want = PH.dipole_coupling(J, M, par, Ji, Mi, pari, om, omi, q, pol)
+                assert abs(quad.imag) < 1e-13
+                assert abs(quad.real - want) < 1e-12, (om, omi, q, quad, want)
+                checked += abs(want) > 1e-6
+    assert checked > 0
+
+
+def test_photo_packet_j0_to_j1_linear_polarisation_closed_form():
+    """J_i = 0 -> J = 1 (final parity -1, helicities 0 and 1), linear polarisation:
+    Phi_0 = d_z Phi_i / sqrt(3) and Phi_1 = -d_x Phi_i / sqrt(3) for a dipole in the
+    x-z plane (d_{+-1} = -+ d_x / sqrt(2), d_0 = d_z): the relative sign of the two
+    helicity blocks is fixed, and |Phi_0|^2 + |Phi_1|^2 = |d|^2 |Phi_i|^2 / 3."""
+    s = tiny_spec(J=1, omega_max=1)
+    s["units"] = [dict(J=1, parity=-1, omega_max=1, n_packets=1)]
+    rng = np.random.default_rng(7)
+    shape = (s["n_gamma"], s["n_R"], s["n_r"])
+    bound = rng.standard_normal((1,) + shape)
+    dx, dz = rng.standard_normal(shape), rng.standard_normal(shape)
+    dip = np.stack([dx / math.sqrt(2), dz, -dx / math.sqrt(2)])
+    u = PH.photo_packet(s, 0, 0, 0, 0, 1, [0], bound, dip, 0)
+    assert u.shape == (2, 1) + shape
+    assert np.max(np.abs(u[0, 0] - dz * bound[0] / math.sqrt(3))) < 1e-14
+    assert np.max(np.abs(u[1, 0] + dx * bound[0] / math.sqrt(3))) < 1e-14
+    # the same J with parity +1 (helicity 1 only) is reached by no in-plane dipole
+    s["units"] = [dict(J=1, parity=1, omega_max=1, n_packets=1)]
+    assert np.max(np.abs(PH.photo_packet(s, 0, 0, 0, 0, 1, [0], bound, dip, 0))) < 1e-15
