@@ -1117,14 +1117,17 @@ __global__ void k_to_format(const double* __restrict__ src, typename Fmt<P>::E* 
 // ---- energy accumulation: acc[c e][s] += sum_b coef[c e][b] ring[b][s] ----------------
 // M = 2 n_E rows (real and imaginary parts), K = buffered steps, N = slice values.
 // One workgroup per 32 slice values; wave w owns M-tiles w, w+4, ...
-// The K loop runs in chunks of eight ring rows (two matrix-core k-steps); within a
-// chunk lane l takes rows 2 (l/16) and 2 (l/16) + 1 for both operands (any pairing
-// of k between the operands' fragments is a valid contraction as long as it is
-// the same for A and B), so its two coefficients are one 16-byte load.  The loads
-// of the next chunk are issued before the current chunk's products (two register
-// buffers), so the ring's HBM latency and the coefficients' L2 latency overlap
-// the matrix-core work instead of preceding each k-step.
+// The workgroup's slab of the ring (K x 32 values, 64 KB at K = 256) is loaded
+// into LDS with every load in flight at once, so the ring's HBM latency is paid
+// once per workgroup.  The coefficients (shared by all workgroups of a packet,
+// L2-resident) are read in chunks of eight ring rows (two matrix-core k-steps):
+// within a chunk lane l takes rows 2 (l/16) and 2 (l/16) + 1 for both operands
+// (any pairing of k between the operands' fragments is a valid contraction as
+// long as it is the same for A and B), so its two coefficients are one 16-byte
+// load, and the next chunk's loads are issued before the current chunk's
+// products (two register buffers).
 constexpr int kAccMaxMT = 8;   // M-tiles per wave (2 n_E <= 512)
+constexpr int kAccCols = 32;   // slice values per workgroup
 struct AccDesc {
   unsigned long acc_off;    // accumulators of the packet [2 n_E][n_slice]
   unsigned long slice_off;  // the packet's slice values in a ring row
@@ -1140,6 +1143,7 @@ __global__ __launch_bounds__(256, 2) void k_accum_mfma(double* __restrict__ acc_
                                                        int rows, int count) {
   using M = Mma<kP64>;
   typedef double v2d __attribute__((ext_vector_type(2)));
+  extern __shared__ __align__(16) double slab[];   // [8 * nch][kAccCols]
   const int l = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int pk = find_packet(blk_start, n_pk, blockIdx.x);
   const AccDesc ad = ads[pk];
@@ -1147,35 +1151,41 @@ __global__ __launch_bounds__(256, 2) void k_accum_mfma(double* __restrict__ acc_
   const double* __restrict__ coef = coef_all + (size_t)pk * rows * ldc;
   const double* __restrict__ ring = ring_all + ad.slice_off;
   const int n_slice = ad.n_slice;
-  const int s0 = (blockIdx.x - blk_start[pk]) * 32;
+  const int s0 = (blockIdx.x - blk_start[pk]) * kAccCols;
   const int MT = (rows + 15) >> 4;
   const int kq = 2 * (l >> 4);
+  const int nch = (count + 7) >> 3;
+  // ---- the ring slab: rows [0, 8 nch), columns s0 .. s0 + 31 (zero outside) ----
+  {
+    const int col = threadIdx.x & (kAccCols - 1);
+    const int s = s0 + col;
+    const bool sok = s < n_slice;
+    const int sc = sok ? s : n_slice - 1;   // clamped, in-range address
+    const int r0 = threadIdx.x / kAccCols;  // 8 rows per pass of the 256 threads
+    constexpr int kBatch = 32;              // rows 8 * kBatch = 256 per thread batch
+    for (int rb = 0; rb < 8 * nch; rb += 8 * kBatch) {
+      double x[kBatch];
+#pragma unroll
+      for (int q = 0; q < kBatch; ++q) {
+        const int k = rb + r0 + 8 * q;
+        const int kc = k < count ? k : count - 1;
+        x[q] = ring[(size_t)kc * ring_stride + sc];
+      }
+#pragma unroll
+      for (int q = 0; q < kBatch; ++q) {
+        const int k = rb + r0 + 8 * q;
+        if (k < 8 * nch) slab[k * kAccCols + col] = (k < count && sok) ? x[q] : 0.0;
+      }
+    }
+  }
+  __syncthreads();
   M::acc_t c[kAccMaxMT][2];
 #pragma unroll
   for (int a = 0; a < kAccMaxMT; ++a) c[a][0] = c[a][1] = M::zero();
-  int scol[2];
-  bool sok[2];
-#pragma unroll
-  for (int nt = 0; nt < 2; ++nt) {
-    const int s = s0 + nt * 16 + (l & 15);
-    sok[nt] = s < n_slice;
-    scol[nt] = sok[nt] ? s : n_slice - 1;   // clamped, in-range address
-  }
-  // fragments of one chunk: A[tile] = (row r, ring rows kb, kb + 1), B[cc][nt]
+  // coefficient fragments of one chunk: A[tile] = (row r, ring rows kb, kb + 1)
   v2d A0[kAccMaxMT], A1[kAccMaxMT];
-  double B0[2][2], B1[2][2];
-  auto load = [&](v2d (&A)[kAccMaxMT], double (&B)[2][2], int ch) {
-    const int kb = 8 * ch + kq;   // even; kb + 1 < 8 * nchunks <= ldc
-#pragma unroll
-    for (int cc = 0; cc < 2; ++cc) {
-      const int k = kb + cc;
-      const int kr = k < count ? k : count - 1;
-#pragma unroll
-      for (int nt = 0; nt < 2; ++nt) {
-        const double x = ring[(size_t)kr * ring_stride + scol[nt]];
-        B[cc][nt] = (k < count && sok[nt]) ? x : 0.0;
-      }
-    }
+  auto load = [&](v2d (&A)[kAccMaxMT], int ch) {
+    const int kb = 8 * ch + kq;   // even; kb + 1 < 8 * nch <= ldc
 #pragma unroll
     for (int a = 0; a < kAccMaxMT; ++a) {
       const int mt = w + 4 * a;
@@ -1187,24 +1197,27 @@ __global__ __launch_bounds__(256, 2) void k_accum_mfma(double* __restrict__ acc_
       A[a] = v2d{(rok && kb < count) ? x[0] : 0.0, (rok && kb + 1 < count) ? x[1] : 0.0};
     }
   };
-  auto compute = [&](const v2d (&A)[kAccMaxMT], const double (&B)[2][2]) {
+  auto compute = [&](const v2d (&A)[kAccMaxMT], int ch) {
 #pragma unroll
-    for (int cc = 0; cc < 2; ++cc)
+    for (int cc = 0; cc < 2; ++cc) {
+      const int k = 8 * ch + kq + cc;
+      const double b0 = slab[k * kAccCols + (l & 15)];
+      const double b1 = slab[k * kAccCols + 16 + (l & 15)];
 #pragma unroll
       for (int a = 0; a < kAccMaxMT; ++a) {
         const int mt = w + 4 * a;
         if (mt >= MT) break;
-        M::mma(c[a][0], A[a][cc], B[cc][0]);
-        M::mma(c[a][1], A[a][cc], B[cc][1]);
+        M::mma(c[a][0], A[a][cc], b0);
+        M::mma(c[a][1], A[a][cc], b1);
       }
+    }
   };
-  const int nch = (count + 7) >> 3;
-  if (nch > 0) load(A0, B0, 0);
+  if (nch > 0) load(A0, 0);
   for (int ch = 0; ch < nch; ch += 2) {
-    if (ch + 1 < nch) load(A1, B1, ch + 1);
-    compute(A0, B0);
-    if (ch + 2 < nch) load(A0, B0, ch + 2);
-    if (ch + 1 < nch) compute(A1, B1);
+    if (ch + 1 < nch) load(A1, ch + 1);
+    compute(A0, ch);
+    if (ch + 2 < nch) load(A0, ch + 2);
+    if (ch + 1 < nch) compute(A1, ch + 1);
   }
 #pragma unroll
   for (int a = 0; a < kAccMaxMT; ++a) {
@@ -1212,8 +1225,8 @@ __global__ __launch_bounds__(256, 2) void k_accum_mfma(double* __restrict__ acc_
     if (mt >= MT) break;
 #pragma unroll
     for (int nt = 0; nt < 2; ++nt) {
-      if (!sok[nt]) continue;
       const int s = s0 + nt * 16 + (l & 15);
+      if (s >= n_slice) continue;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int r = mt * 16 + M::row(l, v);

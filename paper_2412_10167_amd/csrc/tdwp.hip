@@ -718,7 +718,7 @@ int layout_and_allocate(Plan* P) {
   for (auto& pk : P->packets) {
     line_start.push_back(line_start.back() + pk.n_sv);
     slice_off.push_back(pk.slice_off);
-    blk_acc.push_back(blk_acc.back() + (pk.n_slice + 31) / 32);
+    blk_acc.push_back(blk_acc.back() + (pk.n_slice + kAccCols - 1) / kAccCols);
     ad.push_back(AccDesc{pk.acc_off, pk.slice_off, pk.n_slice});
   }
   P->blocks_acc = blk_acc.back();
@@ -906,7 +906,8 @@ int flush_ring(Plan* P) {
                      P->ring_len, nE, c.ecol_min, step, P->d_E, np, P->E0, P->dE, P->ring_k0,
                      P->ring_count);
   if (P->fast_accum) {
-    hipLaunchKernelGGL(k_accum_mfma, dim3(P->blocks_acc), dim3(256), 0, P->stream, P->d_acc,
+    const size_t slab = (size_t)8 * ((P->ring_count + 7) / 8) * kAccCols * sizeof(double);
+    hipLaunchKernelGGL(k_accum_mfma, dim3(P->blocks_acc), dim3(256), slab, P->stream, P->d_acc,
                        P->d_coef, P->ring_len, P->d_ring, P->slice_total,
                        (const AccDesc*)P->d_accdesc, P->d_blk_acc, np, 2 * nE, P->ring_count);
   } else {
