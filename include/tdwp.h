@@ -53,7 +53,8 @@ enum tdwp_status {
   TDWP_ENOMEM = -2,   /* device allocation failed or the plan exceeds limits    */
   TDWP_EDEVICE = -3,  /* HIP runtime error (no device, launch failure)          */
   TDWP_ESTATE = -4,   /* call out of order, e.g. propagate before a packet      */
-  TDWP_ERANGE = -5    /* packet norm diverged: spectral bounds too narrow       */
+  TDWP_ERANGE = -5,   /* packet norm diverged: spectral bounds too narrow       */
+  TDWP_ESCRATCH = -6  /* a no-allocation call's input exceeds its fixed scratch */
 };
 
 /* Arithmetic of the kinetic and angular contractions (the recursion, damping,
@@ -187,6 +188,19 @@ int tdwp_mlp_gradient(tdwp_plan_t p, const float* params, int n_pts, const doubl
 /* Inference kernel on n_pts points with the plan's trained network (BF16
  * weights): v_out [n_pts][n_pair] in hartree. */
 int tdwp_mlp_eval(tdwp_plan_t p, int n_pts, const double* dist, double* v_out);
+
+/* tdwp_mlp_eval without any device allocation, for callers that cannot
+ * allocate (serving loops evaluating the learned surface point by point,
+ * harnesses that forbid hipMalloc).  Same kernel and results as tdwp_mlp_eval;
+ * the distances and outputs are staged in a fixed device array of 4 MiB
+ * (2^19 doubles) that each GPU the library runs on holds until the process
+ * ends.  Limit: n_pts * (3 + n_pair) <= 2^19 (n_pair = n_elec (n_elec + 1) / 2),
+ * else TDWP_ESCRATCH and nothing runs.  Every call on one GPU shares that
+ * GPU's array, so calls that overlap on one GPU (other host threads, other
+ * plans) race; calls from one thread in turn are safe.  dist [n_pts][3] and
+ * v_out [n_pts][n_pair] are host arrays, as for tdwp_mlp_eval.
+ * Errors: EINVAL, ESTATE (no trained network), ESCRATCH, EDEVICE. */
+int tdwp_mlp_eval_noalloc(tdwp_plan_t p, int n_pts, const double* dist, double* v_out);
 
 /* The network's potential on the plan's grid, v_out laid out like the table of
  * tdwp_set_potential (the values every step uses after tdwp_set_potential_mlp). */

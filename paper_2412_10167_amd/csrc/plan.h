@@ -136,6 +136,7 @@ struct tdwp_plan_s {
   int ring_len = tdwp::kRing;
   long ring_k0 = 0;
   // device
+  int device = -1;           // HIP device current when the plan was made
   hipStream_t stream = nullptr;
   bool own_stream = false;
   double* d_u[2] = {nullptr, nullptr};

@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <type_traits>
@@ -1661,6 +1662,35 @@ void reset_propagation(Plan* P) {
 
 // ---- C ABI -------------------------------------------------------------------
 
+// ---- fixed scratch of the network inference without allocation ------------------
+// Device memory for tdwp_mlp_eval_noalloc: the distances of the call, then its
+// outputs.  Each GPU holds its own copy for the life of the process; the host
+// reaches it only through the address hipGetSymbolAddress returns on that
+// device (the array's name is a host-side stand-in, not a device address).
+constexpr size_t kNoAllocDoubles = (size_t)1 << 19;   // 4 MiB
+static __device__ __align__(256) double scratch[kNoAllocDoubles];
+
+namespace {
+constexpr int kMaxDevices = 64;
+double* g_scratch_dev[kMaxDevices] = {};
+std::mutex g_scratch_mu;
+
+// Once per device, with that device current: the device address of its copy.
+int scratch_setup(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return TDWP_EDEVICE;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_dev[dev]) return TDWP_OK;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr) {
+    (void)hipGetLastError();
+    return TDWP_EDEVICE;
+  }
+  g_scratch_dev[dev] = static_cast<double*>(ptr);
+  return TDWP_OK;
+}
+}  // namespace
+
 extern "C" int bounds_from_table(tdwp_plan_t p, const double* v);
 
 extern "C" {
@@ -1675,8 +1705,15 @@ int tdwp_plan(const tdwp_config* cfg, tdwp_plan_t* out) {
     return TDWP_EDEVICE;
   }
   query_lds_limit();
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return TDWP_EDEVICE;
+  }
+  TRY(scratch_setup(dev));
   Plan* P = new (std::nothrow) Plan();
   if (!P) return TDWP_ENOMEM;
+  P->device = dev;
   P->cfg = *cfg;
   P->units_in.assign(cfg->units, cfg->units + cfg->n_units);
   P->cfg.units = nullptr;
@@ -2536,6 +2573,24 @@ int tdwp_mlp_eval(tdwp_plan_t p, int n_pts, const double* dist, double* v_out) {
   return TDWP_OK;
 }
 
+int tdwp_mlp_eval_noalloc(tdwp_plan_t p, int n_pts, const double* dist, double* v_out) {
+  if (!p || !dist || !v_out || n_pts < 1) return TDWP_EINVAL;
+  if (!p->d_mlp_theta || p->pot_mode != TDWP_POT_MLP) return TDWP_ESTATE;
+  const size_t need = (size_t)n_pts * (3 + (size_t)p->npair);
+  if (need > kNoAllocDoubles) return TDWP_ESCRATCH;
+  double* base = (p->device >= 0 && p->device < kMaxDevices) ? g_scratch_dev[p->device] : nullptr;
+  if (!base) return TDWP_EDEVICE;
+  double* dd = base;                          // [n_pts][3] distances
+  double* dv = base + (size_t)n_pts * 3;      // [n_pts][n_pair] outputs (every entry written)
+  HIP_TRY(hipMemcpyAsync(dd, dist, (size_t)n_pts * 3 * sizeof(double), hipMemcpyHostToDevice, p->stream));
+  hipLaunchKernelGGL(k_mlp_eval, dim3((n_pts + 63) / 64), dim3(256), 0, p->stream, mlp_net(p), dd,
+                     n_pts, dv);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(v_out, dv, (size_t)n_pts * p->npair * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  return TDWP_OK;
+}
+
 int tdwp_mlp_grid(tdwp_plan_t p, double* v_out) {
   if (!p || !v_out) return TDWP_EINVAL;
   if (!p->d_mlp_theta || p->pot_mode != TDWP_POT_MLP) return TDWP_ESTATE;
@@ -2563,6 +2618,7 @@ const char* tdwp_strerror(int code) {
     case TDWP_EDEVICE: return "HIP device error";
     case TDWP_ESTATE: return "call out of order";
     case TDWP_ERANGE: return "packet norm diverged (spectral bounds too narrow)";
+    case TDWP_ESCRATCH: return "input larger than the fixed scratch area of a no-allocation call";
     default: return "unknown error";
   }
 }

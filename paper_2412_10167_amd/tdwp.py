@@ -16,7 +16,7 @@ EXPORTED_SYMBOLS = (
     "tdwp_spectral_bounds", "tdwp_set_initial_packet", "tdwp_propagate", "tdwp_step_index",
     "tdwp_get_packet", "tdwp_state_to_state", "tdwp_time_kernels", "tdwp_destroy",
     "tdwp_strerror", "tdwp_mlp_n_params", "tdwp_set_potential_mlp", "tdwp_mlp_params",
-    "tdwp_mlp_gradient", "tdwp_mlp_eval", "tdwp_mlp_grid", "tdwp_autotune",
+    "tdwp_mlp_gradient", "tdwp_mlp_eval", "tdwp_mlp_eval_noalloc", "tdwp_mlp_grid", "tdwp_autotune",
     "tdwp_set_option", "tdwp_get_stat", "tdwp_jshift", "tdwp_jshift_interpolate",
     "tdwp_cumulative_probability", "tdwp_cross_section", "tdwp_fit_jshift_b",
     "tdwp_set_packet_values", "tdwp_autocorrelation", "tdwp_energy_content",
@@ -123,6 +123,7 @@ def load_library():
     lib.tdwp_mlp_params.argtypes = [P, fp]
     lib.tdwp_mlp_gradient.argtypes = [P, fp, ctypes.c_int, dp, dp, dp, fp]
     lib.tdwp_mlp_eval.argtypes = [P, ctypes.c_int, dp, dp]
+    lib.tdwp_mlp_eval_noalloc.argtypes = [P, ctypes.c_int, dp, dp]
     lib.tdwp_mlp_grid.argtypes = [P, dp]
     lib.tdwp_autotune.argtypes = [P, ctypes.c_int, ctypes.c_char_p, ctypes.c_size_t]
     lib.tdwp_set_option.argtypes = [P, ctypes.c_int, ctypes.c_long]
@@ -376,6 +377,15 @@ class Plan:
         d = _f64(dist)
         out = np.empty((d.shape[0], self.spec["n_elec"] * (self.spec["n_elec"] + 1) // 2))
         _check(self.lib.tdwp_mlp_eval(self.handle, d.shape[0], _ptr(d), _ptr(out)), "tdwp_mlp_eval")
+        return out
+
+    def mlp_eval_noalloc(self, dist):
+        """tdwp_mlp_eval_noalloc: the same inference staged in the library's fixed
+        device scratch (no device allocation)."""
+        d = _f64(dist)
+        out = np.empty((d.shape[0], self.spec["n_elec"] * (self.spec["n_elec"] + 1) // 2))
+        _check(self.lib.tdwp_mlp_eval_noalloc(self.handle, d.shape[0], _ptr(d), _ptr(out)),
+               "tdwp_mlp_eval_noalloc")
         return out
 
     def set_option(self, name, value):
