@@ -367,14 +367,16 @@ def r_inf_index(op):
 # ---------------------------------------------------------------------------
 
 def propagate(op, unit_index, u0, K, keep_vectors=(), undamped=False, damping=None,
-              extra_r_flux=()):
+              extra_r_flux=(), line_fn=None):
     """Chebyshev components u_0..u_K with norms and per-k slices.
 
     u_1 = D H_s u_0;  u_{k+1} = D (2 H_s u_k - D u_{k-1});  D = e^{-phi}.
     `damping` replaces D by any array broadcastable to u (tests); `undamped`
     sets D = 1.  Returns dict with norms[k], s_val[k], s_der[k] (flux line at
     r*; one more pair per entry of extra_r_flux in `extra`), w[k] (R_inf line
-    / sqrt(dR)) and the vectors u_k for k in keep_vectors ("all" keeps every one)."""
+    / sqrt(dR)), lines[k] = line_fn(u_k) when line_fn is given (another
+    analysis line, e.g. a product arrangement's), and the vectors u_k for k in
+    keep_vectors ("all" keeps every one)."""
     if damping is not None:
         D = damping
     else:
@@ -383,7 +385,7 @@ def propagate(op, unit_index, u0, K, keep_vectors=(), undamped=False, damping=No
     extra_rows = [flux_rows(op, rs) for rs in extra_r_flux]
     mi = r_inf_index(op)
     out = dict(norms=np.empty(K + 1), s_val=[], s_der=[], w=[], vectors={},
-               extra=[([], []) for _ in extra_rows])
+               extra=[([], []) for _ in extra_rows], lines=[])
 
     def record(k, u):
         out["norms"][k] = float(np.sum(u * u))
@@ -393,6 +395,8 @@ def propagate(op, unit_index, u0, K, keep_vectors=(), undamped=False, damping=No
             lv.append(u @ ar)
             ld.append(u @ dr)
         out["w"].append(u[:, :, :, mi, :] / math.sqrt(op.dR))
+        if line_fn is not None:
+            out["lines"].append(line_fn(u))
         if keep_vectors == "all" or k in keep_vectors:
             out["vectors"][k] = u.copy()
 
@@ -410,7 +414,7 @@ def propagate(op, unit_index, u0, K, keep_vectors=(), undamped=False, damping=No
 
 
 def _stack(out):
-    for key in ("s_val", "s_der", "w"):
+    for key in ("s_val", "s_der", "w", "lines"):
         out[key] = np.array(out[key])
     out["extra"] = [(np.array(lv), np.array(ld)) for lv, ld in out["extra"]]
     return out
