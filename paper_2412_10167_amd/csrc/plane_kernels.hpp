@@ -71,7 +71,8 @@ struct PlaneArgs {
 };
 
 template <int P>
-__global__ __launch_bounds__(kPlaneThreads, 2) void k_plane_epi(PlaneArgs A) {
+__global__ __launch_bounds__(kPlaneThreads) __attribute__((amdgpu_waves_per_eu(4)))
+void k_plane_epi(PlaneArgs A) {
   using M = Mma<P>;
   using F = Fmt<P>;
   using E = typename F::E;
@@ -94,13 +95,15 @@ __global__ __launch_bounds__(kPlaneThreads, 2) void k_plane_epi(PlaneArgs A) {
     const int row = q / ldx, col = q - row * ldx;
     if (row >= nR || col >= nr) X[q] = 0.0f;
   }
-  // per-lane columns of a row and their flux-row entries
-  const int cpl = (nr + 63) >> 6;
+  // per-lane column pairs of a row (c = 2 l + 128 j, n_r even) and their flux-row
+  // entries
+  constexpr int kPairs = kPlaneMaxCols / 2;
+  const int ppl = (nr + 127) >> 7;
   double ar[kPlaneMaxCols], dr[kPlaneMaxCols];
 #pragma unroll
   for (int j = 0; j < kPlaneMaxCols; ++j) {
-    const int c = l + 64 * j;
-    const bool ok = j < cpl && c < nr;
+    const int c = 2 * l + 128 * (j >> 1) + (j & 1);
+    const bool ok = (j >> 1) < ppl && c < nr;
     ar[j] = (rec_ok && ok) ? A.arow[c] : 0.0;
     dr[j] = (rec_ok && ok) ? A.drow[c] : 0.0;
   }
@@ -127,16 +130,20 @@ __global__ __launch_bounds__(kPlaneThreads, 2) void k_plane_epi(PlaneArgs A) {
       soff = A.slice_off[pk];
       nsv = A.line_start[pk + 1] - A.line_start[pk];
     }
+    typedef double v2d __attribute__((ext_vector_type(2)));
+    typedef float v2f __attribute__((ext_vector_type(2)));
     for (int m0 = w; m0 < nR; m0 += nw * kPlaneRowsPerBatch) {
-      double v[kPlaneRowsPerBatch][kPlaneMaxCols];
+      // 16-byte loads of column pairs (n_r even; rows start at even offsets)
+      v2d v[kPlaneRowsPerBatch][kPairs];
 #pragma unroll
       for (int b = 0; b < kPlaneRowsPerBatch; ++b) {
         const int m = m0 + nw * b;
         const int mc = m < nR ? m : nR - 1;
 #pragma unroll
-        for (int j = 0; j < kPlaneMaxCols; ++j) {
-          const int c = l + 64 * j;
-          v[b][j] = (j < cpl) ? uk[(size_t)mc * nr + (c < nr ? c : nr - 1)] : 0.0;
+        for (int j = 0; j < kPairs; ++j) {
+          const int c = 2 * l + 128 * j;
+          v[b][j] = (j < ppl) ? *reinterpret_cast<const v2d*>(uk + (size_t)mc * nr + (c < nr ? c : nr - 2))
+                              : v2d{0.0, 0.0};
         }
       }
 #pragma unroll
@@ -145,14 +152,16 @@ __global__ __launch_bounds__(kPlaneThreads, 2) void k_plane_epi(PlaneArgs A) {
         if (m >= nR) break;
         double sv = 0.0, sd = 0.0;
 #pragma unroll
-        for (int j = 0; j < kPlaneMaxCols; ++j) {
-          const int c = l + 64 * j;
-          if (j < cpl && c < nr) {
-            X[m * ldx + c] = (float)v[b][j];
-            sv += ar[j] * v[b][j];
-            sd += dr[j] * v[b][j];
+        for (int j = 0; j < kPairs; ++j) {
+          const int c = 2 * l + 128 * j;
+          if (j < ppl && c < nr) {
+            const v2d x = v[b][j];
+            *reinterpret_cast<v2f*>(X + m * ldx + c) = v2f{(float)x[0], (float)x[1]};
+            sv += ar[2 * j] * x[0] + ar[2 * j + 1] * x[1];
+            sd += dr[2 * j] * x[0] + dr[2 * j + 1] * x[1];
             if (rec_ok && m == A.m_inf)
-              ring_row[soff + 2 * nsv + (size_t)local * nr + c] = v[b][j] * A.inv_sqrt_dR;
+              *reinterpret_cast<v2d*>(ring_row + soff + 2 * nsv + (size_t)local * nr + c) =
+                  v2d{x[0] * A.inv_sqrt_dR, x[1] * A.inv_sqrt_dR};
           }
         }
         if (rec_ok) {
