@@ -248,8 +248,9 @@ int tdwp_state_to_state(tdwp_plan_t p, int unit, int slot, int n_ch, const tdwp_
 
 /* ---- Photodissociation packets (Sec. "Initial wave packet in photodissociation")
  * A photodissociation packet is the transition dipole applied to an initial bound
- * state, projected on the unit's helicity blocks (Eq. initial-photo-wvp); the
- * caller builds it.  Its energy content is not known in advance and follows from
+ * state, projected on the unit's helicity blocks (Eq. initial-photo-wvp), built
+ * by tdwp_photo_packet from the bound state and the dipole, or by the caller and
+ * installed with tdwp_set_packet_values.  Its energy content is not known in advance and follows from
  * the autocorrelation C_k = <u_0|u_k> of the propagated packet (Eqs.
  * fourier-transform, chebyshev-transform), which the library forms on the
  * device after every step: in the R pass on the matrix-core path with a
@@ -263,6 +264,29 @@ int tdwp_state_to_state(tdwp_plan_t p, int unit, int slot, int n_ch, const tdwp_
  * its autocorrelation; tdwp_state_to_state refuses it (TDWP_ESTATE).
  * Errors: EINVAL (no such packet, u0 zero or not finite), ESTATE (no potential). */
 int tdwp_set_packet_values(tdwp_plan_t p, int unit, int slot, const double* u0);
+
+/* Builds and installs the photodissociation packet of Eq. initial-photo-wvp in
+ * packet (unit, slot): sum over Omega of |W^{JMp}_Omega> <W^{JMp}_Omega| d.e |Psi_i>,
+ * with J and p the unit's (Eq. angular-functions; the unit's helicities only),
+ * d.e = sum_q (-1)^pol D^{1*}_{pol q} d_q (unit polarisation component
+ * (e)_{-pol}), so the final M is M_i + pol; Lambda = 0 electronic states with
+ * sigma = +1.  The Euler-angle integrals are Clebsch-Gordan coefficients; the
+ * result is local in (r, R, gamma) and lands in diabatic state `elec`, the other
+ * states zero.  Then as tdwp_set_packet_values.
+ *   J_i, M_i, p_i: the bound state's total angular momentum, its projection and
+ *     parity; its helicity components Omega_i = om_lo_i .. om_lo_i + n_om_i - 1;
+ *   bound [n_om_i][n_gamma][n_R][n_r]: those components on the plan's grid,
+ *     DVR-weighted like a packet (host, borrowed);
+ *   dip [3][n_gamma][n_R][n_r]: the body-frame spherical components d_q,
+ *     q = -1, 0, +1, of the transition dipole (real; a dipole in the x-z plane
+ *     has d_{+1} = -d_x / sqrt 2, d_{-1} = d_x / sqrt 2, d_0 = d_z);
+ *   pol: -1, 0 (linear, space-fixed z along the polarisation) or +1.
+ * Errors: EINVAL (no such packet or state, |M_i| > J_i, p_i not +-1, helicities
+ * outside 0..J_i or an Omega_i = 0 component with p_i (-1)^J_i = -1, |M_i + pol|
+ * above the unit's J, or a transition that the dipole cannot make: the packet
+ * is zero), ESTATE (no potential). */
+int tdwp_photo_packet(tdwp_plan_t p, int unit, int slot, int elec, int J_i, int M_i, int p_i,
+                      int om_lo_i, int n_om_i, const double* bound, const double* dip, int pol);
 
 /* out = H in for packet (unit, slot): the plan's Hamiltonian (Eq. hamiltonian,
  * with its radial and rotational caps, the potential installed, no damping)

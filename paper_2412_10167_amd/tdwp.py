@@ -21,6 +21,7 @@ EXPORTED_SYMBOLS = (
     "tdwp_cumulative_probability", "tdwp_cross_section", "tdwp_fit_jshift_b",
     "tdwp_set_packet_values", "tdwp_autocorrelation", "tdwp_energy_content",
     "tdwp_photo_cross_section", "tdwp_apply_hamiltonian", "tdwp_lowest_state",
+    "tdwp_photo_packet",
 )
 OPTIONS = {"graphs": 0, "ang_tile": 1, "radial_grid": 2, "ang_kernel": 3, "fuse_r": 4,
            "ang_xcd": 5, "plane_r": 6}
@@ -138,6 +139,7 @@ def load_library():
     lib.tdwp_fit_jshift_b.argtypes = [dp, dp, dp, ci, ci, ci, cd, dp]
     cl = ctypes.c_long
     lib.tdwp_set_packet_values.argtypes = [P, ci, ci, dp]
+    lib.tdwp_photo_packet.argtypes = [P, ci, ci, ci, ci, ci, ci, ci, ci, dp, dp, ci]
     lib.tdwp_autocorrelation.argtypes = [P, ci, ci, cl, dp]
     lib.tdwp_apply_hamiltonian.argtypes = [P, ci, ci, dp, dp]
     lib.tdwp_lowest_state.argtypes = [P, ci, ci, dp, ci, dp, dp, dp]
@@ -299,6 +301,19 @@ class Plan:
             raise ValueError(f"packet of unit {unit} has {n} values, got {u.size}")
         _check(self.lib.tdwp_set_packet_values(self.handle, unit, slot, _ptr(u)),
                "tdwp_set_packet_values")
+
+    def photo_packet(self, unit, slot, elec, J_i, M_i, p_i, om_lo_i, bound, dip, pol):
+        """tdwp_photo_packet: bound [n_om_i][n_gamma][n_R][n_r], dip [3][n_gamma][n_R][n_r]
+        (body-frame d_q, q = -1, 0, +1)."""
+        b = _f64(bound)
+        d = _f64(dip)
+        s = self.spec
+        pts = s["n_gamma"] * s["n_R"] * s["n_r"]
+        if b.size % pts or d.size != 3 * pts:
+            raise ValueError("bound / dip do not match the plan's grid")
+        self._photo_keep = (b, d)
+        _check(self.lib.tdwp_photo_packet(self.handle, unit, slot, elec, J_i, M_i, p_i, om_lo_i,
+                                          b.size // pts, _ptr(b), _ptr(d), pol), "tdwp_photo_packet")
 
     def apply_hamiltonian(self, u, unit=0, slot=0):
         """H u (undamped) for a vector in the layout of packet (unit, slot); no packet

@@ -78,3 +78,31 @@ def bound_spec(spec):
     s["packets"] = []
     s["pes"] = dict(spec["pes"], shifts=[0.0], couplings={})
     return s
+
+
+def bound_components(r, R, x, w, n_om_i):
+    """Stand-in bound-state helicity components [n_om_i][n_gamma][n_R][n_r]
+    (DVR-weighted): a Gaussian in the interaction region with an angular factor
+    that differs per component."""
+    rr, RR, xx = r[None, None, :], R[None, :, None], x[:, None, None]
+    dr, dR = r[1] - r[0], R[1] - R[0]
+    wgt = np.sqrt(dr * dR * np.asarray(w))[:, None, None]
+    out = np.empty((n_om_i, len(x), len(R), len(r)))
+    for b in range(n_om_i):
+        ang = (1.0 - xx * xx) ** (0.5 * b) * (1.0 + 0.3 * xx + 0.1 * (b + 1) * xx * xx)
+        out[b] = wgt * np.exp(-((rr - 1.4) / 0.25) ** 2 - ((RR - 3.0) / 0.4) ** 2) * ang / (1 + b)
+    return out
+
+
+def dipole_components(r, R, x):
+    """Body-frame spherical components d_q, q = -1, 0, +1 [3][n_gamma][n_R][n_r], of
+    a stand-in transition dipole in the molecular x-z plane: d_z along R, d_x
+    across it, smooth in (r, R, gamma); d_{+1} = -d_x / sqrt 2, d_{-1} = d_x / sqrt 2,
+    d_0 = d_z."""
+    rr, RR, xx = r[None, None, :], R[None, :, None], x[:, None, None]
+    dz = np.tanh(0.5 * (RR - 1.0)) * (1.0 + 0.2 * (rr - 1.4)) * (0.6 + 0.4 * xx)
+    dx = 0.5 * np.sqrt(np.maximum(1.0 - xx * xx, 0.0)) * np.exp(-0.1 * (RR - 3.0) ** 2) * (1.0 + 0.1 * rr)
+    s2 = np.sqrt(2.0)
+    shape = (len(x), len(R), len(r))
+    return np.stack([np.broadcast_to(dx / s2, shape), np.broadcast_to(dz, shape),
+                     np.broadcast_to(-dx / s2, shape)]).copy()
