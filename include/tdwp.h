@@ -94,6 +94,18 @@ typedef struct {
   const tdwp_unit* units;
   int precision;                         /* enum tdwp_precision                    */
   void* stream;                          /* hipStream_t or NULL                    */
+  /* State-to-state analysis in a product arrangement XY + Z from the packet in
+   * reactant coordinates (Sec. "Analysis of final states", the reactant-
+   * coordinate-based method, iprod = 2 of the inputprod namelist): every step,
+   * the packet of each J = 0 unit is evaluated on the line R' = prod_R_inf of the
+   * product Jacobi coordinates (r' on prod_n_r equidistant points over
+   * [prod_r_min, prod_r_max], gamma' on prod_n_gamma Gauss-Legendre nodes) and
+   * accumulated in energy like the reactant lines (Eq.
+   * Chebyshev-products-overlaps).  Matrix-core path only (even grid sizes). */
+  int prod_arrangement;                  /* 0: none (default); 1: AB + C; 2: AC + B */
+  int prod_n_r, prod_n_gamma;            /* product r' points, gamma' nodes (>= 2)  */
+  double prod_R_inf;                     /* R'_inf (Rbalinprod)                     */
+  double prod_r_min, prod_r_max;         /* first and last r' points, > 0           */
 } tdwp_config;
 
 /* Initial collision packet (Sec. 2.3.1, Eqs. initial-collision-wvp and
@@ -448,6 +460,30 @@ int tdwp_get_stat(tdwp_plan_t p, int stat, long* value);
  * Returns the number of kernel kinds (>= 0) or an error.  Advances the plan. */
 int tdwp_time_kernels(tdwp_plan_t p, long n_steps, int n_max, double* avg_us,
                       char* names, size_t names_len);
+
+/* The product grid of a plan with a product arrangement: r_prod [prod_n_r],
+ * cos_gamma_prod and weights [prod_n_gamma] (Gauss-Legendre).  Any pointer may
+ * be NULL.  Errors: EINVAL (no product arrangement). */
+int tdwp_product_grid(tdwp_plan_t p, double* r_prod, double* cos_gamma_prod, double* weights);
+
+/* Product channel functions (Eq. final-states): the lowest n_states eigenpairs of
+ * the XY diatomic Hamiltonian on the product r' grid (reduced mass of XY, the
+ * caller's asymptotic potential v_asym [prod_n_r] in hartree, the plan's radial
+ * and rotational caps), as tdwp_diatomic_states does for the reactant BC.
+ * chi [n_states][prod_n_r] DVR-normalised.  Errors: EINVAL. */
+int tdwp_product_diatomic_states(tdwp_plan_t p, const double* v_asym, int j, int n_states,
+                                 double* energies, double* chi);
+
+/* |S'_f(E)|^2 of product channels f = (elec, v, j, omega = 0) for packet (unit,
+ * slot) of a J = 0 unit (Eq. S-matrix-from-chebyshev with the normalisation of
+ * the reactant channels): K0 K'_f |Phi'_f|^2 / (mu mu' |g^(K0)|^2), Phi'_f the
+ * energy-resolved projection of the product line on the channel function
+ * (chi [n_ch][prod_n_r]) times the Legendre row of j, K'_f = sqrt(2 mu' (E -
+ * energy_f)), mu' the reduced mass of Z + XY; zero for closed channels.
+ * p_prod [n_ch][n_energy].  Errors: EINVAL (no product arrangement, J > 0 unit,
+ * bad channel), ESTATE (packet not set or a photodissociation packet). */
+int tdwp_state_to_state_products(tdwp_plan_t p, int unit, int slot, int n_ch,
+                                 const tdwp_channel* ch, const double* chi, double* p_prod);
 
 void tdwp_destroy(tdwp_plan_t p);
 const char* tdwp_strerror(int code);

@@ -8,7 +8,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libtdwp.so")
-SOURCES = ["tdwp.hip", "host_tables.cpp", "partial_waves.cpp", "spectra.cpp", "photo_packet.cpp"]
+SOURCES = ["tdwp.hip", "host_tables.cpp", "partial_waves.cpp", "spectra.cpp", "photo_packet.cpp", "products.cpp"]
 HEADERS = ["plan.h", "host_tables.h", "step_kernels.hpp"]
 
 FLAGS = [

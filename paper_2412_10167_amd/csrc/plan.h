@@ -52,6 +52,8 @@ struct PacketInfo {
   int n_slice;         // 2 * n_sv + n_w
   size_t acc_off;      // offset of this packet's accumulators [2][n_E][n_slice]
   size_t snap_off;     // offset of the elastic snapshot [2][n_E][n_w]
+  int n_p = 0;         // product-line values (n_elec * prod points; J = 0 units), after the R_inf line
+  int prod_idx = -1;   // index among the packets with a product line
   size_t wg_off;       // offset of this packet's workgroups in the norm partials
   int n_wg;
   bool set = false;
@@ -110,6 +112,20 @@ struct tdwp_plan_s {
   int* d_blk_plane = nullptr; // planes per packet, prefix sums
   int blocks_plane = 0;
   int* d_n_wg_plane = nullptr;   // norm partials per packet of the plane pass
+  // product-arrangement analysis (reactant-coordinate based, J = 0 units)
+  int prod_np = 0;                // product points per state: prod_n_r * prod_n_gamma
+  double prod_mu = 0, prod_m = 0; // reduced masses of Z + XY and of XY
+  double prod_dr = 0, prod_L = 0, prod_wall = 0;
+  std::vector<double> prod_r, prod_x, prod_w, prod_T, prod_Br, prod_P;
+  std::vector<double> prod_wr, prod_wR, prod_wL, prod_factor;   // interpolation tables
+  int prod_kr = 0, prod_kR = 0;   // row pitch of the r and R weight tables (padded to 4)
+  int prod_n_pk = 0;              // packets with a product line
+  double* d_prod_wr = nullptr;    // [P][prod_kr]  sine-DVR functions of r at the points
+  double* d_prod_wR = nullptr;    // [P][prod_kR]  ... of R
+  double* d_prod_wL = nullptr;    // [P][n_gamma]  Legendre DVR functions at cos gamma
+  double* d_prod_factor = nullptr;// [P] r'R'/(rR) sqrt(dr' w')
+  double* d_prod_Z = nullptr;     // [prod_n_pk][n_elec][n_gamma][P] partial contractions
+  void* d_prod_desc = nullptr;    // ProdDesc[prod_n_pk]
   int nrhk = 0, nRhk = 0, ngk = 0, ngr = 0;
   size_t lds_radr = 0, lds_ang = 0, lds_radR = 0;
   std::vector<double> Trs, Trd, TRs, TRd, Pc;

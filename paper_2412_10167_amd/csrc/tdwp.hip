@@ -19,6 +19,8 @@
 #include "mlp_kernels.hpp"
 #include "photo_kernels.hpp"
 #include "plane_kernels.hpp"
+#include "product_kernels.hpp"
+#include "products.h"
 #include "step_kernels.hpp"
 
 using namespace tdwp;
@@ -591,6 +593,10 @@ int layout_and_allocate(Plan* P) {
   const int n_tiles_R = (nR + P->rt_rad - 1) / P->rt_rad;
   choose_fast_path(P);
   if (!P->fast && P->cfg.precision != TDWP_FP64) return TDWP_EINVAL;
+  if (P->cfg.prod_arrangement != 0) {
+    if (!P->fast) return TDWP_EINVAL;   // the product line is recorded by the matrix-core path
+    TRY(build_product_tables(P));
+  }
   P->fast_accum = P->cfg.n_energy <= 16 * kAccMaxMT * 4 / 2;
   P->ring_len = P->fast_accum ? kRingFast : kRing;
   const int rtf = 16 * P->ntr;
@@ -608,7 +614,9 @@ int layout_and_allocate(Plan* P) {
       pk.n_values = (size_t)U.n_om * ne * ng * nR * nr;
       pk.n_sv = U.n_om * ne * ng * nR;
       pk.n_w = U.n_om * ne * ng * nr;
-      pk.n_slice = 2 * pk.n_sv + pk.n_w;
+      pk.n_p = (P->prod_np > 0 && U.J == 0 && U.n_om == 1) ? ne * P->prod_np : 0;
+      pk.prod_idx = pk.n_p > 0 ? P->prod_n_pk++ : -1;
+      pk.n_slice = 2 * pk.n_sv + pk.n_w + pk.n_p;
       pk.slice_off = soff;
       pk.acc_off = aoff;
       pk.snap_off = snoff;
@@ -669,6 +677,22 @@ int layout_and_allocate(Plan* P) {
   TRY(dev_alloc(P, (void**)&P->d_acc, P->acc_total * sizeof(double)));
   TRY(dev_alloc(P, (void**)&P->d_snap, P->snap_total * sizeof(double)));
   TRY(dev_alloc(P, (void**)&P->d_coef, P->packets.size() * 2 * nE * P->ring_len * sizeof(double)));
+  if (P->prod_n_pk > 0) {
+    TRY(alloc_copy(P, &P->d_prod_wr, P->prod_wr));
+    TRY(alloc_copy(P, &P->d_prod_wR, P->prod_wR));
+    TRY(alloc_copy(P, &P->d_prod_wL, P->prod_wL));
+    TRY(alloc_copy(P, &P->d_prod_factor, P->prod_factor));
+    const size_t zper = (size_t)ne * ng * P->prod_np;
+    TRY(dev_alloc(P, (void**)&P->d_prod_Z, (size_t)P->prod_n_pk * zper * sizeof(double)));
+    std::vector<ProdDesc> pdv;
+    for (auto& pk : P->packets)
+      if (pk.prod_idx >= 0)
+        pdv.push_back(ProdDesc{pk.off, pk.slice_off + 2 * (size_t)pk.n_sv + pk.n_w,
+                               (size_t)pk.prod_idx * zper});
+    ProdDesc* dpd = nullptr;
+    TRY(alloc_copy(P, &dpd, pdv));
+    P->d_prod_desc = dpd;
+  }
   if (P->fast) {
     {
       const int h2 = nr / 2;
@@ -857,8 +881,8 @@ void store_tile(Plan* P, int nt) {
 
 struct Timing {
   hipEvent_t ev[2];
-  double ms[7] = {0, 0, 0, 0, 0, 0, 0};
-  long calls[7] = {0, 0, 0, 0, 0, 0, 0};
+  double ms[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  long calls[8] = {0, 0, 0, 0, 0, 0, 0, 0};
 };
 
 int timed_begin(Plan* P, Timing* T) {
@@ -1043,6 +1067,24 @@ bool use_plane(const Plan* P) {
   return P->fast && P->plane_ok && P->plane_r && P->pot_mode == TDWP_POT_TABLE && !P->acf_in_pass;
 }
 
+// The product lines of u in d_u[cur] into the ring row counters[0] (J = 0 packets
+// of a plan with a product arrangement); nothing otherwise.
+int launch_product_lines(Plan* P, int cur) {
+  if (P->prod_n_pk == 0) return TDWP_OK;
+  const int np = P->prod_np;
+  const unsigned g1 = (unsigned)((size_t)P->prod_n_pk * P->ne * P->ng * ((np + kProdPts - 1) / kProdPts));
+  hipLaunchKernelGGL(k_prod_contract, dim3(g1), dim3(256), 0, P->stream, P->d_u[cur],
+                     (const ProdDesc*)P->d_prod_desc, P->ne, P->ng, P->nR, P->nr, P->d_prod_wr,
+                     P->prod_kr, P->d_prod_wR, P->prod_kR, np, P->d_prod_Z);
+  const long n2 = (long)P->prod_n_pk * P->ne * np;
+  hipLaunchKernelGGL(k_prod_finish, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, P->stream,
+                     (const ProdDesc*)P->d_prod_desc, P->prod_n_pk, P->ne, P->ng, np, P->d_prod_Z,
+                     P->d_prod_wL, P->d_prod_factor, P->d_ring, P->slice_total, P->d_counters,
+                     P->ring_len);
+  HIP_TRY(hipGetLastError());
+  return TDWP_OK;
+}
+
 // Launches the kernels of one step of the matrix-core path (no host state change):
 // u_k in d_u[cur], u_{k-1} in d_u[1 - cur]; rec: record the slices of u_k.
 template <int PR>
@@ -1098,6 +1140,11 @@ int enqueue_step(Plan* P, int cur, int first, int rec, Timing* T) {
   }
   HIP_TRY(hipGetLastError());
   TRY(timed_end(P, T, 0));
+  if (rec && P->prod_n_pk > 0) {   // before the step's last pass advances the ring row
+    TRY(timed_begin(P, T));
+    TRY(launch_product_lines(P, cur));
+    TRY(timed_end(P, T, 7));
+  }
   if constexpr (PR != kP64) {
     if (plane) {
       // T_r and T_R over whole planes, potential, recursion, damping, norm, slices
@@ -1296,6 +1343,7 @@ int record_via_radr(Plan* P) {
                      dim3(256), P->lds_radr, P->stream, P->d_u[P->cur],
                      reinterpret_cast<typename HType<PR>::T*>(P->d_h), (const E*)P->d_TrsF,
                      (const E*)P->d_TrdF, P->nrhk, P->nrhk * P->nrhk, nr, nlines, sa);
+  TRY(launch_product_lines(P, P->cur));
   hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, P->stream, P->d_counters, 1, 0);
   HIP_TRY(hipGetLastError());
   return TDWP_OK;
@@ -2221,10 +2269,10 @@ int tdwp_time_kernels(tdwp_plan_t p, long n_steps, int n_max, double* avg_us, ch
   (void)hipEventDestroy(T.ev[0]);
   (void)hipEventDestroy(T.ev[1]);
   if (st != TDWP_OK) return st;
-  static const char* kinds[7] = {"angular", "radial_R_epilogue", "slices", "accumulate", "radial_r",
-                                 "autocorrelation", "radial_rR_epilogue"};
+  static const char* kinds[8] = {"angular", "radial_R_epilogue", "slices", "accumulate", "radial_r",
+                                 "autocorrelation", "radial_rR_epilogue", "products"};
   std::string joined;
-  for (int i = 0; i < 7; ++i) {
+  for (int i = 0; i < 8; ++i) {
     if (i < n_max && avg_us) avg_us[i] = T.calls[i] ? 1000.0 * T.ms[i] / T.calls[i] : 0.0;
     if (i) joined += ";";
     joined += kinds[i];
@@ -2233,7 +2281,7 @@ int tdwp_time_kernels(tdwp_plan_t p, long n_steps, int n_max, double* avg_us, ch
     std::strncpy(names, joined.c_str(), names_len - 1);
     names[names_len - 1] = 0;
   }
-  return 7;
+  return 8;
 }
 
 int tdwp_autotune(tdwp_plan_t p, int steps, char* report, size_t report_len) {
@@ -2605,6 +2653,87 @@ int tdwp_mlp_grid(tdwp_plan_t p, double* v_out) {
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipMemcpyAsync(v_out, dv, (size_t)p->npair * plane * sizeof(double), hipMemcpyDeviceToHost, p->stream));
   HIP_TRY(hipStreamSynchronize(p->stream));
+  return TDWP_OK;
+}
+
+int tdwp_product_grid(tdwp_plan_t p, double* r_prod, double* cos_gamma_prod, double* weights) {
+  if (!p || p->prod_np == 0) return TDWP_EINVAL;
+  if (r_prod) std::copy(p->prod_r.begin(), p->prod_r.end(), r_prod);
+  if (cos_gamma_prod) std::copy(p->prod_x.begin(), p->prod_x.end(), cos_gamma_prod);
+  if (weights) std::copy(p->prod_w.begin(), p->prod_w.end(), weights);
+  return TDWP_OK;
+}
+
+int tdwp_product_diatomic_states(tdwp_plan_t p, const double* v_asym, int j, int n_states,
+                                 double* energies, double* chi) {
+  if (!p || p->prod_np == 0) return TDWP_EINVAL;
+  return product_channels(p, v_asym, j, n_states, energies, chi);
+}
+
+int tdwp_state_to_state_products(tdwp_plan_t p, int unit, int slot, int n_ch,
+                                 const tdwp_channel* ch, const double* chi, double* p_prod) {
+  if (!p || n_ch < 0 || (n_ch > 0 && (!ch || !chi || !p_prod))) return TDWP_EINVAL;
+  if (p->prod_np == 0) return TDWP_EINVAL;
+  int ip = -1;
+  for (size_t i = 0; i < p->packets.size(); ++i)
+    if (p->packets[i].unit == unit && p->packets[i].slot == slot) ip = (int)i;
+  if (ip < 0) return TDWP_EINVAL;
+  PacketInfo& P = p->packets[ip];
+  if (P.prod_idx < 0) return TDWP_EINVAL;   // no product line: a J > 0 unit
+  if (!P.set || P.photo) return TDWP_ESTATE;
+  const int npg = p->cfg.prod_n_gamma, npr = p->cfg.prod_n_r, np = p->prod_np;
+  for (int f = 0; f < n_ch; ++f)
+    if (ch[f].elec < 0 || ch[f].elec >= p->ne || ch[f].j < 0 || ch[f].j > npg - 1 || ch[f].omega != 0)
+      return TDWP_EINVAL;
+  TRY(finish_slices(p, nullptr));
+  TRY(flush_ring(p));
+  const tdwp_config& c = p->cfg;
+  const int nE = c.n_energy;
+  const size_t w = (size_t)p->ne * np;
+  const size_t col0 = 2 * (size_t)P.n_sv + P.n_w;
+  std::vector<double> A((size_t)2 * nE * w), g(p->nR);
+  HIP_TRY(hipMemcpy2DAsync(A.data(), w * sizeof(double), p->d_acc + P.acc_off + col0,
+                           (size_t)P.n_slice * sizeof(double), w * sizeof(double), (size_t)2 * nE,
+                           hipMemcpyDeviceToHost, p->stream));
+  HIP_TRY(hipMemcpyAsync(g.data(), p->d_g + (size_t)ip * p->nR, p->nR * sizeof(double),
+                         hipMemcpyDeviceToHost, p->stream));
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  const double step = (c.ecol_max - c.ecol_min) / (nE - 1);
+  std::vector<double> K0(nE), g2(nE);
+  for (int e = 0; e < nE; ++e) {
+    K0[e] = std::sqrt(2.0 * p->mu * (c.ecol_min + e * step));
+    double gr = 0.0, gi = 0.0;
+    for (int m = 0; m < p->nR; ++m) {
+      const double a = std::sqrt(p->dR) * g[m], Rm = c.R_min + m * p->dR;
+      gr += a * std::cos(K0[e] * Rm);
+      gi += a * std::sin(K0[e] * Rm);
+    }
+    g2[e] = gr * gr + gi * gi;
+  }
+  for (int f = 0; f < n_ch; ++f) {
+    // the channel's product-line weights: Legendre row of j times chi (Eq. final-states)
+    std::vector<double> wf(np);
+    for (int n = 0; n < npg; ++n)
+      for (int i = 0; i < npr; ++i)
+        wf[(size_t)n * npr + i] = p->prod_P[(size_t)ch[f].j * npg + n] * chi[(size_t)f * npr + i];
+    const size_t off = (size_t)ch[f].elec * np;
+    for (int e = 0; e < nE; ++e) {
+      double re = 0.0, im = 0.0;
+      const double* ar = A.data() + (size_t)e * w + off;
+      const double* ai = A.data() + (size_t)(nE + e) * w + off;
+      for (int q = 0; q < np; ++q) {
+        re += wf[q] * ar[q];
+        im += wf[q] * ai[q];
+      }
+      const double Ef = c.ecol_min + e * step + P.pk.E_v0j0 - ch[f].energy;
+      double prob = 0.0;
+      if (Ef > 0) {
+        const double Kf = std::sqrt(2.0 * p->prod_mu * Ef);
+        prob = K0[e] * Kf * (re * re + im * im) / (p->mu * p->prod_mu * g2[e]);
+      }
+      p_prod[(size_t)f * nE + e] = prob;
+    }
+  }
   return TDWP_OK;
 }
 

@@ -21,7 +21,8 @@ EXPORTED_SYMBOLS = (
     "tdwp_cumulative_probability", "tdwp_cross_section", "tdwp_fit_jshift_b",
     "tdwp_set_packet_values", "tdwp_autocorrelation", "tdwp_energy_content",
     "tdwp_photo_cross_section", "tdwp_apply_hamiltonian", "tdwp_lowest_state",
-    "tdwp_photo_packet",
+    "tdwp_photo_packet", "tdwp_product_grid", "tdwp_product_diatomic_states",
+    "tdwp_state_to_state_products",
 )
 OPTIONS = {"graphs": 0, "ang_tile": 1, "radial_grid": 2, "ang_kernel": 3, "fuse_r": 4,
            "ang_xcd": 5, "plane_r": 6}
@@ -56,6 +57,10 @@ class Config(ctypes.Structure):
         ("n_units", ctypes.c_int), ("units", ctypes.POINTER(Unit)),
         ("precision", ctypes.c_int),
         ("stream", ctypes.c_void_p),
+        ("prod_arrangement", ctypes.c_int),
+        ("prod_n_r", ctypes.c_int), ("prod_n_gamma", ctypes.c_int),
+        ("prod_R_inf", ctypes.c_double), ("prod_r_min", ctypes.c_double),
+        ("prod_r_max", ctypes.c_double),
     ]
 
 
@@ -140,6 +145,9 @@ def load_library():
     cl = ctypes.c_long
     lib.tdwp_set_packet_values.argtypes = [P, ci, ci, dp]
     lib.tdwp_photo_packet.argtypes = [P, ci, ci, ci, ci, ci, ci, ci, ci, dp, dp, ci]
+    lib.tdwp_product_grid.argtypes = [P, dp, dp, dp]
+    lib.tdwp_product_diatomic_states.argtypes = [P, dp, ci, ci, dp, dp]
+    lib.tdwp_state_to_state_products.argtypes = [P, ci, ci, ci, ctypes.POINTER(Channel), dp, dp]
     lib.tdwp_autocorrelation.argtypes = [P, ci, ci, cl, dp]
     lib.tdwp_apply_hamiltonian.argtypes = [P, ci, ci, dp, dp]
     lib.tdwp_lowest_state.argtypes = [P, ci, ci, dp, ci, dp, dp, dp]
@@ -211,6 +219,11 @@ class Plan:
             n_energy=spec["n_energy"], ecol_min=spec["ecol_min"], ecol_max=spec["ecol_max"],
             n_units=len(units), units=self._units, precision=PRECISIONS[precision],
             stream=stream)
+        prod = spec.get("products")
+        if prod:
+            c.prod_arrangement = {"C": 1, "B": 2}[prod["arrangement"]]
+            c.prod_n_r, c.prod_n_gamma = prod["n_r"], prod["n_gamma"]
+            c.prod_R_inf, c.prod_r_min, c.prod_r_max = prod["R_inf"], prod["r_min"], prod["r_max"]
         self._cfg = c
         h = ctypes.c_void_p()
         _check(self.lib.tdwp_plan(ctypes.byref(c), ctypes.byref(h)), "tdwp_plan")
@@ -314,6 +327,37 @@ class Plan:
         self._photo_keep = (b, d)
         _check(self.lib.tdwp_photo_packet(self.handle, unit, slot, elec, J_i, M_i, p_i, om_lo_i,
                                           b.size // pts, _ptr(b), _ptr(d), pol), "tdwp_photo_packet")
+
+    def product_grid(self):
+        pr = self.spec["products"]
+        r = np.empty(pr["n_r"])
+        x = np.empty(pr["n_gamma"])
+        w = np.empty(pr["n_gamma"])
+        _check(self.lib.tdwp_product_grid(self.handle, _ptr(r), _ptr(x), _ptr(w)), "tdwp_product_grid")
+        return r, x, w
+
+    def product_diatomic_states(self, v_asym, j, n_states):
+        n = self.spec["products"]["n_r"]
+        e = np.empty(n_states)
+        chi = np.empty((n_states, n))
+        _check(self.lib.tdwp_product_diatomic_states(self.handle, _ptr(_f64(v_asym)), j, n_states,
+                                                     _ptr(e), _ptr(chi)), "tdwp_product_diatomic_states")
+        return e, chi
+
+    def state_to_state_products(self, unit, slot, channels):
+        """|S'|^2 [n_ch][n_energy] of product channels (dicts elec, v, j, energy, chi)."""
+        nE = self.spec["n_energy"]
+        n = self.spec["products"]["n_r"]
+        n_ch = len(channels)
+        arr = (Channel * max(n_ch, 1))(*[Channel(c["elec"], c["v"], c["j"], c.get("omega", 0),
+                                                 c["energy"]) for c in channels])
+        chi = np.ascontiguousarray(np.array([c["chi"] for c in channels], dtype=np.float64)
+                                   .reshape(n_ch, n))
+        out = np.empty((n_ch, nE))
+        _check(self.lib.tdwp_state_to_state_products(self.handle, unit, slot, n_ch, arr,
+                                                     _ptr(chi), _ptr(out)),
+               "tdwp_state_to_state_products")
+        return out
 
     def apply_hamiltonian(self, u, unit=0, slot=0):
         """H u (undamped) for a vector in the layout of packet (unit, slot); no packet
