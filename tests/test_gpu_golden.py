@@ -1,0 +1,119 @@
+"""Full-length workloads against the oracle's stored probabilities.
+
+tests/golden/pe_w{workload}_u{unit}_s{slot}_k{steps}.json hold the FP64 oracle's
+reactive and reactant-channel probabilities after the workload's full step
+count (written by tests/golden/make_golden_pe.py from oracle/ alone).  Here the
+whole workload is propagated on the GPU as it is timed (the autotuner's
+variant) in the FP64 form and in the mixed forms; every stored probability is
+compared: within 1e-8 for FP64, within 1e-3 for the mixed forms.  The largest
+difference of the mixed forms from the FP64 form is printed per partial wave J
+over every packet of the batch."""
+import glob
+import importlib.util
+import json
+import os
+
+import numpy as np
+import pytest
+
+from workloads import config
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+TOL = {"fp64": 1e-8, "fp16x3": 1e-3}
+
+
+def _golden_files(wl):
+    return sorted(glob.glob(os.path.join(HERE, "golden", f"pe_w{wl}_u*_s*_k*.json")))
+
+
+def _spec_hash(spec):
+    path = os.path.join(HERE, "golden", "make_golden_pe.py")
+    mod_spec = importlib.util.spec_from_file_location("make_golden_pe", path)
+    mod = importlib.util.module_from_spec(mod_spec)
+    mod_spec.loader.exec_module(mod)
+    return mod.spec_hash(spec)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+
+
+_RESULTS = {}
+
+
+def _run(wl, precision):
+    """Propagates workload wl for its full step count in the autotuned form;
+    returns {(unit, slot): (p_inel, p_reac, channels)} for every packet and the
+    plan's spectral bounds."""
+    key = (wl, precision)
+    if key in _RESULTS:
+        return _RESULTS[key]
+    from paper_2412_10167_amd import problem
+    spec = config(wl)
+    plan, info = problem.build(spec, precision=precision, autotune=3)
+    print(f"[result] workload {wl} {precision}: variant {info['autotune'].split('chosen=')[-1]}",
+          flush=True)
+    plan.propagate(spec["steps"], norms=False)
+    out = {}
+    for pk in spec["packets"]:
+        chans = problem.channels(plan, spec, pk["unit"], min(10, spec["n_gamma"] - 1), 2)
+        p_inel, p_reac = plan.state_to_state(pk["unit"], pk["slot"], chans)
+        out[(pk["unit"], pk["slot"])] = (p_inel, p_reac, chans)
+    bounds = plan.spectral_bounds()
+    plan.close()
+    _RESULTS[key] = (out, bounds)
+    return _RESULTS[key]
+
+
+def _compare(wl, precision):
+    spec = config(wl)
+    files = _golden_files(wl)
+    assert files, f"no stored oracle probabilities for workload {wl}"
+    h = _spec_hash(spec)
+    res, bounds = _run(wl, precision)
+    worst = 0.0
+    for f in files:
+        g = json.load(open(f))
+        assert g["spec_sha16"] == h and g["steps"] == spec["steps"], f
+        lo, hi = float(g["bounds"][0]), float(g["bounds"][1])
+        assert abs(bounds[0] - lo) < 1e-12 and abs(bounds[1] - hi) < 1e-12 * abs(hi)
+        p_inel, p_reac, chans = res[(g["unit"], g["slot"])]
+        assert [(c["elec"], c["v"], c["j"], c["omega"]) for c in chans] == \
+            [(c["elec"], c["v"], c["j"], c["omega"]) for c in g["channels"]]
+        gr = np.array(g["p_reac"], float)
+        gi = np.array(g["p_inel"], float)
+        d = max(float(np.max(np.abs(p_reac - gr))), float(np.max(np.abs(p_inel - gi))))
+        print(f"[result] workload {wl} J={g['J']} j0={g['j0']} {precision}: max |P - P_oracle| "
+              f"{d:.2e} over {gr.size + gi.size} probabilities", flush=True)
+        worst = max(worst, d)
+    assert worst < TOL[precision]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp16x3"])
+def test_batched_workload_full_length_against_oracle(precision):
+    print(f"\n[case] workload 4 (21 J x 3 packets, 128x128x48), 8000 steps, {precision}, "
+          "stored oracle probabilities", flush=True)
+    _compare(4, precision)
+
+
+def test_batched_workload_mixed_vs_fp64_per_partial_wave():
+    print("\n[case] workload 4: mixed forms against the FP64 form, every packet, per J", flush=True)
+    spec = config(4)
+    ref, _ = _run(4, "fp64")
+    for precision in ("fp16x3",):
+        got, _ = _run(4, precision)
+        by_J = {}
+        for pk in spec["packets"]:
+            J = spec["units"][pk["unit"]]["J"]
+            a, b = got[(pk["unit"], pk["slot"])], ref[(pk["unit"], pk["slot"])]
+            d = max(float(np.max(np.abs(a[0] - b[0]))), float(np.max(np.abs(a[1] - b[1]))))
+            by_J[J] = max(by_J.get(J, 0.0), d)
+        print(f"[result] {precision}: max |dP| per J " +
+              " ".join(f"{J}:{v:.1e}" for J, v in sorted(by_J.items())), flush=True)
+        assert max(by_J.values()) < 1e-3
