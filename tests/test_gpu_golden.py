@@ -1,4 +1,6 @@
-"""Full-length workloads against the oracle's stored probabilities.
+"""Full-length workloads against the oracle's stored probabilities (the batched
+workload's J=0 and J=40 units for 8000 steps, the single-packet workload for
+20000 steps).
 
 tests/golden/pe_w{workload}_u{unit}_s{slot}_k{steps}.json hold the FP64 oracle's
 reactive and reactant-channel probabilities after the workload's full step
@@ -100,6 +102,13 @@ def test_batched_workload_full_length_against_oracle(precision):
     print(f"\n[case] workload 4 (21 J x 3 packets, 128x128x48), 8000 steps, {precision}, "
           "stored oracle probabilities", flush=True)
     _compare(4, precision)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp16x3"])
+def test_single_packet_workload_full_length_against_oracle(precision):
+    print(f"\n[case] workload 2 (J=0, 256x192x80), 20000 steps, {precision}, "
+          "stored oracle probabilities", flush=True)
+    _compare(2, precision)
 
 
 def test_batched_workload_mixed_vs_fp64_per_partial_wave():
