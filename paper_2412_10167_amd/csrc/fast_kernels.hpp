@@ -1116,7 +1116,9 @@ __global__ void k_to_format(const double* __restrict__ src, typename Fmt<P>::E* 
 
 // ---- energy accumulation: acc[c e][s] += sum_b coef[c e][b] ring[b][s] ----------------
 // M = 2 n_E rows (real and imaginary parts), K = buffered steps, N = slice values.
-// One workgroup per 32 slice values; wave w owns M-tiles w, w+4, ...
+// One workgroup of eight waves per 32 slice values; wave w owns M-tiles w, w+8, ...
+// (four waves per SIMD with two workgroups a CU, so one wave's coefficient loads
+// hide behind the others' products).
 // The workgroup's slab of the ring (K x 32 values, 64 KB at K = 256) is loaded
 // into LDS with every load in flight at once, so the ring's HBM latency is paid
 // once per workgroup.  The coefficients (shared by all workgroups of a packet,
@@ -1126,15 +1128,17 @@ __global__ void k_to_format(const double* __restrict__ src, typename Fmt<P>::E* 
 // long as it is the same for A and B), so its two coefficients are one 16-byte
 // load, and the next chunk's loads are issued before the current chunk's
 // products (two register buffers).
-constexpr int kAccMaxMT = 8;   // M-tiles per wave (2 n_E <= 512)
-constexpr int kAccCols = 32;   // slice values per workgroup
+constexpr int kAccThreads = 512;                  // eight waves
+constexpr int kAccWaves = kAccThreads / 64;
+constexpr int kAccMaxMT = 4;                      // M-tiles per wave (2 n_E <= 16 * 4 * 8)
+constexpr int kAccCols = 32;                      // slice values per workgroup
 struct AccDesc {
   unsigned long acc_off;    // accumulators of the packet [2 n_E][n_slice]
   unsigned long slice_off;  // the packet's slice values in a ring row
   int n_slice;
 };
 
-__global__ __launch_bounds__(256, 2) void k_accum_mfma(double* __restrict__ acc_all,
+__global__ __launch_bounds__(kAccThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_accum_mfma(double* __restrict__ acc_all,
                                                        const double* __restrict__ coef_all, int ldc,
                                                        const double* __restrict__ ring_all,
                                                        size_t ring_stride,
@@ -1161,19 +1165,20 @@ __global__ __launch_bounds__(256, 2) void k_accum_mfma(double* __restrict__ acc_
     const int s = s0 + col;
     const bool sok = s < n_slice;
     const int sc = sok ? s : n_slice - 1;   // clamped, in-range address
-    const int r0 = threadIdx.x / kAccCols;  // 8 rows per pass of the 256 threads
-    constexpr int kBatch = 32;              // rows 8 * kBatch = 256 per thread batch
-    for (int rb = 0; rb < 8 * nch; rb += 8 * kBatch) {
+    constexpr int kRows = kAccThreads / kAccCols;   // rows per pass of the workgroup
+    const int r0 = threadIdx.x / kAccCols;
+    constexpr int kBatch = 16;                       // rows kRows * kBatch = 256 per thread batch
+    for (int rb = 0; rb < 8 * nch; rb += kRows * kBatch) {
       double x[kBatch];
 #pragma unroll
       for (int q = 0; q < kBatch; ++q) {
-        const int k = rb + r0 + 8 * q;
+        const int k = rb + r0 + kRows * q;
         const int kc = k < count ? k : count - 1;
         x[q] = ring[(size_t)kc * ring_stride + sc];
       }
 #pragma unroll
       for (int q = 0; q < kBatch; ++q) {
-        const int k = rb + r0 + 8 * q;
+        const int k = rb + r0 + kRows * q;
         if (k < 8 * nch) slab[k * kAccCols + col] = (k < count && sok) ? x[q] : 0.0;
       }
     }
@@ -1188,7 +1193,7 @@ __global__ __launch_bounds__(256, 2) void k_accum_mfma(double* __restrict__ acc_
     const int kb = 8 * ch + kq;   // even; kb + 1 < 8 * nch <= ldc
 #pragma unroll
     for (int a = 0; a < kAccMaxMT; ++a) {
-      const int mt = w + 4 * a;
+      const int mt = w + kAccWaves * a;
       if (mt >= MT) break;
       int r = mt * 16 + (l & 15);
       const bool rok = r < rows;
@@ -1205,7 +1210,7 @@ __global__ __launch_bounds__(256, 2) void k_accum_mfma(double* __restrict__ acc_
       const double b1 = slab[k * kAccCols + 16 + (l & 15)];
 #pragma unroll
       for (int a = 0; a < kAccMaxMT; ++a) {
-        const int mt = w + 4 * a;
+        const int mt = w + kAccWaves * a;
         if (mt >= MT) break;
         M::mma(c[a][0], A[a][cc], b0);
         M::mma(c[a][1], A[a][cc], b1);
@@ -1221,7 +1226,7 @@ __global__ __launch_bounds__(256, 2) void k_accum_mfma(double* __restrict__ acc_
   }
 #pragma unroll
   for (int a = 0; a < kAccMaxMT; ++a) {
-    const int mt = w + 4 * a;
+    const int mt = w + kAccWaves * a;
     if (mt >= MT) break;
 #pragma unroll
     for (int nt = 0; nt < 2; ++nt) {

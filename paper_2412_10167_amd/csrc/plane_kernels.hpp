@@ -24,6 +24,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "fast_kernels.hpp"
 #include "mfma.hpp"
 
@@ -32,11 +34,15 @@ namespace tdwp {
 constexpr int kPlaneThreads = 512;   // eight waves per plane
 constexpr int kPlaneMTW = 4;         // 16-row tiles (R) per wave work item
 constexpr int kPlaneNTW = 2;         // 16-column tiles (r) per wave work item
-constexpr int kPlaneRowsPerBatch = 8;   // plane rows whose loads a wave issues together
+constexpr int kPlaneRowsPerBatch = 4;   // plane rows whose loads a wave issues together
 constexpr int kPlaneMaxCols = 4;        // r values per lane and row: n_r <= 256
+constexpr int kPlaneEpiTiles = 2;       // row tiles whose epilogue operands are loaded together
 
 __host__ __device__ constexpr int plane_pad(int n, int ks) { return round_up(round_up(n, 16), ks); }
 __host__ __device__ constexpr int plane_ld(int cols) { return cols + 2; }   // floats; rows 8 apart 16 banks apart
+__host__ __device__ constexpr size_t plane_tile_bytes(int rows, int cols) {
+  return (size_t)rows * plane_ld(cols) * sizeof(float);
+}
 
 struct PlaneArgs {
   const double* uk_all;
@@ -70,6 +76,12 @@ struct PlaneArgs {
   int ring_len;
 };
 
+// Bytes of the FP64 rows staged ahead of the tile: the damping factors (r, then
+// R) and the flux rows a and d over r, padded to 16 bytes.
+__host__ __device__ constexpr int plane_aux_bytes(int nr, int nR) {
+  return (int)(((((nr + nR + 1) & ~1) + 2 * nr) * sizeof(double) + 15) / 16 * 16);
+}
+
 template <int P>
 __global__ __launch_bounds__(kPlaneThreads) __attribute__((amdgpu_waves_per_eu(4)))
 void k_plane_epi(PlaneArgs A) {
@@ -77,9 +89,12 @@ void k_plane_epi(PlaneArgs A) {
   using F = Fmt<P>;
   using E = typename F::E;
   extern __shared__ __align__(16) double lds[];
-  float* __restrict__ X = reinterpret_cast<float*>(lds);
-  __shared__ double red[kPlaneThreads / 64];
   const int nR = A.nR, nr = A.nr, ng = A.ng;
+  double* __restrict__ Ds = lds;                // damping: r factors, then R factors
+  double* __restrict__ Fa = lds + ((nr + nR + 1) & ~1);   // flux rows over r (value, derivative)
+  double* __restrict__ Fd = Fa + nr;
+  float* __restrict__ X = reinterpret_cast<float*>(reinterpret_cast<char*>(lds) + plane_aux_bytes(nr, nR));
+  __shared__ double red[kPlaneThreads / 64];
   const int rows_x = plane_pad(nR, M::KS), cols_x = plane_pad(nr, M::KS);
   const int ldx = plane_ld(cols_x);
   const int l = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -90,6 +105,11 @@ void k_plane_epi(PlaneArgs A) {
   const int crow = A.record ? A.counters[0] : -1;
   const bool rec_ok = crow >= 0 && crow < A.ring_len;
   double* ring_row = rec_ok ? A.ring_base + (size_t)crow * A.ring_stride : nullptr;
+  for (int q = threadIdx.x; q < nr + nR; q += kPlaneThreads) Ds[q] = A.Dsep[q];
+  for (int q = threadIdx.x; q < nr; q += kPlaneThreads) {
+    Fa[q] = rec_ok ? A.arow[q] : 0.0;
+    Fd[q] = rec_ok ? A.drow[q] : 0.0;
+  }
   // zero padding of the tile (rows >= n_R, columns >= n_r): never overwritten
   for (int q = threadIdx.x; q < rows_x * ldx; q += kPlaneThreads) {
     const int row = q / ldx, col = q - row * ldx;
@@ -98,18 +118,13 @@ void k_plane_epi(PlaneArgs A) {
   // per-lane column pairs of a row (c = 2 l + 128 j, n_r even) and their flux-row
   // entries
   constexpr int kPairs = kPlaneMaxCols / 2;
+  constexpr int RB = kPlaneRowsPerBatch;
+  static_assert(RB == 1 || RB == 2 || RB == 4 || RB == 8, "rows per batch");
   const int ppl = (nr + 127) >> 7;
-  double ar[kPlaneMaxCols], dr[kPlaneMaxCols];
-#pragma unroll
-  for (int j = 0; j < kPlaneMaxCols; ++j) {
-    const int c = 2 * l + 128 * (j >> 1) + (j & 1);
-    const bool ok = (j >> 1) < ppl && c < nr;
-    ar[j] = (rec_ok && ok) ? A.arow[c] : 0.0;
-    dr[j] = (rec_ok && ok) ? A.drow[c] : 0.0;
-  }
   const size_t plane = (size_t)nR * nr;
   const int MT = (nR + 15) >> 4, NT = (nr + 15) >> 4;
-  const int MG = (MT + kPlaneMTW - 1) / kPlaneMTW, NG = (NT + kPlaneNTW - 1) / kPlaneNTW;
+  const int NG = (NT + kPlaneNTW - 1) / kPlaneNTW;
+  const int MG = (MT + kPlaneMTW - 1) / kPlaneMTW;
   const int nblk = A.blk_start[A.n_pk];
   double nsum = 0.0;
   int local = 0;
@@ -132,11 +147,11 @@ void k_plane_epi(PlaneArgs A) {
     }
     typedef double v2d __attribute__((ext_vector_type(2)));
     typedef float v2f __attribute__((ext_vector_type(2)));
-    for (int m0 = w; m0 < nR; m0 += nw * kPlaneRowsPerBatch) {
+    for (int m0 = w; m0 < nR; m0 += nw * RB) {
       // 16-byte loads of column pairs (n_r even; rows start at even offsets)
-      v2d v[kPlaneRowsPerBatch][kPairs];
+      v2d v[RB][kPairs];
 #pragma unroll
-      for (int b = 0; b < kPlaneRowsPerBatch; ++b) {
+      for (int b = 0; b < RB; ++b) {
         const int m = m0 + nw * b;
         const int mc = m < nR ? m : nR - 1;
 #pragma unroll
@@ -146,40 +161,69 @@ void k_plane_epi(PlaneArgs A) {
                               : v2d{0.0, 0.0};
         }
       }
+      // t[2b] = this lane's part of a . u on row b, t[2b + 1] the part of d . u
+      double t[2 * RB];
 #pragma unroll
-      for (int b = 0; b < kPlaneRowsPerBatch; ++b) {
+      for (int b = 0; b < RB; ++b) {
         const int m = m0 + nw * b;
-        if (m >= nR) break;
         double sv = 0.0, sd = 0.0;
 #pragma unroll
         for (int j = 0; j < kPairs; ++j) {
           const int c = 2 * l + 128 * j;
-          if (j < ppl && c < nr) {
+          if (j < ppl && c < nr && m < nR) {
             const v2d x = v[b][j];
+            const v2d fa = *reinterpret_cast<const v2d*>(Fa + c);
+            const v2d fd = *reinterpret_cast<const v2d*>(Fd + c);
             *reinterpret_cast<v2f*>(X + m * ldx + c) = v2f{(float)x[0], (float)x[1]};
-            sv += ar[2 * j] * x[0] + ar[2 * j + 1] * x[1];
-            sd += dr[2 * j] * x[0] + dr[2 * j + 1] * x[1];
+            sv += fa[0] * x[0] + fa[1] * x[1];
+            sd += fd[0] * x[0] + fd[1] * x[1];
             if (rec_ok && m == A.m_inf)
               *reinterpret_cast<v2d*>(ring_row + soff + 2 * nsv + (size_t)local * nr + c) =
                   v2d{x[0] * A.inv_sqrt_dR, x[1] * A.inv_sqrt_dR};
           }
         }
-        if (rec_ok) {
-          for (int off = 32; off > 0; off >>= 1) {
-            sv += __shfl_down(sv, off, 64);
-            sd += __shfl_down(sd, off, 64);
-          }
-          if (l == 0) {
-            ring_row[soff + lidx0 + m] = sv;
-            ring_row[soff + nsv + lidx0 + m] = sd;
+        t[2 * b] = sv;
+        t[2 * b + 1] = sd;
+      }
+      if (rec_ok) {
+        // All 2 RB lane sums at once: each exchange over lane bit o halves the
+        // quantities a lane holds (it keeps the half its bit selects and adds the
+        // partner's copy of it), so after the exchanges over bits 5, 4, ... lane l
+        // holds quantity (l >> kLo) & (2 RB - 1) summed over those bits; the low
+        // bits finish the sum.
+        constexpr int kSteps = RB == 8 ? 4 : RB == 4 ? 3 : RB == 2 ? 2 : 1;
+        constexpr int kLo = 6 - kSteps;
+#pragma unroll
+        for (int st = 0; st < kSteps; ++st) {
+          const int o = 32 >> st, half = RB >> st;   // quantities per lane: 2 * half -> half
+          const bool up = (l & o) != 0;
+#pragma unroll
+          for (int q = 0; q < half; ++q) {
+            const double keep = up ? t[q + half] : t[q];
+            const double send = up ? t[q] : t[q + half];
+            t[q] = keep + __shfl_xor(send, o, 64);
           }
         }
+        double s = t[0];
+#pragma unroll
+        for (int o = (1 << kLo) >> 1; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+        const int q = (l >> kLo) & (2 * RB - 1), b = q >> 1;
+        const int m = m0 + nw * b;
+        if ((l & ((1 << kLo) - 1)) == 0 && m < nR)
+          ring_row[soff + ((q & 1) ? nsv : 0) + lidx0 + m] = s;
       }
     }
     __syncthreads();
     // ---- contractions and epilogue, one work item of MTW x NTW tiles at a time ---
+    // Tiles past the plane's last one (ragged sizes) are computed on the last
+    // tile's data and not stored.
     for (int g = w; g < MG * NG; g += nw) {
       const int mg = g / NG, ngi = g % NG;
+      int mtc[kPlaneMTW], ntc[kPlaneNTW];
+#pragma unroll
+      for (int a = 0; a < kPlaneMTW; ++a) mtc[a] = min(mg * kPlaneMTW + a, MT - 1);
+#pragma unroll
+      for (int b = 0; b < kPlaneNTW; ++b) ntc[b] = min(ngi * kPlaneNTW + b, NT - 1);
       typename M::acc_t acc[kPlaneMTW][kPlaneNTW];
 #pragma unroll
       for (int a = 0; a < kPlaneMTW; ++a)
@@ -188,73 +232,88 @@ void k_plane_epi(PlaneArgs A) {
       // T_R u: A = operator rows (global), B = plane columns (LDS)
       const E* TRf = reinterpret_cast<const E*>(A.TRf);
       for (int k0 = 0; k0 < A.kR; k0 += M::KS) {
-        typename M::frag_t fb[kPlaneNTW];
+        typename M::frag_t fa[kPlaneMTW], fb[kPlaneNTW];
+#pragma unroll
+        for (int a = 0; a < kPlaneMTW; ++a)
+          fa[a] = F::frag(TRf + (size_t)mtc[a] * 16 * A.kR, A.kR, A.psR, l, k0);
 #pragma unroll
         for (int b = 0; b < kPlaneNTW; ++b) {
-          const int nt = ngi * kPlaneNTW + b;   // past the last tile: loaded, not used
-          const int c0 = (nt < NT ? nt : NT - 1) * 16;
+          const int c0 = ntc[b] * 16;
           fb[b] = M::load_b([&](int k, int c) { return X[k * ldx + c0 + c]; }, k0, l);
         }
 #pragma unroll
-        for (int a = 0; a < kPlaneMTW; ++a) {
-          const int mt = mg * kPlaneMTW + a;
-          if (mt >= MT) break;
-          const typename M::frag_t fa = F::frag(TRf + (size_t)mt * 16 * A.kR, A.kR, A.psR, l, k0);
+        for (int a = 0; a < kPlaneMTW; ++a)
 #pragma unroll
-          for (int b = 0; b < kPlaneNTW; ++b)
-            if ((ngi * kPlaneNTW + b) < NT) M::mma(acc[a][b], fa, fb[b]);
-        }
+          for (int b = 0; b < kPlaneNTW; ++b) M::mma(acc[a][b], fa[a], fb[b]);
       }
       // u T_r: A = plane rows (LDS), B = operator rows (global; T_r is symmetric)
       const E* Trf = reinterpret_cast<const E*>(A.Trf);
       for (int k0 = 0; k0 < A.kr; k0 += M::KS) {
-        typename M::frag_t fb[kPlaneNTW];
+        typename M::frag_t fa[kPlaneMTW], fb[kPlaneNTW];
 #pragma unroll
-        for (int b = 0; b < kPlaneNTW; ++b) {
-          const int nt = ngi * kPlaneNTW + b;
-          fb[b] = F::frag(Trf + (size_t)(nt < NT ? nt : NT - 1) * 16 * A.kr, A.kr, A.psr, l, k0);
-        }
+        for (int b = 0; b < kPlaneNTW; ++b)
+          fb[b] = F::frag(Trf + (size_t)ntc[b] * 16 * A.kr, A.kr, A.psr, l, k0);
 #pragma unroll
         for (int a = 0; a < kPlaneMTW; ++a) {
-          const int mt = mg * kPlaneMTW + a;
-          if (mt >= MT) break;
-          const int r0 = mt * 16;
-          const typename M::frag_t fa =
-              M::load_a([&](int row, int k) { return X[(r0 + row) * ldx + k]; }, k0, l);
-#pragma unroll
-          for (int b = 0; b < kPlaneNTW; ++b)
-            if ((ngi * kPlaneNTW + b) < NT) M::mma(acc[a][b], fa, fb[b]);
+          const int r0 = mtc[a] * 16;
+          fa[a] = M::load_a([&](int row, int k) { return X[(r0 + row) * ldx + k]; }, k0, l);
         }
-      }
-      // epilogue of this work item's outputs
 #pragma unroll
-      for (int a = 0; a < kPlaneMTW; ++a) {
-        const int mt = mg * kPlaneMTW + a;
-        if (mt >= MT) break;
+        for (int a = 0; a < kPlaneMTW; ++a)
+#pragma unroll
+          for (int b = 0; b < kPlaneNTW; ++b) M::mma(acc[a][b], fa[a], fb[b]);
+      }
+      // epilogue of this work item's outputs: the operands of a group of tiles are
+      // loaded together (clamped to the plane), then the outputs are formed and
+      // stored where they lie inside it
+      auto epilogue = [&](auto first_tag) {
+        constexpr bool FIRST = decltype(first_tag)::value;
+        constexpr int GA = kPlaneEpiTiles;   // row tiles per load group
 #pragma unroll
         for (int b = 0; b < kPlaneNTW; ++b) {
           const int nt = ngi * kPlaneNTW + b;
           const int i = nt * 16 + (l & 15);
-          if (nt >= NT || i >= nr) continue;
-          const double dr_i = A.Dsep[i];
+          const int ic = i < nr ? i : nr - 1;
+          const bool col_ok = nt < NT && i < nr;
+          const double dr_i = Ds[ic];
 #pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int mm = mt * 16 + M::row(l, v);
-            if (mm >= nR) continue;
-            const size_t idx = poff + (size_t)mm * nr + i;
-            const double ukv = (double)X[mm * ldx + i];
-            const double hv = (double)A.h_all[idx];
-            const double vv = (double)A.V[(size_t)n * plane + (size_t)mm * nr + i];
-            const double pv = A.first ? 0.0 : A.uprev_all[idx];
-            const double sacc = (double)acc[a][b][v] * M::kUnscale + hv + vv * ukv;
-            const double wv = (sacc - A.E0 * ukv) * A.inv_dE;
-            const double dmp = A.Dsep[nr + mm] * dr_i;
-            const double un = A.first ? dmp * wv : dmp * (2.0 * wv - dmp * pv);
-            A.uprev_all[idx] = un;
-            nsum += un * un;
+          for (int a0 = 0; a0 < kPlaneMTW; a0 += GA) {
+            float hv[GA][4], vv[GA][4];
+            double pv[GA][4];
+#pragma unroll
+            for (int a = 0; a < GA; ++a)
+#pragma unroll
+              for (int v = 0; v < 4; ++v) {
+                const int mm = (mg * kPlaneMTW + a0 + a) * 16 + M::row(l, v);
+                const int mc = mm < nR ? mm : nR - 1;
+                const size_t idx = poff + (size_t)mc * nr + ic;
+                hv[a][v] = A.h_all[idx];
+                vv[a][v] = A.V[(size_t)n * plane + (size_t)mc * nr + ic];
+                pv[a][v] = FIRST ? 0.0 : A.uprev_all[idx];
+              }
+#pragma unroll
+            for (int a = 0; a < GA; ++a)
+#pragma unroll
+              for (int v = 0; v < 4; ++v) {
+                const int mm = (mg * kPlaneMTW + a0 + a) * 16 + M::row(l, v);
+                if (!col_ok || mm >= nR) continue;
+                const size_t idx = poff + (size_t)mm * nr + i;
+                const double ukv = (double)X[mm * ldx + i];
+                const double sacc = (double)acc[a0 + a][b][v] * M::kUnscale + (double)hv[a][v] +
+                                    (double)vv[a][v] * ukv;
+                const double wv = (sacc - A.E0 * ukv) * A.inv_dE;
+                const double dmp = Ds[nr + mm] * dr_i;
+                const double un = FIRST ? dmp * wv : dmp * (2.0 * wv - dmp * pv[a][v]);
+                A.uprev_all[idx] = un;
+                nsum += un * un;
+              }
           }
         }
-      }
+      };
+      if (A.first)
+        epilogue(std::true_type{});
+      else
+        epilogue(std::false_type{});
     }
     // ---- norm partial of this plane ------------------------------------------------
     for (int off = 32; off > 0; off >>= 1) nsum += __shfl_down(nsum, off, 64);

@@ -538,7 +538,7 @@ int plane_tables(Plan* P) {
   TRY(upload_formatted<PR>(P, &P->d_TRfullF, padded(P->TR, nR, P->plane_kR)));
   TRY(upload_formatted<PR>(P, &P->d_TrfullF, padded(P->Tr, nr, P->plane_kr)));
   const int rows_x = plane_pad(nR, M::KS), cols_x = plane_pad(nr, M::KS);
-  P->lds_plane = (size_t)rows_x * plane_ld(cols_x) * sizeof(float);
+  P->lds_plane = (size_t)plane_aux_bytes(nr, nR) + plane_tile_bytes(rows_x, cols_x);
   hipFuncAttributes fa{};
   size_t stat = 0;
   if (hipFuncGetAttributes(&fa, (const void*)k_plane_epi<PR>) == hipSuccess) stat = fa.sharedSizeBytes;
@@ -597,7 +597,7 @@ int layout_and_allocate(Plan* P) {
     if (!P->fast) return TDWP_EINVAL;   // the product line is recorded by the matrix-core path
     TRY(build_product_tables(P));
   }
-  P->fast_accum = P->cfg.n_energy <= 16 * kAccMaxMT * 4 / 2;
+  P->fast_accum = P->cfg.n_energy <= 16 * kAccMaxMT * kAccWaves / 2;
   P->ring_len = P->fast_accum ? kRingFast : kRing;
   const int rtf = 16 * P->ntr;
   // packets
@@ -932,7 +932,7 @@ int flush_ring(Plan* P) {
                      P->ring_count);
   if (P->fast_accum) {
     const size_t slab = (size_t)8 * ((P->ring_count + 7) / 8) * kAccCols * sizeof(double);
-    hipLaunchKernelGGL(k_accum_mfma, dim3(P->blocks_acc), dim3(256), slab, P->stream, P->d_acc,
+    hipLaunchKernelGGL(k_accum_mfma, dim3(P->blocks_acc), dim3(kAccThreads), slab, P->stream, P->d_acc,
                        P->d_coef, P->ring_len, P->d_ring, P->slice_total,
                        (const AccDesc*)P->d_accdesc, P->d_blk_acc, np, 2 * nE, P->ring_count);
   } else {
