@@ -110,11 +110,12 @@ void k_plane_epi(PlaneArgs A) {
     Fa[q] = rec_ok ? A.arow[q] : 0.0;
     Fd[q] = rec_ok ? A.drow[q] : 0.0;
   }
-  // zero padding of the tile (rows >= n_R, columns >= n_r): never overwritten
-  for (int q = threadIdx.x; q < rows_x * ldx; q += kPlaneThreads) {
-    const int row = q / ldx, col = q - row * ldx;
-    if (row >= nR || col >= nr) X[q] = 0.0f;
-  }
+  // zero padding of the tile read by the contractions (rows n_R .. rows_x - 1,
+  // columns n_r .. cols_x - 1): never overwritten; none for 16-multiple planes
+  for (int q = threadIdx.x; q < (rows_x - nR) * cols_x; q += kPlaneThreads)
+    X[(nR + q / cols_x) * ldx + q % cols_x] = 0.0f;
+  for (int q = threadIdx.x; q < nR * (cols_x - nr); q += kPlaneThreads)
+    X[(q / (cols_x - nr)) * ldx + nr + q % (cols_x - nr)] = 0.0f;
   // per-lane column pairs of a row (c = 2 l + 128 j, n_r even) and their flux-row
   // entries
   constexpr int kPairs = kPlaneMaxCols / 2;
