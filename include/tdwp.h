@@ -424,8 +424,11 @@ enum tdwp_option {
   TDWP_OPT_RADIAL_GRID = 2, /* workgroups of the two radial passes, each looping over its
                                blocks; 0 (default): one workgroup per block                 */
   TDWP_OPT_ANG_KERNEL = 3,  /* angular kernel: 0 (default) automatic, 1 helicity mixing
-                               through LDS, 2 helicity mixing in registers; a kernel that
-                               does not fit the plan's shapes is refused with TDWP_EINVAL  */
+                               through LDS, 2 helicity mixing in registers, 3 every wave
+                               holding its own columns in registers (split forms,
+                               n_gamma <= 64, at most 8 helicities; used when the r pass
+                               is not fused, else kernel 2 runs); a kernel that does not
+                               fit the plan's shapes is refused with TDWP_EINVAL          */
   TDWP_OPT_FUSE_R = 4,      /* 1 (default): the angular pass and the r pass in one launch
                                (T_r u into a buffer of its own); 0: two launches, the r
                                pass adding T_r u to the angular terms                      */
@@ -440,8 +443,8 @@ enum tdwp_stat {
   TDWP_STAT_GRAPH_STEPS = 0,        /* steps taken so far by graph replay      */
   TDWP_STAT_ANG_TILE = 1,           /* current angular-kernel tile (0: general kernels) */
   TDWP_STAT_MATRIX_CORE_PATH = 2,   /* 1 when the matrix-core kernels are in use */
-  TDWP_STAT_ANG_KERNEL = 3,         /* angular kernel in use: 1 LDS mixing, 2 register mixing
-                                       (0: general kernels) */
+  TDWP_STAT_ANG_KERNEL = 3,         /* angular kernel in use: 1 LDS mixing, 2 register mixing,
+                                       3 columns held per wave (0: general kernels) */
   TDWP_STAT_FUSE_R = 4,             /* 1 when the angular and r passes share a launch */
   TDWP_STAT_RING_LEN = 5,           /* steps of slices buffered between two energy
                                        accumulations (Eq. wvf-chebyshev, blocked)     */

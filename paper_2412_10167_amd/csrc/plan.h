@@ -102,6 +102,12 @@ struct tdwp_plan_s {
   int ang_pref = 0;          // angular kernel: 0 automatic, 1 k_ang, 2 k_angr
   bool fuse_r = true;        // angular and r passes in one launch (T_r u into d_h2)
   bool ang_xcd = false;      // angular blocks in XCD order
+  // angular pass with every wave holding its own columns (k_angw, split forms)
+  bool angw_ok = false;      // the shapes and the form allow it
+  bool ang_wave = false;     // in use when the r pass is not fused (option / autotuner)
+  int* d_blk_angw = nullptr; // workgroups per packet, prefix sums
+  int blocks_angw = 0;
+  size_t lds_angw = 0;       // the largest unit's tridiagonal blocks (FP32)
   // both radial terms in one pass over whole (R, r) planes (one state, mixed forms)
   bool plane_ok = false;     // the plane fits the device's LDS and the form allows it
   bool plane_r = false;      // in use (option / autotuner)
@@ -136,6 +142,8 @@ struct tdwp_plan_s {
   double* d_Pc = nullptr;
   std::vector<double> PcT;
   std::vector<double> Pf;    // [omega][parity][j < ngr][n' < ngk], rows of one parity of j + omega
+  std::vector<double> Pb;    // [omega][parity][n < nbr][slot < kbk], back rows in k_angw slot order
+  int nbr = 0, kbk = 0;
   // operator tables in the compute format of the plan's precision
   void* d_TrsF = nullptr;
   void* d_TrdF = nullptr;
@@ -144,6 +152,7 @@ struct tdwp_plan_s {
   void* d_PcF = nullptr;
   void* d_PcTF = nullptr;
   void* d_PfF = nullptr;
+  void* d_PbF = nullptr;
   // propagation state
   long k = 0;
   int cur = 0;               // u_k lives in d_u[cur], u_{k-1} in d_u[1 - cur]

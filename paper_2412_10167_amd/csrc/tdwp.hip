@@ -19,6 +19,7 @@
 #include "mlp_kernels.hpp"
 #include "photo_kernels.hpp"
 #include "plane_kernels.hpp"
+#include "angw_kernels.hpp"
 #include "product_kernels.hpp"
 #include "products.h"
 #include "step_kernels.hpp"
@@ -299,6 +300,23 @@ int build_tables(Plan* P) {
           P->Pf[(((size_t)om * 2 + c) * ngr + j) * ngk + n] =
               P->Ptab[((size_t)om * P->ng + j) * P->ng + n];
       }
+    // back rows of k_angw: [omega][parity][n][slot], the row j of a slot given by
+    // the accumulator layout (zero for j of the other parity, j < omega, j >= n_gamma)
+    if (P->ng <= 64) {
+      P->nbr = round_up(ngh, 16);
+      P->kbk = round_up(P->ng, 32);
+      const int nbr = P->nbr, kbk = P->kbk;
+      P->Pb.assign((size_t)(P->max_om + 1) * 2 * nbr * kbk, 0.0);
+      for (int om = 0; om <= P->max_om; ++om)
+        for (int c = 0; c < 2; ++c)
+          for (int n = 0; n < ngh; ++n)
+            for (int q = 0; q < kbk; ++q) {
+              const int j = angw_slot_j(q / 32, (q % 32) / 8, q % 8);
+              if (j < om || j >= P->ng || ((j + om) & 1) != c) continue;
+              P->Pb[(((size_t)om * 2 + c) * nbr + n) * kbk + q] =
+                  P->Ptab[((size_t)om * P->ng + j) * P->ng + n];
+            }
+    }
   }
   return TDWP_OK;
 }
@@ -404,6 +422,7 @@ int upload_tables(Plan* P) {
   TRY(upload_formatted<PR>(P, &P->d_PcF, P->Pc));
   TRY(upload_formatted<PR>(P, &P->d_PcTF, P->PcT));
   TRY(upload_formatted<PR>(P, &P->d_PfF, P->Pf));
+  if (!P->Pb.empty()) TRY(upload_formatted<PR>(P, &P->d_PbF, P->Pb));
   return TDWP_OK;
 }
 
@@ -439,6 +458,21 @@ void with_angr(int nt, int mom, int tpw, Tag tag, F&& f) {
   if (nt == 4) by_nt(std::integral_constant<int, 4>{});
   else if (nt == 2) by_nt(std::integral_constant<int, 2>{});
   else by_nt(std::integral_constant<int, 1>{});
+}
+
+// Calls f with the per-wave angular kernel for helicity width mom (1 or 8) and
+// mtj 16-row j tiles (1 .. 4).
+template <int PR, class F>
+void with_angw(int mom, int mtj, F&& f) {
+  auto by = [&](auto mc) {
+    constexpr int MOM = decltype(mc)::value;
+    if (mtj == 1) f(k_angw<PR, MOM, 1>);
+    else if (mtj == 2) f(k_angw<PR, MOM, 2>);
+    else if (mtj == 3) f(k_angw<PR, MOM, 3>);
+    else f(k_angw<PR, MOM, 4>);
+  };
+  if (mom == 1) by(std::integral_constant<int, 1>{});
+  else by(std::integral_constant<int, 8>{});
 }
 
 // The same for the LDS-mixing angular kernel (one helicity or up to kMaxOmega).
@@ -770,7 +804,9 @@ int layout_and_allocate(Plan* P) {
   HIP_TRY(hipGetLastError());
   if (P->fast) {
     std::vector<PkDesc> pd;
-    std::vector<int> ba(1, 0), br(1, 0);
+    std::vector<int> ba(1, 0), br(1, 0), bw(1, 0);
+    const int nrt_w = (nr + 15) / 16;
+    constexpr int kWaves = kAngwThreads / 64;
     const int nrt_a = (nr + 16 * P->nta - 1) / (16 * P->nta);
     const int nrt_r = (nr + 16 * P->ntr - 1) / (16 * P->ntr);
     P->lds_ang_max = P->lds_ang;
@@ -781,6 +817,8 @@ int layout_and_allocate(Plan* P) {
                           U.d_mixU, U.d_mixell, U.d_mixL, U.d_mixUf, U.d_mixellf, U.d_mixLf,
                           (int)U.mix_L.size()});
       ba.push_back(ba.back() + nrt_a * nR * ne);
+      bw.push_back(bw.back() + (nrt_w * nR * ne + kWaves - 1) / kWaves);
+      P->lds_angw = std::max(P->lds_angw, U.mix_L.size() * sizeof(float));
       br.push_back(br.back() + nrt_r * U.n_om * ng);
     }
     P->blocks_ang = ba.back();
@@ -789,6 +827,15 @@ int layout_and_allocate(Plan* P) {
     TRY(alloc_copy(P, &dpd, pd));
     P->d_pkdesc = dpd;
     TRY(alloc_copy(P, &P->d_blk_ang, ba));
+    P->blocks_angw = bw.back();
+    TRY(alloc_copy(P, &P->d_blk_angw, bw));
+    {
+      int max_om = 0;
+      for (auto& U : P->units) max_om = std::max(max_om, U.n_om);
+      const int prec = P->cfg.precision;
+      P->angw_ok = (prec == TDWP_FP16X3 || prec == TDWP_BF16X3) && !P->Pb.empty() &&
+                   mix_width(max_om) <= 8 && P->lds_angw <= kLdsMax;
+    }
     TRY(alloc_copy(P, &P->d_blk_radR, br));
   }
   return TDWP_OK;
@@ -1067,6 +1114,12 @@ bool use_plane(const Plan* P) {
   return P->fast && P->plane_ok && P->plane_r && P->pot_mode == TDWP_POT_TABLE && !P->acf_in_pass;
 }
 
+// Whether the angular pass runs the per-wave kernel (chosen, feasible, and its
+// launch not shared with the r pass).
+bool use_angw(const Plan* P) {
+  return P->fast && P->angw_ok && P->ang_wave && !(P->fuse_r && !use_plane(P));
+}
+
 // The product lines of u in d_u[cur] into the ring row counters[0] (J = 0 packets
 // of a plan with a product arrangement); nothing otherwise.
 int launch_product_lines(Plan* P, int cur) {
@@ -1126,7 +1179,21 @@ int enqueue_step(Plan* P, int cur, int first, int rec, Timing* T) {
     };
     int max_om = 0;
     for (auto& U : P->units) max_om = std::max(max_om, U.n_om);
-    if (P->ang_regs) {
+    bool wave = false;
+    if constexpr (PR == kPF16 || PR == kPBF) {
+      if (use_angw(P)) {
+        wave = true;
+        AngwArgs wa{uk, reinterpret_cast<float*>(h), pkd, P->d_blk_angw, np, ne, ng, nR, nr,
+                    P->d_PfF, P->ngr, P->ngk, (int)P->Pf.size(), P->d_PbF, P->nbr, P->kbk,
+                    (int)P->Pb.size(), P->d_Br, P->d_BR, P->cfg.rot_cut};
+        with_angw<PR>(mix_width(max_om), (ng + 15) / 16, [&](auto kern) {
+          hipLaunchKernelGGL(kern, dim3(P->blocks_angw), dim3(kAngwThreads), P->lds_angw, P->stream,
+                             wa);
+        });
+      }
+    }
+    if (wave) {
+    } else if (P->ang_regs) {
       aa.Pfwd = P->d_PfF;
       // column tiles per wave: (j tiles) x (r tiles) over the four waves
       const int tpw = ((ng + 15) / 16 * P->nta + 3) / 4;
@@ -1784,16 +1851,17 @@ int tdwp_plan(const tdwp_config* cfg, tdwp_plan_t* out) {
   }
   if (P->fast) {
     // cached choice: 1000 * (angular blocks in XCD order) + 100 * (r pass fused) +
-    // 10 * kernel + tile (kernel 1: LDS mixing, 2: register mixing)
+    // 10 * kernel + tile (kernel 1: LDS mixing, 2: register mixing, 3: columns per wave)
     const int c = cached_tile(P);
     const int nt = c % 10, kern = (c / 10) % 10, fz = (c / 100) % 10, xo = (c / 1000) % 10;
     const int pl = c / 10000;
-    if ((nt == 1 || nt == 2 || nt == 4) && kern <= 2 && fz <= 1 && xo <= 1 && pl <= 1) {
+    if ((nt == 1 || nt == 2 || nt == 4) && kern <= 3 && fz <= 1 && xo <= 1 && pl <= 1) {
       P->fuse_r = fz == 1;
       P->ang_xcd = xo == 1;
       P->plane_r = pl == 1 && P->plane_ok;
+      P->ang_wave = kern == 3 && P->angw_ok;
       const int keep = P->ang_pref;
-      P->ang_pref = kern;
+      P->ang_pref = kern == 3 ? 2 : kern;
       if (set_ang_tiles(P, nt) != TDWP_OK) {
         P->ang_pref = keep;
         (void)set_ang_tiles(P, P->nta);
@@ -2299,22 +2367,26 @@ int tdwp_autotune(tdwp_plan_t p, int steps, char* report, size_t report_len) {
   std::string rep;
   const int keep_pref = p->ang_pref, keep_nt = p->nta;
   const bool keep_fuse = p->fuse_r, keep_xcd = p->ang_xcd, keep_plane = p->plane_r;
+  const bool keep_wave = p->ang_wave;
   int best_k = -1, best_nt = keep_nt, best_f = keep_fuse ? 1 : 0, best_x = keep_xcd ? 1 : 0;
   int best_p = keep_plane ? 1 : 0;
   double best_us = 1e300;
   // both radial terms in one plane pass, or the r pass beside the angular pass or
-  // after it x angular kernel (2: helicity mixing in registers, 1: through LDS) x
-  // tile width; the kernels of whole steps are timed
+  // after it x angular kernel (3: columns held per wave, 2: helicity mixing in
+  // registers, 1: through LDS) x tile width; the kernels of whole steps are timed
   for (int pl : {1, 0})
   for (int xo : {0, 1})
   for (int fz : {1, 0})
-  for (int kern : {2, 1})
+  for (int kern : {3, 2, 1})
     for (int nt : {4, 2, 1}) {
       if (pl && (!p->plane_ok || fz)) continue;   // the plane pass follows a plain angular pass
+      // the per-wave kernel has no tile width, no XCD order and no fused form
+      if (kern == 3 && (!p->angw_ok || fz || nt != 1 || xo)) continue;
       p->plane_r = pl == 1;
       p->ang_xcd = xo == 1;
       p->fuse_r = fz == 1;
-      p->ang_pref = kern;
+      p->ang_wave = kern == 3;
+      p->ang_pref = kern == 3 ? 2 : kern;
       if (set_ang_tiles(p, nt) != TDWP_OK) continue;
       reset_propagation(p);
       int st = sync_counters(p);
@@ -2334,6 +2406,7 @@ int tdwp_autotune(tdwp_plan_t p, int steps, char* report, size_t report_len) {
         p->fuse_r = keep_fuse;
         p->ang_xcd = keep_xcd;
         p->plane_r = keep_plane;
+        p->ang_wave = keep_wave;
         (void)set_ang_tiles(p, keep_nt);
         return st;
       }
@@ -2360,9 +2433,11 @@ int tdwp_autotune(tdwp_plan_t p, int steps, char* report, size_t report_len) {
     p->fuse_r = keep_fuse;
     p->ang_xcd = keep_xcd;
     p->plane_r = keep_plane;
+    p->ang_wave = keep_wave;
     TRY(set_ang_tiles(p, keep_nt));
   } else {
-    p->ang_pref = best_k;
+    p->ang_wave = best_k == 3;
+    p->ang_pref = best_k == 3 ? 2 : best_k;
     p->fuse_r = best_f == 1;
     p->ang_xcd = best_x == 1;
     p->plane_r = best_p == 1;
@@ -2374,7 +2449,8 @@ int tdwp_autotune(tdwp_plan_t p, int steps, char* report, size_t report_len) {
   if (report && report_len) {
     rep += ";chosen=p" + std::to_string(use_plane(p) ? 1 : 0) + "_x" +
            std::to_string(p->ang_xcd ? 1 : 0) + "_f" + std::to_string(p->fuse_r ? 1 : 0) +
-           "_k" + std::to_string(p->ang_regs ? 2 : 1) + "_nt" + std::to_string(p->nta);
+           "_k" + std::to_string(use_angw(p) ? 3 : (p->ang_regs ? 2 : 1)) + "_nt" +
+           std::to_string(p->nta);
     std::strncpy(report, rep.c_str(), report_len - 1);
     report[report_len - 1] = 0;
   }
@@ -2394,7 +2470,14 @@ int tdwp_set_option(tdwp_plan_t p, int option, long value) {
       drop_graphs(p);
       return TDWP_OK;
     case TDWP_OPT_ANG_KERNEL: {
-      if (!p->fast || value < 0 || value > 2) return TDWP_EINVAL;
+      if (!p->fast || value < 0 || value > 3) return TDWP_EINVAL;
+      if (value == 3) {
+        if (!p->angw_ok) return TDWP_EINVAL;
+        p->ang_wave = true;
+        drop_graphs(p);
+        return TDWP_OK;
+      }
+      p->ang_wave = false;
       const int keep = p->ang_pref;
       p->ang_pref = (int)value;
       int regs = 0;
@@ -2438,7 +2521,9 @@ int tdwp_get_stat(tdwp_plan_t p, int stat, long* value) {
   switch (stat) {
     case TDWP_STAT_GRAPH_STEPS: *value = p->graph_steps; return TDWP_OK;
     case TDWP_STAT_ANG_TILE: *value = p->fast ? p->nta : 0; return TDWP_OK;
-    case TDWP_STAT_ANG_KERNEL: *value = p->fast ? (p->ang_regs ? 2 : 1) : 0; return TDWP_OK;
+    case TDWP_STAT_ANG_KERNEL:
+      *value = p->fast ? (use_angw(p) ? 3 : (p->ang_regs ? 2 : 1)) : 0;
+      return TDWP_OK;
     case TDWP_STAT_MATRIX_CORE_PATH: *value = p->fast ? 1 : 0; return TDWP_OK;
     case TDWP_STAT_FUSE_R: *value = (p->fast && p->fuse_r) ? 1 : 0; return TDWP_OK;
     case TDWP_STAT_RING_LEN: *value = p->ring_len; return TDWP_OK;

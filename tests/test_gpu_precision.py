@@ -98,3 +98,75 @@ def test_general_path_odd_sizes():
     du = np.max(np.abs(plan.get_packet(0, 0, 0) - run["vectors"][K])) / np.max(np.abs(run["vectors"][K]))
     plan.close()
     assert du < 1e-10
+
+
+def _wave_cases():
+    """(name, spec) cases for the per-wave angular kernel: one helicity, Coriolis
+    coupling over two states, and 48 / 40 gamma nodes (three j tiles, capped
+    rotational energies at small r) with up to eight helicities."""
+    a = small_variant(1, n_R=24, n_r=20, n_gamma=10)
+    b = small_variant(3, n_R=22, n_r=18, n_gamma=14)
+    b["units"] = [dict(J=5, parity=1, omega_max=3, n_packets=1)]
+    b["packets"] = [dict(b["packets"][0], omega0=1, j0=1)]
+    c = small_variant(1, n_R=24, n_r=20, n_gamma=48)
+    c["units"] = [dict(J=4, parity=1, omega_max=4, n_packets=1)]
+    c["packets"] = [dict(c["packets"][0], omega0=0, j0=2)]
+    d = small_variant(1, n_R=20, n_r=16, n_gamma=40)
+    d["units"] = [dict(J=8, parity=1, omega_max=7, n_packets=1)]
+    d["packets"] = [dict(d["packets"][0], omega0=2, j0=3)]
+    return [("J=0 24x20x10", a), ("J=5 Omega 1..3, 2 states, 22x18x14", b),
+            ("J=4 Omega 0..4, 24x20x48", c), ("J=8 Omega 0..7, 20x16x40", d)]
+
+
+@pytest.mark.parametrize("precision", ["bf16x3", "fp16x3"])
+def test_wave_angular_kernel_per_precision(precision):
+    """Angular kernel 3 (columns held per wave) against the FP64 oracle and against
+    kernel 2 on the same plan: packets after 60 steps, r pass after the angular
+    pass (and the plane pass where the form allows it)."""
+    from paper_2412_10167_amd import problem
+    K = 60
+    for name, s in _wave_cases():
+        print(f"\n[case] angular kernel 3, {name}, {precision}", flush=True)
+        got = {}
+        for kern in (3, 2):
+            plan, _ = problem.build(s, precision=precision)
+            plan.set_option("fuse_r", 0)
+            plan.set_option("ang_kernel", kern)
+            assert plan.stat("ang_kernel") == kern
+            plan.propagate(K)
+            got[kern] = plan.get_packet(0, 0, 0)
+            plan.close()
+        op, run, _ = _oracle(s, K)
+        ref = run["vectors"][K]
+        scale = np.max(np.abs(ref))
+        du = np.max(np.abs(got[3] - ref)) / scale
+        d32 = np.max(np.abs(got[3] - got[2])) / scale
+        print(f"[result] {precision}: packet rel {du:.2e}; kernel 3 vs kernel 2 {d32:.2e}", flush=True)
+        assert du < 1e-4 and d32 < 1e-4
+
+
+def test_wave_angular_kernel_is_checked():
+    """Kernel 3 is refused where it does not apply: the FP64 form, more than eight
+    helicities; with the r pass fused into the angular launch kernel 2 runs."""
+    from paper_2412_10167_amd import problem
+    from paper_2412_10167_amd.tdwp import TdwpError
+    print("\n[case] angular kernel 3: refused for FP64 and for nine helicities", flush=True)
+    s = _wave_cases()[1][1]
+    plan, _ = problem.build(s)
+    with pytest.raises(TdwpError):
+        plan.set_option("ang_kernel", 3)
+    plan.close()
+    plan, _ = problem.build(s, precision="fp16x3")
+    plan.set_option("ang_kernel", 3)
+    plan.set_option("fuse_r", 1)
+    assert plan.stat("ang_kernel") == 2
+    plan.set_option("fuse_r", 0)
+    assert plan.stat("ang_kernel") == 3
+    plan.close()
+    e = small_variant(3, n_R=22, n_r=18, n_gamma=24)
+    e["units"] = [dict(J=10, parity=1, omega_max=8, n_packets=1)]
+    e["packets"] = [dict(e["packets"][0], omega0=1, j0=2)]
+    plan, _ = problem.build(e, precision="fp16x3")
+    with pytest.raises(TdwpError):
+        plan.set_option("ang_kernel", 3)
+    plan.close()
