@@ -34,7 +34,7 @@ namespace tdwp {
 constexpr int kPlaneThreads = 512;   // eight waves per plane
 constexpr int kPlaneMTW = 4;         // 16-row tiles (R) per wave work item
 constexpr int kPlaneNTW = 2;         // 16-column tiles (r) per wave work item
-constexpr int kPlaneRowsPerBatch = 4;   // plane rows whose loads a wave issues together
+constexpr int kPlaneRowsPerBatch = 8;   // plane rows whose loads a wave issues together
 constexpr int kPlaneMaxCols = 4;        // r values per lane and row: n_r <= 256
 constexpr int kPlaneEpiTiles = 2;       // row tiles whose epilogue operands are loaded together
 
@@ -97,7 +97,7 @@ void k_plane_epi(PlaneArgs A) {
   __shared__ double red[kPlaneThreads / 64];
   const int rows_x = plane_pad(nR, M::KS), cols_x = plane_pad(nr, M::KS);
   const int ldx = plane_ld(cols_x);
-  const int l = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int nw = kPlaneThreads / 64;
   const int nrow_ix = A.counters[1];
   double* __restrict__ normpart_row =
@@ -132,6 +132,11 @@ void k_plane_epi(PlaneArgs A) {
   PkDesc dsc{};
   for (int blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
     __syncthreads();   // the previous plane's tile has been read
+    // The lane index as an opaque value of this iteration: per-lane offsets are
+    // formed where they are used rather than hoisted out of the loop (which holds
+    // them in registers across it and spills them).
+    int l = lane;
+    asm volatile("" : "+v"(l));
     const int pk = find_packet(A.blk_start, A.n_pk, blk);
     local = blk - A.blk_start[pk];
     dsc = A.pks[pk];
@@ -158,7 +163,8 @@ void k_plane_epi(PlaneArgs A) {
 #pragma unroll
         for (int j = 0; j < kPairs; ++j) {
           const int c = 2 * l + 128 * j;
-          v[b][j] = (j < ppl) ? *reinterpret_cast<const v2d*>(uk + (size_t)mc * nr + (c < nr ? c : nr - 2))
+          v[b][j] = (j < ppl) ? __builtin_nontemporal_load(reinterpret_cast<const v2d*>(
+                                    uk + (size_t)mc * nr + (c < nr ? c : nr - 2)))
                               : v2d{0.0, 0.0};
         }
       }
@@ -288,9 +294,9 @@ void k_plane_epi(PlaneArgs A) {
                 const int mm = (mg * kPlaneMTW + a0 + a) * 16 + M::row(l, v);
                 const int mc = mm < nR ? mm : nR - 1;
                 const size_t idx = poff + (size_t)mc * nr + ic;
-                hv[a][v] = A.h_all[idx];
+                hv[a][v] = __builtin_nontemporal_load(A.h_all + idx);
                 vv[a][v] = A.V[(size_t)n * plane + (size_t)mc * nr + ic];
-                pv[a][v] = FIRST ? 0.0 : A.uprev_all[idx];
+                pv[a][v] = FIRST ? 0.0 : __builtin_nontemporal_load(A.uprev_all + idx);
               }
 #pragma unroll
             for (int a = 0; a < GA; ++a)
@@ -305,7 +311,7 @@ void k_plane_epi(PlaneArgs A) {
                 const double wv = (sacc - A.E0 * ukv) * A.inv_dE;
                 const double dmp = Ds[nr + mm] * dr_i;
                 const double un = FIRST ? dmp * wv : dmp * (2.0 * wv - dmp * pv[a][v]);
-                A.uprev_all[idx] = un;
+                __builtin_nontemporal_store(un, A.uprev_all + idx);
                 nsum += un * un;
               }
           }
@@ -318,7 +324,7 @@ void k_plane_epi(PlaneArgs A) {
     }
     // ---- norm partial of this plane ------------------------------------------------
     for (int off = 32; off > 0; off >>= 1) nsum += __shfl_down(nsum, off, 64);
-    if (l == 0) red[w] = nsum;
+    if (lane == 0) red[w] = nsum;
     nsum = 0.0;
     __syncthreads();
     if (threadIdx.x == 0 && normpart_row) {
