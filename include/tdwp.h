@@ -448,7 +448,11 @@ enum tdwp_stat {
   TDWP_STAT_FUSE_R = 4,             /* 1 when the angular and r passes share a launch */
   TDWP_STAT_RING_LEN = 5,           /* steps of slices buffered between two energy
                                        accumulations (Eq. wvf-chebyshev, blocked)     */
-  TDWP_STAT_PLANE_R = 6             /* 1 when steps run the plane pass               */
+  TDWP_STAT_PLANE_R = 6,            /* 1 when steps run the plane pass               */
+  TDWP_STAT_POTENTIAL_BYTES = 7     /* device bytes held for the potential: the table
+                                       (FP64, plus its FP32 copy in the mixed forms), or
+                                       the trained network's parameters once the steps
+                                       evaluate it (the table is then released)        */
 };
 
 /* Sets a plan option; EINVAL for an unknown option or value. */

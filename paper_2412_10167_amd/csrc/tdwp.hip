@@ -68,6 +68,25 @@ int dev_alloc(Plan* P, void** ptr, size_t bytes) {
   return TDWP_OK;
 }
 
+// Releases one allocation of the plan before the plan itself is destroyed.
+void dev_release(Plan* P, void** ptr) {
+  if (!*ptr) return;
+  for (auto& a : P->allocations)
+    if (a == *ptr) a = nullptr;
+  (void)hipFree(*ptr);
+  *ptr = nullptr;
+}
+
+// The potential table (FP64, and its FP32 copy in the mixed forms of the
+// matrix-core path), allocated while the plan holds one.
+int ensure_table(Plan* P) {
+  const size_t n = (size_t)P->npair * P->ng * P->nR * P->nr;
+  if (!P->d_V) TRY(dev_alloc(P, (void**)&P->d_V, n * sizeof(double)));
+  if (!P->d_Vf && P->fast && P->cfg.precision != TDWP_FP64)
+    TRY(dev_alloc(P, (void**)&P->d_Vf, n * sizeof(float)));
+  return TDWP_OK;
+}
+
 template <class T>
 int alloc_copy(Plan* P, T** dptr, const std::vector<T>& h) {
   TRY(dev_alloc(P, (void**)dptr, h.size() * sizeof(T)));
@@ -677,9 +696,7 @@ int layout_and_allocate(Plan* P) {
   TRY(dev_alloc(P, (void**)&P->d_u[1], P->n_total * sizeof(double)));
   TRY(dev_alloc(P, (void**)&P->d_h, P->n_total * sizeof(double)));
   if (P->fast) TRY(dev_alloc(P, (void**)&P->d_h2, P->n_total * sizeof(double)));
-  TRY(dev_alloc(P, (void**)&P->d_V, (size_t)P->npair * ng * nR * nr * sizeof(double)));
-  if (P->fast && P->cfg.precision != TDWP_FP64)
-    TRY(dev_alloc(P, (void**)&P->d_Vf, (size_t)P->npair * ng * nR * nr * sizeof(float)));
+  TRY(ensure_table(P));
   TRY(alloc_copy(P, &P->d_Tr, P->Tr));
   TRY(alloc_copy(P, &P->d_TR, P->TR));
   TRY(alloc_copy(P, &P->d_P, P->Ptab));
@@ -1924,6 +1941,7 @@ int tdwp_set_potential(tdwp_plan_t p, int mode, const double* v, size_t n_values
   if (mode != TDWP_POT_TABLE) return TDWP_EINVAL;
   const size_t plane = (size_t)p->ng * p->nR * p->nr;
   if (n_values != (size_t)p->npair * plane) return TDWP_EINVAL;
+  TRY(ensure_table(p));
   HIP_TRY(hipMemcpyAsync(p->d_V, v, n_values * sizeof(double), hipMemcpyHostToDevice, p->stream));
   if (p->d_Vf) {
     hipLaunchKernelGGL(k_to_f32, dim3(1024), dim3(256), 0, p->stream, p->d_V, p->d_Vf, n_values);
@@ -2528,6 +2546,16 @@ int tdwp_get_stat(tdwp_plan_t p, int stat, long* value) {
     case TDWP_STAT_FUSE_R: *value = (p->fast && p->fuse_r) ? 1 : 0; return TDWP_OK;
     case TDWP_STAT_RING_LEN: *value = p->ring_len; return TDWP_OK;
     case TDWP_STAT_PLANE_R: *value = use_plane(p) ? 1 : 0; return TDWP_OK;
+    case TDWP_STAT_POTENTIAL_BYTES: {
+      const size_t n = (size_t)p->npair * p->ng * p->nR * p->nr;
+      size_t b = (p->d_V ? n * sizeof(double) : 0) + (p->d_Vf ? n * sizeof(float) : 0);
+      if (p->pot_mode == TDWP_POT_MLP)
+        b += (size_t)p->mlp_nparams * sizeof(float) +
+             ((size_t)kMlpH * 32 + 2 * kMlpH * kMlpH + 16 * kMlpH) * sizeof(__bf16) +
+             (size_t)(3 * kMlpH + 16) * sizeof(float);
+      *value = (long)b;
+      return TDWP_OK;
+    }
     default: return TDWP_EINVAL;
   }
 }
@@ -2550,6 +2578,7 @@ int tdwp_set_potential_mlp(tdwp_plan_t p, const double* v, size_t n_values,
     if (o->sample_idx[i] < 0 || (size_t)o->sample_idx[i] >= plane) return TDWP_EINVAL;
     if (o->order[i] < 0 || o->order[i] >= o->n_samples) return TDWP_EINVAL;
   }
+  TRY(ensure_table(p));   // the training targets
   HIP_TRY(hipMemcpyAsync(p->d_V, v, n_values * sizeof(double), hipMemcpyHostToDevice, p->stream));
   const int npar = mlp_param_count(p->npair);
   p->mlp_nparams = npar;
@@ -2645,6 +2674,10 @@ int tdwp_set_potential_mlp(tdwp_plan_t p, const double* v, size_t n_values,
     report[2] = mx;
   }
   drop_graphs(p);
+  // the steps evaluate the network: the table is no longer held
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  dev_release(p, (void**)&p->d_V);
+  dev_release(p, (void**)&p->d_Vf);
   p->pot_mode = TDWP_POT_MLP;
   p->have_potential = true;
   reset_propagation(p);

@@ -27,7 +27,7 @@ EXPORTED_SYMBOLS = (
 OPTIONS = {"graphs": 0, "ang_tile": 1, "radial_grid": 2, "ang_kernel": 3, "fuse_r": 4,
            "ang_xcd": 5, "plane_r": 6}
 STATS = {"graph_steps": 0, "ang_tile": 1, "matrix_core_path": 2, "ang_kernel": 3, "fuse_r": 4,
-         "ring_len": 5, "plane_r": 6}
+         "ring_len": 5, "plane_r": 6, "potential_bytes": 7}
 
 
 class TdwpError(RuntimeError):

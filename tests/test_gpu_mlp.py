@@ -122,3 +122,44 @@ def test_mlp_training_and_on_the_fly_step():
         p.close()
     assert rel < 1e-12
     assert cm.shape == (K + 1,) and relc < 1e-12
+
+
+def test_mlp_gain_footprint_and_probabilities():
+    """What the learned potential gains: once trained, the plan holds the network
+    (parameters and packed weights) instead of the table, and its steps read no
+    table; the cost is the fit's error, reported as the largest difference of the
+    state-to-state probabilities from the tabulated run (config 5 on a
+    128 x 128 x 48 grid)."""
+    from paper_2412_10167_amd import problem
+    print("\n[case] MLP plan footprint vs table plan, and |dP(E)| after 400 steps "
+          "(128x128x48, J=4, 3 states)", flush=True)
+    spec = small_variant(5, n_R=128, n_r=128, n_gamma=48)
+    spec["packets"][0]["k_min_elastic"] = 60
+    plan_t, _ = problem.build(spec)
+    vtab = problem.potential_table(plan_t, spec)
+    idx = sample_indices(vtab[0].size, n_samples=16384)
+    mlp = dict(sample_idx=idx, init_params=init_params(6), order=batch_order(idx.size), batch=512,
+               epochs=200, lr=2e-3)
+    plan_m, info = problem.build(spec, mlp=mlp)   # its own spectral bounds (from the network)
+    table_bytes = plan_t.stat("potential_bytes")
+    net_bytes = plan_m.stat("potential_bytes")
+    npts = vtab.size
+    print(f"[result] potential held on the device: table {table_bytes} bytes "
+          f"({npts} FP64 values), network {net_bytes} bytes; the network's steps read "
+          f"{8 * npts} fewer table bytes per step", flush=True)
+    assert table_bytes == 8 * npts
+    assert net_bytes * 100 < table_bytes
+    K = 400
+    plan_t.propagate(K)
+    plan_m.propagate(K)
+    chans = problem.channels(plan_t, spec, 0, 6, 1)
+    pi_t, pr_t = plan_t.state_to_state(0, 0, chans)
+    pi_m, pr_m = plan_m.state_to_state(0, 0, chans)
+    dp = max(float(np.max(np.abs(pi_m - pi_t))), float(np.max(np.abs(pr_m - pr_t))))
+    rep = info["mlp_report"]
+    print(f"[result] fit rms {rep[1] * 27211.386:.1f} meV, max {rep[2] * 27211.386:.1f} meV; "
+          f"max |dP(E)| network vs table {dp:.3e} (largest P {max(np.max(pi_t), np.max(pr_t)):.3f})",
+          flush=True)
+    assert np.isfinite(dp)
+    plan_t.close()
+    plan_m.close()
