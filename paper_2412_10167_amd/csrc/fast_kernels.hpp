@@ -1132,6 +1132,7 @@ constexpr int kAccThreads = 512;                  // eight waves
 constexpr int kAccWaves = kAccThreads / 64;
 constexpr int kAccMaxMT = 4;                      // M-tiles per wave (2 n_E <= 16 * 4 * 8)
 constexpr int kAccCols = 32;                      // slice values per workgroup
+constexpr int kAccChunks = 32;                    // chunks of eight steps in a full ring
 struct AccDesc {
   unsigned long acc_off;    // accumulators of the packet [2 n_E][n_slice]
   unsigned long slice_off;  // the packet's slice values in a ring row
@@ -1184,61 +1185,105 @@ __global__ __launch_bounds__(kAccThreads) __attribute__((amdgpu_waves_per_eu(4))
     }
   }
   __syncthreads();
-  M::acc_t c[kAccMaxMT][2];
+  // The wave's M-tiles are w, w + 8, ...: their count NT is the same for the
+  // whole wave, and each count has a body of its own, so no tile loop branches
+  // (branches would break the straight-line code the waits are counted in).
+  const int ntile = (MT - w + kAccWaves - 1) / kAccWaves;
+  auto body = [&](auto ntag) __attribute__((always_inline)) {
+    constexpr int NT = decltype(ntag)::value;
+    M::acc_t c[NT][2];
 #pragma unroll
-  for (int a = 0; a < kAccMaxMT; ++a) c[a][0] = c[a][1] = M::zero();
-  // coefficient fragments of one chunk: A[tile] = (row r, ring rows kb, kb + 1)
-  v2d A0[kAccMaxMT], A1[kAccMaxMT];
-  auto load = [&](v2d (&A)[kAccMaxMT], int ch) {
-    const int kb = 8 * ch + kq;   // even; kb + 1 < 8 * nch <= ldc
+    for (int a = 0; a < NT; ++a) c[a][0] = c[a][1] = M::zero();
+    // coefficient fragments of one chunk: A[tile] = (row r, ring rows kb, kb + 1)
+    v2d A0[NT], A1[NT];
+    auto load = [&](v2d (&A)[NT], int ch) __attribute__((always_inline)) {
+      const int kb = 8 * ch + kq;   // even; kb + 1 < 8 * nch <= ldc
 #pragma unroll
-    for (int a = 0; a < kAccMaxMT; ++a) {
+      for (int a = 0; a < NT; ++a) {
+        // rows past the last are clamped (their products are not stored); columns
+        // past count are zero in the coefficient table, so fragments load whole
+        const int r = min((w + kAccWaves * a) * 16 + (l & 15), rows - 1);
+        A[a] = *reinterpret_cast<const v2d*>(coef + (size_t)r * ldc + kb);
+      }
+    };
+    auto compute = [&](const v2d (&A)[NT], int ch) __attribute__((always_inline)) {
+#pragma unroll
+      for (int cc = 0; cc < 2; ++cc) {
+        const int k = 8 * ch + kq + cc;
+        const double b0 = slab[k * kAccCols + (l & 15)];
+        const double b1 = slab[k * kAccCols + 16 + (l & 15)];
+#pragma unroll
+        for (int a = 0; a < NT; ++a) {
+          M::mma(c[a][0], A[a][cc], b0);
+          M::mma(c[a][1], A[a][cc], b1);
+        }
+      }
+    };
+    if (nch == kAccChunks) {
+      // a full ring: straight-line code, each wait covering only the chunk about
+      // to be used while the next chunk's loads stay in flight (the scheduling
+      // barriers keep each prefetch ahead of the products it overlaps)
+      load(A0, 0);
+#pragma unroll
+      for (int ch = 0; ch < kAccChunks; ch += 2) {
+        load(A1, ch + 1);
+        __builtin_amdgcn_sched_barrier(0);
+        compute(A0, ch);
+        if (ch + 2 < kAccChunks) load(A0, ch + 2);
+        __builtin_amdgcn_sched_barrier(0);
+        compute(A1, ch + 1);
+      }
+    } else {
+      if (nch > 0) load(A0, 0);
+      for (int ch = 0; ch < nch; ch += 2) {
+        if (ch + 1 < nch) load(A1, ch + 1);
+        compute(A0, ch);
+        if (ch + 2 < nch) load(A0, ch + 2);
+        if (ch + 1 < nch) compute(A1, ch + 1);
+      }
+    }
+    // accumulators of one M-tile: all eight loads in flight, then the stores
+    // (without per-lane conditions when the tile lies inside the slice and rows)
+    const bool cols_full = s0 + kAccCols <= n_slice;
+#pragma unroll
+    for (int a = 0; a < NT; ++a) {
       const int mt = w + kAccWaves * a;
-      if (mt >= MT) break;
-      int r = mt * 16 + (l & 15);
-      const bool rok = r < rows;
-      r = rok ? r : rows - 1;
-      const v2d x = *reinterpret_cast<const v2d*>(coef + (size_t)r * ldc + kb);
-      A[a] = v2d{(rok && kb < count) ? x[0] : 0.0, (rok && kb + 1 < count) ? x[1] : 0.0};
+      if (cols_full && (mt + 1) * 16 <= rows) {
+        double* __restrict__ base = acc + (size_t)mt * 16 * n_slice + s0 + (l & 15);
+        double old[2][4];
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) old[nt][v] = base[(size_t)M::row(l, v) * n_slice + nt * 16];
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            base[(size_t)M::row(l, v) * n_slice + nt * 16] = old[nt][v] + c[a][nt][v];
+        continue;
+      }
+      double old[2][4];
+#pragma unroll
+      for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int s = s0 + nt * 16 + (l & 15), r = mt * 16 + M::row(l, v);
+          old[nt][v] = (s < n_slice && r < rows) ? acc[(size_t)r * n_slice + s] : 0.0;
+        }
+#pragma unroll
+      for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int s = s0 + nt * 16 + (l & 15), r = mt * 16 + M::row(l, v);
+          if (s < n_slice && r < rows) acc[(size_t)r * n_slice + s] = old[nt][v] + c[a][nt][v];
+        }
     }
   };
-  auto compute = [&](const v2d (&A)[kAccMaxMT], int ch) {
-#pragma unroll
-    for (int cc = 0; cc < 2; ++cc) {
-      const int k = 8 * ch + kq + cc;
-      const double b0 = slab[k * kAccCols + (l & 15)];
-      const double b1 = slab[k * kAccCols + 16 + (l & 15)];
-#pragma unroll
-      for (int a = 0; a < kAccMaxMT; ++a) {
-        const int mt = w + kAccWaves * a;
-        if (mt >= MT) break;
-        M::mma(c[a][0], A[a][cc], b0);
-        M::mma(c[a][1], A[a][cc], b1);
-      }
-    }
-  };
-  if (nch > 0) load(A0, 0);
-  for (int ch = 0; ch < nch; ch += 2) {
-    if (ch + 1 < nch) load(A1, ch + 1);
-    compute(A0, ch);
-    if (ch + 2 < nch) load(A0, ch + 2);
-    if (ch + 1 < nch) compute(A1, ch + 1);
-  }
-#pragma unroll
-  for (int a = 0; a < kAccMaxMT; ++a) {
-    const int mt = w + kAccWaves * a;
-    if (mt >= MT) break;
-#pragma unroll
-    for (int nt = 0; nt < 2; ++nt) {
-      const int s = s0 + nt * 16 + (l & 15);
-      if (s >= n_slice) continue;
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int r = mt * 16 + M::row(l, v);
-        if (r < rows) acc[(size_t)r * n_slice + s] += c[a][nt][v];
-      }
-    }
-  }
+  static_assert(kAccMaxMT == 4, "bodies for one to four M-tiles per wave");
+  if (ntile >= 4) body(std::integral_constant<int, 4>{});
+  else if (ntile == 3) body(std::integral_constant<int, 3>{});
+  else if (ntile == 2) body(std::integral_constant<int, 2>{});
+  else if (ntile == 1) body(std::integral_constant<int, 1>{});
 }
 
 }  // namespace tdwp

@@ -206,11 +206,19 @@ __global__ void k_slices(const double* __restrict__ u_all, const long* __restric
 __global__ void k_coef(double* __restrict__ coef_all, int ldc, int nE, double ecol_min,
                        double ecol_step, const double* __restrict__ E_v0j0, int n_pk, double E0,
                        double dE, long k0, int count) {
+  // one thread per (packet, energy, buffered step) of the ldc columns: the columns
+  // past count are zeroed, so that the matrix-core accumulation may read whole
+  // fragments without masking them
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= nE * count * n_pk) return;
-  const int p = q / (nE * count);
-  const int e = (q / count) % nE, b = q % count;
+  if (q >= nE * ldc * n_pk) return;
+  const int p = q / (nE * ldc);
+  const int e = (q / ldc) % nE, b = q % ldc;
   double* coef = coef_all + (size_t)p * 2 * nE * ldc;
+  if (b >= count) {
+    coef[(size_t)e * ldc + b] = 0.0;
+    coef[((size_t)nE + e) * ldc + b] = 0.0;
+    return;
+  }
   const double Es = (ecol_min + e * ecol_step + E_v0j0[p] - E0) / dE;
   const double th = acos(Es);
   const long kk = k0 + b;

@@ -651,6 +651,7 @@ int layout_and_allocate(Plan* P) {
     TRY(build_product_tables(P));
   }
   P->fast_accum = P->cfg.n_energy <= 16 * kAccMaxMT * kAccWaves / 2;
+  static_assert(kAccChunks * 8 == kRingFast, "a full ring is kAccChunks chunks of eight steps");
   P->ring_len = P->fast_accum ? kRingFast : kRing;
   const int rtf = 16 * P->ntr;
   // packets
@@ -990,7 +991,7 @@ int flush_ring(Plan* P) {
   const int nE = c.n_energy;
   const double step = (c.ecol_max - c.ecol_min) / (nE - 1);
   const int np = (int)P->packets.size();
-  const int nq = nE * P->ring_count * np;
+  const int nq = nE * P->ring_len * np;
   hipLaunchKernelGGL(k_coef, dim3((nq + 255) / 256), dim3(256), 0, P->stream, P->d_coef,
                      P->ring_len, nE, c.ecol_min, step, P->d_E, np, P->E0, P->dE, P->ring_k0,
                      P->ring_count);
