@@ -92,7 +92,9 @@ def kernel_model(spec, name, precision, fused=False, photo=False):
 
 
 KERNEL_SOURCES = ("paper_2412_10167_amd/csrc/fast_kernels.hpp", "paper_2412_10167_amd/csrc/mfma.hpp",
-                  "paper_2412_10167_amd/csrc/tdwp.hip")
+                  "paper_2412_10167_amd/csrc/plane_kernels.hpp",
+                  "paper_2412_10167_amd/csrc/angw_kernels.hpp",
+                  "paper_2412_10167_amd/csrc/step_kernels.hpp", "paper_2412_10167_amd/csrc/tdwp.hip")
 
 
 def kernel_source_digest():
