@@ -69,9 +69,9 @@ def kernel_model(spec, name, precision, fused=False, photo=False):
             byts += values * 8
     elif name == "radial_rR_epilogue":
         # both radial terms over whole planes (one state): T_R and T_r full-size,
-        # nR + nr flops per value; bytes: u_k, h, u_{k-1}, V (FP32, one read per
-        # helicity block), u_{k+1}
-        flops, byts = values * (nR + nr), values * (8 + hb + 8 + hb + 8)
+        # nR + nr flops per value; bytes: u_k, h, u_{k-1}, u_{k+1}, and V (FP32)
+        # once per grid point
+        flops, byts = values * (nR + nr), values * (8 + hb + 8 + 8) + hb * nR * nr * ng
     elif name == "radial_r" and not fused:
         # T_r split: nr flops per value; bytes: u_k, h read and written
         flops, byts = values * nr, values * (8 + 2 * hb)

@@ -163,8 +163,10 @@ void k_plane_epi(PlaneArgs A) {
 #pragma unroll
         for (int j = 0; j < kPairs; ++j) {
           const int c = 2 * l + 128 * j;
+          // byte offset within the plane (32-bit: see the epilogue)
+          const unsigned ob = ((unsigned)mc * (unsigned)nr + (unsigned)(c < nr ? c : nr - 2)) * 8u;
           v[b][j] = (j < ppl) ? __builtin_nontemporal_load(reinterpret_cast<const v2d*>(
-                                    uk + (size_t)mc * nr + (c < nr ? c : nr - 2)))
+                                    reinterpret_cast<const char*>(uk) + ob))
                               : v2d{0.0, 0.0};
         }
       }
@@ -273,6 +275,12 @@ void k_plane_epi(PlaneArgs A) {
       // epilogue of this work item's outputs: the operands of a group of tiles are
       // loaded together (clamped to the plane), then the outputs are formed and
       // stored where they lie inside it
+      // uniform bases of this plane's arrays and 32-bit per-lane byte offsets (a
+      // plane fits in LDS as FP32, so 8 n_R n_r is far below 2^32): the loads and
+      // stores take the scalar-base form, and no 64-bit lane addresses are held
+      const char* __restrict__ hp = reinterpret_cast<const char*>(A.h_all + poff);
+      const char* __restrict__ vp = reinterpret_cast<const char*>(A.V + (size_t)n * plane);
+      char* __restrict__ pp = reinterpret_cast<char*>(A.uprev_all + poff);
       auto epilogue = [&](auto first_tag) {
         constexpr bool FIRST = decltype(first_tag)::value;
         constexpr int GA = kPlaneEpiTiles;   // row tiles per load group
@@ -293,10 +301,11 @@ void k_plane_epi(PlaneArgs A) {
               for (int v = 0; v < 4; ++v) {
                 const int mm = (mg * kPlaneMTW + a0 + a) * 16 + M::row(l, v);
                 const int mc = mm < nR ? mm : nR - 1;
-                const size_t idx = poff + (size_t)mc * nr + ic;
-                hv[a][v] = __builtin_nontemporal_load(A.h_all + idx);
-                vv[a][v] = A.V[(size_t)n * plane + (size_t)mc * nr + ic];
-                pv[a][v] = FIRST ? 0.0 : __builtin_nontemporal_load(A.uprev_all + idx);
+                const unsigned o = (unsigned)mc * (unsigned)nr + (unsigned)ic;
+                hv[a][v] = __builtin_nontemporal_load(reinterpret_cast<const float*>(hp + 4u * o));
+                vv[a][v] = *reinterpret_cast<const float*>(vp + 4u * o);
+                pv[a][v] = FIRST ? 0.0
+                                 : __builtin_nontemporal_load(reinterpret_cast<const double*>(pp + 8u * o));
               }
 #pragma unroll
             for (int a = 0; a < GA; ++a)
@@ -304,14 +313,14 @@ void k_plane_epi(PlaneArgs A) {
               for (int v = 0; v < 4; ++v) {
                 const int mm = (mg * kPlaneMTW + a0 + a) * 16 + M::row(l, v);
                 if (!col_ok || mm >= nR) continue;
-                const size_t idx = poff + (size_t)mm * nr + i;
+                const unsigned o = (unsigned)mm * (unsigned)nr + (unsigned)i;
                 const double ukv = (double)X[mm * ldx + i];
                 const double sacc = (double)acc[a0 + a][b][v] * M::kUnscale + (double)hv[a][v] +
                                     (double)vv[a][v] * ukv;
                 const double wv = (sacc - A.E0 * ukv) * A.inv_dE;
                 const double dmp = Ds[nr + mm] * dr_i;
                 const double un = FIRST ? dmp * wv : dmp * (2.0 * wv - dmp * pv[a][v]);
-                __builtin_nontemporal_store(un, A.uprev_all + idx);
+                __builtin_nontemporal_store(un, reinterpret_cast<double*>(pp + 8u * o));
                 nsum += un * un;
               }
           }
