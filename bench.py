@@ -166,8 +166,7 @@ def mlp_bench(args, torch, problem, config):
     against the tabulated step of the same plan shape.  Prints one JSON line."""
     import numpy as np
     from workloads.mlp_inputs import batch_order, init_params, sample_indices
-    wl = args.workload if args.workload != 2 else 5
-    spec = config(wl)
+    spec = config(args.workload)
     torch.cuda.set_device(0)
     torch.cuda.set_stream(torch.cuda.Stream())
     stream = torch.cuda.current_stream()
@@ -405,9 +404,9 @@ def main():
                          "flushes, so the energy accumulation is timed)")
     ap.add_argument("--autotune", type=int, default=5,
                     help="steps per tile variant timed by the library's autotuner (0: off)")
-    ap.add_argument("--workload", type=int, default=4,
+    ap.add_argument("--workload", type=int, default=None,
                     help="workload number 1..5 (default 4: 21 partial waves x 3 packets, "
-                         "128x128x48)")
+                         "128x128x48; 2 with --photo, 5 with --mlp)")
     ap.add_argument("--no-side-workload", action="store_true",
                     help="skip timing workload 2 (J=0 256x192x80) beside the batched workload")
     ap.add_argument("--radial-grid", type=int, default=0,
@@ -440,6 +439,8 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="also run one device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
+    if args.workload is None:
+        args.workload = 2 if args.photo else 5 if args.mlp else 4
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
               "(independent partial waves would shard across GPUs with no per-step traffic)",
